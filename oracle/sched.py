@@ -1,0 +1,193 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+Greedy co-scheduling (Kernelet, Section 4.2 "Scheduling", Algorithm 1 and
+procedure FindCoSchedule) and the FIFO baseline, on a virtual clock.
+
+FindCoSchedule(R):
+  1. candidate space: pairs of pending kernels (one representative per
+     kernel type: the earliest submitted pending instance);
+  2. prune by PUR / MUR (prune.py);
+  3. evaluate every surviving pair with the Markov model over its feasible
+     slice ratios (markov.best_ratio);
+  4. return the pair and ratio with the largest profit.
+Algorithm 1: while kernels are pending, take the co-schedule and keep
+issuing it while both kernels still have thread blocks; then decide again
+on the pending set, which now holds the residual of the kernel that did not
+finish and every kernel that arrived meanwhile.
+
+Readings (listed in the design doc): ties between pairs go to the pair whose
+earlier kernel was submitted first, then whose later kernel was; with a
+single pending kernel type, or when the best predicted profit is not above
+`cp_min`, the earliest pending kernel runs alone at its own full occupancy
+(a co-schedule of one slice, which the problem definition allows).
+
+Virtual clock: one time unit is one issue slot of one SIMD.  A kernel whose
+waves reach IPC c on each SIMD finishes n_cu * c / (waves_per_wg * I)
+workgroups per unit (I = instructions per wave).  Progress is fluid (slice
+boundaries are not modelled).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+from . import markov, prune
+
+
+@dataclass(frozen=True)
+class TypeInfo:
+    prof: markov.KProfile
+    pur: float
+    mur: float
+
+
+@dataclass
+class Job:
+    id: int
+    type: int
+    wgs: int
+    arrival: float = 0.0
+    rem: float = field(default=None)
+
+    def __post_init__(self):
+        if self.rem is None:
+            self.rem = float(self.wgs)
+
+
+@dataclass(frozen=True)
+class Config:
+    alpha_p: float = 0.4
+    alpha_m: float = 0.1
+    use_prune: bool = True
+    beta: float = 0.0
+    mode: str = "balanced"
+    cp_min: float = 0.0
+    wmax: int = 8
+    vgpr_file: int = 512
+    lds_cu: int = 160 * 1024
+    n_cu: int = 256
+
+
+@dataclass(frozen=True)
+class Decision:
+    j1: int
+    j2: int          # -1: solo
+    b1: int
+    b2: int
+    value: float
+    cipc1: float
+    cipc2: float
+
+
+class Model:
+    """Caches solo IPCs and per-type-pair ratio searches."""
+
+    def __init__(self, types: dict, cfg: Config):
+        self.types, self.cfg = types, cfg
+        self._pair, self._solo = {}, {}
+
+    def solo_ipc(self, t):
+        if t not in self._solo:
+            p = self.types[t].prof
+            self._solo[t] = markov.ipc_homogeneous(
+                p.kernel, p.max_wg_per_cu * p.wave_per_wg, self.cfg.beta)
+        return self._solo[t]
+
+    def pair(self, t1, t2):
+        key = (t1, t2)
+        if key not in self._pair:
+            c = self.cfg
+            self._pair[key] = markov.best_ratio(
+                self.types[t1].prof, self.types[t2].prof, c.beta, c.mode,
+                wmax=c.wmax, vgpr_file=c.vgpr_file, lds_cu=c.lds_cu)
+        return self._pair[key]
+
+    def rate(self, t, ipc):
+        p = self.types[t].prof
+        return self.cfg.n_cu * ipc / (p.wave_per_wg * p.instr_per_wave)
+
+
+def find_coschedule(pending, model: Model) -> Decision:
+    cfg = model.cfg
+    reps = {}
+    for j in sorted(pending, key=lambda j: j.id):
+        reps.setdefault(j.type, j)
+    order = sorted(reps.values(), key=lambda j: j.id)
+    first = order[0]
+    solo = Decision(first.id, -1, model.types[first.type].prof.max_wg_per_cu,
+                    0, 0.0, model.solo_ipc(first.type), 0.0)
+    if len(order) < 2:
+        return solo
+    pairs = [(a, b) for ia, a in enumerate(order) for b in order[ia + 1:]]
+    if cfg.use_prune:
+        chars = [(model.types[j.type].pur, model.types[j.type].mur) for j in order]
+        pos = {j.id: i for i, j in enumerate(order)}
+        keep = set(prune.surviving_pairs(chars, cfg.alpha_p, cfg.alpha_m))
+        pairs = [(a, b) for a, b in pairs if (pos[a.id], pos[b.id]) in keep]
+    best = None
+    for a, b in pairs:
+        r = model.pair(a.type, b.type)
+        if r is None:
+            continue
+        b1, b2, val, c1, c2 = r
+        if best is None or val > best.value:
+            best = Decision(a.id, b.id, b1, b2, val, c1, c2)
+    if best is None or best.value <= cfg.cp_min:
+        return solo
+    return best
+
+
+EPS_WG = 1e-6   # residual workgroups below this count as finished
+
+
+def simulate_kernelet(jobs, types, cfg: Config):
+    """Algorithm 1 on the virtual clock.  Returns (decision log, makespan,
+    completion time per job id)."""
+    model = Model(types, cfg)
+    jobs = [Job(j.id, j.type, j.wgs, j.arrival) for j in jobs]
+    byid = {j.id: j for j in jobs}
+    t, log, done = 0.0, [], {}
+    while len(done) < len(jobs):
+        pend = [j for j in jobs if j.arrival <= t and j.id not in done]
+        if not pend:
+            t = min(j.arrival for j in jobs if j.id not in done)
+            continue
+        d = find_coschedule(pend, model)
+        log.append(d)
+        j1 = byid[d.j1]
+        if d.j2 < 0:
+            dt = j1.rem / model.rate(j1.type, d.cipc1)
+            t += dt
+            j1.rem = 0.0
+            done[j1.id] = t
+            continue
+        j2 = byid[d.j2]
+        r1, r2 = model.rate(j1.type, d.cipc1), model.rate(j2.type, d.cipc2)
+        t1, t2 = j1.rem / r1, j2.rem / r2
+        dt = min(t1, t2)
+        t += dt
+        if t1 <= t2:
+            j2.rem -= dt * r2
+            j1.rem = 0.0
+            done[j1.id] = t
+            if j2.rem <= EPS_WG:
+                j2.rem = 0.0
+                done[j2.id] = t
+        else:
+            j1.rem -= dt * r1
+            j2.rem = 0.0
+            done[j2.id] = t
+            if j1.rem <= EPS_WG:
+                j1.rem = 0.0
+                done[j1.id] = t
+    return log, t, done
+
+
+def simulate_fifo(jobs, types, cfg: Config):
+    """Every kernel alone, unsliced, in submission order."""
+    model = Model(types, cfg)
+    t, done = 0.0, {}
+    for j in sorted(jobs, key=lambda j: j.id):
+        t = max(t, j.arrival)
+        t += j.wgs / model.rate(j.type, model.solo_ipc(j.type))
+        done[j.id] = t
+    return t, done

@@ -1,0 +1,309 @@
+"""Mix throughput of the sliced co-execution engine on one MI355X.
+
+One step = one pass of the hot path over a batch of kernel instances: the
+eight-kernel mix (SGEMM 4096^3 on FP32 matrix cores, CSR SpMV 2^20 rows ~16
+nnz/row, 5-point stencil 8192^2 x 10 sweeps, Black-Scholes 2^25 options,
+256-bin histogram of 2^28 bytes, lower_bound of 2^26 queries in 2^26 sorted
+keys, degree-256 polynomial of 2^20 values, random gather of 2^22 from a
+2^24 table), `--instances` of each type, submitted in a seeded interleaved
+order, registered, profiled, scheduled (Markov-model greedy pairs over
+sliced, co-running kernels) and executed to completion.  The same instances
+also run under FIFO (one in-order stream, unsliced) in every step.
+
+Prints one JSON line (see the keys below).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mix throughput (kernels/s) vs FIFO on 1 MI355X; roofline frac; p99 turnaround"
+PEAK_HBM = 8.0e12            # B/s
+PEAK_MFMA_F32 = 157.3e12     # dense FP32 matrix FLOP/s
+PEAK_VALU_F32 = 78.6e12      # unpacked FP32 FMA: 256 CU * 4 SIMD * 16 lanes * 2 * 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--instances", type=int, default=8, help="instances per kernel type")
+    ap.add_argument("--policy", default="markov", choices=["markov", "fixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="fifo,kernelet")
+    ap.add_argument("--seed", type=int, default=0)
+    return ap.parse_args()
+
+
+def algorithmic(kind, inst_args):
+    """(flops, bytes, compute peak) of one instance, from its argument block."""
+    a = inst_args
+    if kind == "poly":
+        return 2.0 * a.n * (a.ncoef - 1), 8.0 * a.n + 4.0 * a.ncoef, PEAK_VALU_F32
+    if kind == "gather":
+        return 0.0, 12.0 * a.n, PEAK_VALU_F32
+    if kind == "sgemm":
+        return 2.0 * a.m * a.n * a.k, 4.0 * (a.m * a.k + a.k * a.n + a.m * a.n), PEAK_MFMA_F32
+    if kind == "spmv":
+        return 2.0 * a.nnz, 4.0 * (a.nrows + 1) + 8.0 * a.nnz + 4.0 * a.nrows + 4.0 * a.ncols, \
+            PEAK_VALU_F32
+    if kind == "stencil":
+        return 6.0 * a.nx * a.ny, 8.0 * a.nx * a.ny, PEAK_VALU_F32
+    if kind == "bs":
+        return 0.0, 20.0 * a.n, PEAK_VALU_F32
+    if kind == "hist":
+        return 0.0, 1.0 * a.n + 1024, PEAK_VALU_F32
+    if kind == "lookup":
+        return 0.0, 8.0 * a.nq + 4.0 * a.nkeys, PEAK_VALU_F32
+    raise KeyError(kind)
+
+
+def cpu_baseline(hosts):
+    """The CPU oracle on a bounded sample of one instance of each type; the
+    per-instance time of each type is scaled up from its sample."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    t_inst = {}
+    samples = {}
+
+    def timed(fn):
+        t = time.perf_counter()
+        fn()
+        return time.perf_counter() - t
+
+    h = hosts["poly"]
+    t_inst["poly"] = timed(lambda: oracle.poly(h["x"], h["coef"]))
+    samples["poly"] = "full"
+    h = hosts["gather"]
+    t_inst["gather"] = timed(lambda: oracle.gather(h["idx"], h["table"]))
+    samples["gather"] = "full"
+    h = hosts["sgemm"]
+    fr = 8
+    m = h["a"].shape[0] // fr
+    t_inst["sgemm"] = fr * timed(lambda: oracle.sgemm(h["a"][:m], h["b"]))
+    samples["sgemm"] = f"first {m} rows of A"
+    h = hosts["spmv"]
+    t_inst["spmv"] = timed(lambda: oracle.spmv(h["row_ptr"], h["col"], h["val"], h["x"]))
+    samples["spmv"] = "full"
+    h = hosts["stencil"]
+    fr = 4
+    ny = h["u"].shape[0] // fr
+    t_inst["stencil"] = fr * timed(lambda: oracle.stencil(h["u"][:ny], 10, 0.5, 0.125))
+    samples["stencil"] = f"first {ny} rows, 10 sweeps"
+    h = hosts["bs"]
+    fr = 4
+    n = h["s"].size // fr
+    t_inst["bs"] = fr * timed(lambda: oracle.black_scholes(h["s"][:n], h["k"][:n],
+                                                           h["t"][:n], 0.02, 0.30))
+    samples["bs"] = f"first {n} options"
+    h = hosts["hist"]
+    t_inst["hist"] = timed(lambda: oracle.histogram(h["data"]))
+    samples["hist"] = "full"
+    h = hosts["lookup"]
+    fr = 16
+    nq = h["q"].size // fr
+    t_inst["lookup"] = fr * timed(lambda: oracle.lower_bound(h["keys"], h["q"][:nq]))
+    samples["lookup"] = f"first {nq} queries"
+    total = sum(t_inst.values())
+    return {"value": len(t_inst) / total, "unit": "kernels/s", "cores": cores, "kind": "oracle",
+            "sample": "one instance of each of the 8 types, CPU time scaled from: " +
+                      "; ".join(f"{k}: {v}" for k, v in samples.items()),
+            "seconds_per_instance": {k: round(v, 4) for k, v in t_inst.items()}}
+
+
+def nearest_rank(v, q):
+    v = sorted(v)
+    return v[max(1, math.ceil(q * len(v))) - 1]
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py runs on one GPU only: the co-execution engine shares one device "
+              "between kernels; a multi-GPU run would be independent engines behind a "
+              "dispatcher and is not measured here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import profiles
+    from paper_1303_5164_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    t_setup = time.perf_counter()
+    F = synth.FULL
+    hosts = {
+        "poly": synth.poly(args.seed, **F["poly"]),
+        "gather": synth.gather(args.seed, **F["gather"]),
+        "sgemm": synth.sgemm(args.seed, **F["sgemm"]),
+        "spmv": synth.spmv(args.seed, **F["spmv"]),
+        "stencil": synth.stencil(args.seed, F["stencil"]["ny"], F["stencil"]["nx"]),
+        "bs": synth.bs(args.seed, F["bs"]["n"]),
+        "hist": synth.hist(args.seed, F["hist"]["n"]),
+        "lookup": synth.lookup(args.seed, **F["lookup"]),
+    }
+    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
+                              c1=F["stencil"]["c1"]),
+              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    dev_in = {k: W.device_inputs(k, h, dev) for k, h in hosts.items()}
+    insts = []
+    for i in range(args.instances):
+        for k in W.TYPES:
+            insts.append(W.build(k, dev_in[k], params.get(k, {}), dev))
+    order = np.random.default_rng(args.seed).permutation(len(insts))
+    insts = [insts[i] for i in order]
+    torch.cuda.synchronize()
+
+    rt = K.Runtime(0)
+    prof = profiles.load()
+    kids = {k: rt.register_builtin(k, prof[k]) for k in W.TYPES}
+    setup_s = time.perf_counter() - t_setup
+
+    # algorithmic work per instance and per workgroup
+    work = {}
+    for inst in insts:
+        if inst.kind in work:
+            continue
+        f = b = 0.0
+        wgs = 0
+        peak = None
+        for ln in inst.launches:
+            ff, bb, peak = algorithmic(inst.kind, ln.args)
+            f += ff
+            b += bb
+            wgs += ln.grid[0] * ln.grid[1] * ln.grid[2]
+        work[inst.kind] = dict(flops=f, bytes=b, peak=peak, wgs=wgs)
+
+    legs = [l for l in args.legs.split(",") if l]
+    times = {l: [] for l in legs}
+    turn = {l: [] for l in legs}
+    ktime = {k: [0.0, 0, 0] for k in W.TYPES}
+    decisions = 0
+    for step in range(args.warmup + args.steps):
+        timed_step = step >= args.warmup
+        for leg in legs:
+            for inst in insts:
+                inst.reset()
+            if timed_step:
+                for k in W.TYPES:
+                    rt.time_kernel(kids[k], True)
+            jobs = [W.submit(rt, kids, inst) for inst in insts]
+            torch.cuda.synchronize()
+            t0 = time.monotonic_ns()
+            rt.schedule("fifo" if leg == "fifo" else args.policy, blocking=True,
+                        wait_done=True)
+            torch.cuda.synchronize()
+            t1 = time.monotonic_ns()
+            if timed_step:
+                times[leg].append((t1 - t0) / 1e9)
+                for js in jobs:
+                    _, _, td = rt.job_times(js[-1])
+                    turn[leg].append(max(td - t0, 0) / 1e6)
+                for k in W.TYPES:
+                    ms, n, w = rt.kernel_time(kids[k])
+                    ktime[k][0] += ms
+                    ktime[k][1] += n
+                    ktime[k][2] += w
+                    rt.time_kernel(kids[k], False)
+            if leg != "fifo":
+                decisions += len(rt.decisions())
+            rt.reap()
+            print(f"# step {step} {leg}: {(t1 - t0) / 1e6:.2f} ms", file=sys.stderr,
+                  flush=True)
+
+    n_inst = len(insts)
+    med = {l: float(np.median(times[l])) for l in legs}
+    main_leg = "kernelet" if "kernelet" in legs else legs[0]
+    value = n_inst / med[main_leg]
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "kernels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(med[main_leg] * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "eight-kernel mix (sgemm 4096^3, spmv 2^20 rows, stencil "
+                               "8192^2 x10, black-scholes 2^25, histogram 2^28 B, lookup "
+                               "2^26 in 2^26, polynomial 2^20 x256 fma, gather 2^22 of "
+                               "2^24), seed %d" % args.seed,
+                   "instances_per_type": args.instances, "instances": n_inst,
+                   "policy": args.policy, "parallelism": "single GPU, 2 co-execution lanes"},
+    }
+    if "fifo" in legs:
+        out["fifo_kernels_per_s"] = round(n_inst / med["fifo"], 3)
+        out["fifo_ms_per_step"] = round(med["fifo"] * 1e3, 4)
+        if main_leg != "fifo":
+            out["gain_vs_fifo"] = round(med["fifo"] / med[main_leg], 4)
+    for l in legs:
+        out[f"{l}_p50_turnaround_ms"] = round(nearest_rank(turn[l], 0.5), 3)
+        out[f"{l}_p99_turnaround_ms"] = round(nearest_rank(turn[l], 0.99), 3)
+    out["decisions_per_step"] = decisions / max(1, args.warmup + args.steps)
+
+    # roofline of the dominant kernel: all its launches in the timed region
+    dom = max(W.TYPES, key=lambda k: ktime[k][0])
+    ms, n, wg = ktime[dom]
+    wk = work[dom]
+    per_wg_f = wk["flops"] / wk["wgs"]
+    per_wg_b = wk["bytes"] / wk["wgs"]
+    if dom == "sgemm":
+        ach = per_wg_f * wg / (ms / 1e3)
+        roof = {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_MFMA_F32 / 1e12,
+                "unit": "TFLOP/s"}
+    elif dom == "poly":
+        ach = per_wg_f * wg / (ms / 1e3)
+        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_VALU_F32 / 1e12,
+                "unit": "TFLOP/s"}
+    else:
+        ach = per_wg_b * wg / (ms / 1e3)
+        roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["achieved"] = round(roof["achieved"], 3)
+    roof["frac"] = round(roof["frac"], 4)
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launches"] = n
+    roof["avg_launch_ms"] = round(ms / max(n, 1), 5)
+    roof["per_launch_work"] = round((per_wg_f if dom in ("sgemm", "poly") else per_wg_b)
+                                    * wg / max(n, 1), 1)
+    out["roofline"] = roof
+    # whole-mix roofline fraction: overlapped bound over measured time
+    comp = sum(work[k]["flops"] / work[k]["peak"] for k in W.TYPES) * args.instances
+    mem = sum(work[k]["bytes"] / PEAK_HBM for k in W.TYPES) * args.instances
+    out["mix_roofline"] = {l: round(max(comp, mem) / med[l], 4) for l in legs}
+    out["mix_bound_ms"] = {"compute": round(comp * 1e3, 4), "hbm": round(mem * 1e3, 4)}
+    out["kernel_ms_per_step"] = {k: round(ktime[k][0] / max(1, args.steps), 3) for k in W.TYPES}
+    out["setup_s"] = round(setup_s, 1)
+    st = rt.stats()
+    out["decision_us_mean"] = round(st["decision_us_total"] / max(1, st["decisions"]), 2)
+    rt.close()
+    if not args.no_cpu_baseline:
+        print("# cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(hosts)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,298 @@
+/*
+ * kernelet.h -- C ABI of the sliced co-execution engine (libkernelet.so).
+ *
+ * The engine raises the throughput of many independent GPU kernels sharing
+ * one MI355X (gfx950) by the method of Kernelet (Zhong & He): every
+ * submitted kernel is cut into slices (contiguous ranges of workgroup ids,
+ * Section 2.2 "Problem Definition"), slices of two kernels with
+ * complementary demands run at the same time (a co-schedule), and the pair
+ * and its slice sizes are chosen greedily (Algorithm 1 with procedure
+ * FindCoSchedule, Section 4.2) after PUR/MUR pruning (Section 4.3) by a
+ * Markov-chain model of wavefront states (Section 4.4).
+ *
+ * Conventions for every call:
+ *   - the return value is a kl_status: 0 on success, a negative KL_E* code
+ *     on failure; kernelet_last_error() gives a message for the calling
+ *     thread's last failure.  No C++ exception crosses this boundary.
+ *   - "host" pointers point to CPU memory, "device" pointers to memory
+ *     allocated on the runtime's GPU (e.g. by PyTorch).  The library never
+ *     frees memory it did not allocate.
+ *   - calls are thread-safe except kernelet_init / kernelet_shutdown, which
+ *     must not race with any other call on the same runtime.
+ */
+#ifndef KERNELET_H
+#define KERNELET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kl_status;
+#define KL_OK 0
+#define KL_EINVAL (-1)     /* bad argument, size or grid */
+#define KL_ENOMEM (-2)     /* request larger than the memory budget */
+#define KL_EEXIST (-3)     /* a kernel of that name is registered */
+#define KL_ENOTFOUND (-4)  /* unknown kernel, job or symbol */
+#define KL_ESTATE (-5)     /* call not valid in the object's state */
+#define KL_ETIMEOUT (-6)   /* wait timed out; the job keeps running */
+#define KL_EHIP (-7)       /* a HIP runtime call failed */
+#define KL_ECANCELED (-8)  /* the job was cancelled */
+#define KL_EINTERNAL (-9)
+
+typedef struct kl_runtime kl_runtime; /* opaque; owned by the library */
+typedef int32_t kl_kernel;            /* kernel type handle (>= 0) */
+typedef int64_t kl_job;               /* job handle (>= 0) */
+#define KL_NO_JOB ((kl_job)-1)
+
+typedef struct {
+    uint32_t x, y, z;
+} kl_dim3;
+
+/* Device-side slice descriptor.  Every sliceable kernel takes it as its
+ * LAST argument and is launched on a 1-D grid of `count` workgroups; its
+ * workgroup with built-in index b is workgroup offset + b of the ORIGINAL
+ * grid (gx, gy, gz), linearised row-major: id = x + gx (y + gy z).  This is
+ * the paper's index rectification (Section 4.1), done at source level. */
+typedef struct {
+    uint32_t offset; /* first original workgroup id of the slice */
+    uint32_t count;  /* workgroups in the slice (= launch grid) */
+    uint32_t gx, gy, gz;
+    uint32_t reserved;
+} kl_slice;
+
+/* Per-kernel inputs of the performance model and of pruning (Section 4.4,
+ * "getting the input for the model"; PUR and MUR of Section 4.3).  The
+ * Markov model runs on a virtual SIMD (the paper's virtual single-scheduler
+ * SM, one of the 4 SIMDs of a CU); its time unit is one issue slot. */
+typedef struct {
+    double r_mem;          /* P(issued instruction stalls on memory)      */
+    double mem_req;        /* memory requests held by one stalled wave     */
+    double lat_mem;        /* memory-stall latency when the memory system
+                              is idle, issue slots (0: the config's)       */
+    double r_comp;         /* P(issued instruction stalls on compute)     */
+    double lat_comp;       /* compute-stall latency, issue slots           */
+    double instr_per_wave; /* instructions one wave executes (I_K)         */
+    double pur, mur;       /* pipeline / memory-bandwidth utilisation     */
+    double solo_ipc;       /* measured solo IPC (informational)            */
+    int32_t max_wg_per_cu; /* resource-limited workgroups per CU, alone   */
+    int32_t waves_per_simd;/* waves one workgroup puts on each SIMD        */
+    int32_t vgpr;          /* VGPRs per lane (0: not limiting)             */
+    int32_t lds_bytes;     /* static LDS bytes per workgroup               */
+    int32_t min_slice_wgs; /* calibrated minimum slice (0: unknown)        */
+    int32_t reserved;
+} kl_profile;
+
+#define KL_KF_IDEMPOTENT 1u /* re-running a slice gives the same result */
+
+typedef struct {
+    const char* name;        /* copied; unique per runtime */
+    const void* host_fn;     /* __global__ fn(ArgsT args, kl_slice s) */
+    uint32_t block_threads;  /* workgroup size; a multiple of 256 */
+    uint32_t args_bytes;     /* sizeof(ArgsT), <= 256 */
+    uint32_t flags;          /* KL_KF_* */
+    const kl_profile* profile; /* optional; copied */
+} kl_kernel_desc;
+
+typedef enum {
+    KL_POLICY_FIFO = 0,    /* every job unsliced, in submission order, one stream */
+    KL_POLICY_MARKOV = 1,  /* Algorithm 1 driven by the Markov model */
+    KL_POLICY_SURROGATE = 2, /* Algorithm 1, pairs ranked by the surrogate
+                                network, the Markov model evaluating its top k */
+    KL_POLICY_FIXED = 3    /* Algorithm 1 with explicit slice plans only */
+} kl_policy;
+
+#define KL_BLOCKING 1u           /* return when every pending job is launched */
+#define KL_REPLAN_ON_ARRIVAL 2u  /* re-decide when a job arrives */
+#define KL_WAIT_DONE 4u          /* with KL_BLOCKING: return when every job has
+                                    finished (completion times are stamped by
+                                    the dispatcher as slices retire) */
+
+typedef enum {
+    KL_MODE_BALANCED = 0, /* max 1 - max(T1,T2)/(T1s+T2s) over slice ratios */
+    KL_MODE_CP = 1,       /* max Eq. (1) */
+    KL_MODE_LITERAL = 2   /* min Delta T of Eq. (8), ties to larger CP */
+} kl_ratio_mode;
+
+typedef struct {
+    int32_t n_cu;          /* compute units (0: query the device) */
+    int32_t wmax;          /* wave slots per SIMD (8 on gfx950) */
+    int32_t vgpr_file;     /* VGPRs per lane per SIMD (512) */
+    int32_t lds_cu;        /* LDS bytes per CU (163840) */
+    double alpha_p, alpha_m; /* pruning thresholds (0.4, 0.1) */
+    int32_t use_prune;
+    int32_t ratio_mode;    /* kl_ratio_mode (KL_MODE_CP) */
+    double cp_min;         /* co-run only if predicted profit exceeds this */
+    double mem_latency;    /* memory latency with an idle memory system, slots */
+    double beta;           /* latency added per outstanding request, slots */
+    int32_t lanes;         /* co-execution streams (2) */
+    int32_t inflight;      /* slices queued per lane ahead of the GPU (2) */
+    int32_t lds_reserve;   /* 1: reserve LDS so a CU holds <= b1+b2 slices' WGs */
+    int32_t max_slices;    /* cap on slices per co-schedule of one kernel (0: none) */
+    int64_t hbm_budget;    /* bytes of job footprint admitted at once (0: none) */
+    int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE) */
+    int32_t reserved[7];
+} kl_config;
+
+typedef struct {
+    int64_t jobs_submitted, jobs_done;
+    int64_t slices_launched, decisions;
+    double decision_us_total;   /* host time spent in FindCoSchedule */
+    double model_us_total;      /* of which Markov solves */
+    int64_t cache_hits;
+} kl_stats;
+
+/* One scheduling decision, as logged (Algorithm 1, one co-schedule). */
+typedef struct {
+    kl_job j1, j2;       /* j2 = KL_NO_JOB: kernel runs alone */
+    int32_t b1, b2;      /* workgroups per CU of each slice */
+    uint32_t slice1, slice2; /* slice sizes in workgroups */
+    double value;        /* objective of the chosen ratio */
+    double cipc1, cipc2; /* predicted co-run IPCs */
+    double t_us;         /* host time of the decision since the first */
+} kl_decision;
+
+/* ---------------------------------------------------------------- set-up */
+
+/* Fill *cfg with the defaults listed beside kl_config's fields. */
+kl_status kernelet_default_config(kl_config* cfg);
+
+/* Create a runtime on HIP device `hip_device`.  `cfg` (host, may be NULL for
+ * defaults) is copied.  The runtime owns its streams, events and threads. */
+kl_status kernelet_init(kl_runtime** rt, int hip_device, const kl_config* cfg);
+
+/* Wait for every launched slice, stop the scheduler thread, free all. */
+kl_status kernelet_shutdown(kl_runtime* rt);
+
+/* Message of the calling thread's last failure ("" if none); owned by the
+ * library, valid until the thread's next call. */
+const char* kernelet_last_error(void);
+
+/* --------------------------------------------------------------- kernels */
+
+/* Register a kernel type (Section 3.2: submitted kernels are kept per
+ * type so that a profile and a slice size are reused).  Duplicate name:
+ * KL_EEXIST.  block_threads not a positive multiple of 256 or args_bytes
+ * > 256: KL_EINVAL. */
+kl_status kernelet_register(kl_runtime* rt, const kl_kernel_desc* d,
+                            kl_kernel* out);
+
+/* Look up one of the library's eight workload kernels by name ("poly",
+ * "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup") and fill a
+ * descriptor for kernelet_register.  The descriptor's strings are static. */
+kl_status kernelet_builtin(const char* name, kl_kernel_desc* out);
+
+/* Original grid a built-in kernel needs for the argument block `args`
+ * (host, the kernel's argument struct of include/kernelet_workloads.h). */
+kl_status kernelet_builtin_grid(const char* name, const void* args,
+                                uint32_t args_bytes, kl_dim3* grid);
+
+kl_status kernelet_set_profile(kl_runtime* rt, kl_kernel k, const kl_profile* p);
+kl_status kernelet_get_profile(kl_runtime* rt, kl_kernel k, kl_profile* p);
+
+/* ------------------------------------------------------------------ jobs */
+
+/* Submit one launch of kernel `k` over the ORIGINAL grid `grid` with
+ * argument block `args` (host, args_bytes bytes, copied before return).
+ * Device pointers inside `args` are borrowed: the caller keeps the memory
+ * alive until kernelet_wait on this job returns KL_OK.  `after` (or
+ * KL_NO_JOB) names a job that must finish before this one starts.
+ * `client` tags the submitting client; `footprint` is the device memory the
+ * job holds (for the memory budget).  A job becomes pending at once (and
+ * is scheduled by the next or the running kernelet_schedule).  Errors:
+ * KL_EINVAL (grid of zero workgroups or > 2^32-1, size mismatch, grid not
+ * the built-in kernel's required grid), KL_ENOTFOUND (k or after),
+ * KL_ENOMEM (footprint above the whole budget). */
+kl_status kernelet_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid,
+                          const void* args, uint32_t args_bytes, kl_job after,
+                          uint32_t client, uint64_t footprint, kl_job* out);
+
+/* Fix the slicing plan of a job before it starts: slices of `wgs_per_slice`
+ * workgroups (0: the calibrated minimum of its kernel, else its whole
+ * grid); *n_slices receives the slice count.  Used by the FIXED policy and
+ * by tests.  KL_ESTATE if the job has started. */
+kl_status kernelet_slice(kl_runtime* rt, kl_job j, uint32_t wgs_per_slice,
+                         uint32_t* n_slices);
+
+/* Run the scheduler with `policy` over the pending jobs.  With KL_BLOCKING
+ * the call returns once every pending job (including dependants released
+ * meanwhile) has been launched; otherwise a scheduler thread keeps serving
+ * submissions until kernelet_shutdown.  Launches are asynchronous: use
+ * kernelet_wait for completion. */
+kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags);
+
+/* Block until job j has finished on the GPU, or `timeout_ns` (< 0:
+ * forever) elapses.  KL_OK, KL_ETIMEOUT, KL_EHIP (device error),
+ * KL_ECANCELED, KL_ENOTFOUND. */
+kl_status kernelet_wait(kl_runtime* rt, kl_job j, int64_t timeout_ns);
+
+/* Block until every launched slice has finished. */
+kl_status kernelet_synchronize(kl_runtime* rt);
+
+/* Cancel a job that has not started.  KL_ESTATE once it has. */
+kl_status kernelet_cancel(kl_runtime* rt, kl_job j);
+
+/* Host timestamps (ns, steady clock) of a job: submission, first launch,
+ * completion observed by the library (0 when unknown). */
+kl_status kernelet_job_times(kl_runtime* rt, kl_job j, int64_t* t_submit,
+                             int64_t* t_start, int64_t* t_done);
+
+/* Forget finished jobs (their handles become unknown). */
+kl_status kernelet_reap(kl_runtime* rt);
+
+/* ----------------------------------------------------------------- model */
+
+/* Performance model on two kernel profiles (host; no GPU needed): per-kernel
+ * IPCs when w1 and w2 waves per SIMD co-run (Eqs. 5-7; w2 = 0 gives the
+ * homogeneous model of Eq. 4), and CP of Eq. (1) against each kernel alone
+ * at its own full occupancy.  Latency: mem_latency + beta * outstanding
+ * requests (cfg may be NULL for defaults).  Any output pointer may be NULL. */
+kl_status kernelet_predict(const kl_config* cfg, const kl_profile* p1,
+                           const kl_profile* p2, int32_t w1, int32_t w2,
+                           double* ipc1, double* ipc2, double* cp);
+
+/* Best feasible slice ratio of a pair (Section 4.4, balanced slice ratio):
+ * writes b1, b2 (workgroups per CU), the objective and the two IPCs.
+ * KL_ENOTFOUND when no ratio fits the CU's resources. */
+kl_status kernelet_best_ratio(const kl_config* cfg, const kl_profile* p1,
+                              const kl_profile* p2, int32_t* b1, int32_t* b2,
+                              double* value, double* cipc1, double* cipc2);
+
+/* Greedy co-scheduling on the virtual clock of the model (no GPU): runs
+ * Algorithm 1 (or FIFO if policy == KL_POLICY_FIFO) over n jobs given by
+ * kernel profile index, workgroup count and arrival time; writes up to
+ * max_dec decisions (j1/j2 are job indices), their count, the makespan and
+ * each job's completion time (host arrays of n).  Used to test the
+ * scheduler against the oracle and to predict a plan's gain. */
+kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
+                            int32_t n_profiles, const int32_t* job_profile,
+                            const uint64_t* job_wgs, const double* job_arrival,
+                            int32_t n_jobs, kl_policy policy,
+                            kl_decision* decisions, int32_t max_dec,
+                            int32_t* n_dec, double* makespan, double* done);
+
+/* --------------------------------------------------------------- logging */
+
+/* Time every launch of kernel k (enable != 0) with a pair of HIP events
+ * recorded around it on the stream it is launched on.  Enabling resets the
+ * kernel's counters. */
+kl_status kernelet_time_kernel(kl_runtime* rt, kl_kernel k, int32_t enable);
+
+/* Launch timing of kernel k since it was enabled: summed GPU time of its
+ * launches (ms, event to event), number of launches and workgroups.  Only
+ * launches that have finished are counted (call after a synchronisation). */
+kl_status kernelet_kernel_time(kl_runtime* rt, kl_kernel k, double* total_ms,
+                               int64_t* launches, int64_t* workgroups);
+
+kl_status kernelet_stats(kl_runtime* rt, kl_stats* out);
+
+/* Copy up to `max` logged decisions of the runtime (oldest first) to
+ * `out` (host); *n receives the number copied.  The log is cleared. */
+kl_status kernelet_decisions(kl_runtime* rt, kl_decision* out, int32_t max,
+                             int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KERNELET_H */

@@ -1,0 +1,125 @@
+/*
+ * kernelet_workloads.h -- argument blocks of the eight built-in workload
+ * kernels of libkernelet.so (see kernelet_builtin in kernelet.h).
+ *
+ * Each kernel is launched by the runtime as fn(Args a, kl_slice s) on
+ * 256-thread workgroups; the ORIGINAL grid is what kernelet_builtin_grid
+ * returns for the argument block, and kernelet_submit rejects any other.
+ * All pointers are device pointers; all arrays are dense and row-major.
+ * The paper's evaluation names its workloads only by name and size (its
+ * benchmark description table); the eight here take their roles (compute
+ * bound, memory bound, irregular, latency bound).
+ */
+#ifndef KERNELET_WORKLOADS_H
+#define KERNELET_WORKLOADS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* poly: y[t] = sum_{k<ncoef} coef[k] x[t]^k by Horner's rule in fp32 with one
+ * fused multiply-add per coefficient, highest degree first.  One thread per
+ * element; grid = ceil(n / 256).  ncoef in [1, 1024]. */
+typedef struct {
+    const float* x;
+    const float* coef;
+    float* y;
+    uint32_t n;
+    uint32_t ncoef;
+} kl_poly_args;
+
+/* gather: out[t] = table[idx[t]], idx[t] in [0, table_n).  One thread per
+ * element; grid = ceil(n / 256).  Indices outside the table are not read
+ * (out[t] = 0). */
+typedef struct {
+    const int32_t* idx;
+    const int32_t* table;
+    int32_t* out;
+    uint32_t n;
+    uint32_t table_n;
+} kl_gather_args;
+
+/* sgemm: C = A B in fp32 on matrix cores, A m x k, B k x n, C m x n.
+ * m, n multiples of 128, k a multiple of 16.  grid = (m/128) (n/128). */
+typedef struct {
+    const float* a;
+    const float* b;
+    float* c;
+    uint32_t m, n, k;
+} kl_sgemm_args;
+
+/* spmv: y = A x, A in CSR (row_ptr[nrows+1], col[nnz], val[nnz]),
+ * x[ncols], y[nrows] in fp32.  16 lanes per row; grid = ceil(nrows / 16).
+ * Entries past nnz and columns outside [0, ncols) are skipped. */
+typedef struct {
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const float* val;
+    const float* x;
+    float* y;
+    uint32_t nrows;
+    uint32_t ncols;
+    uint32_t nnz;
+    uint32_t reserved;
+} kl_spmv_args;
+
+/* stencil: one Jacobi sweep of the 5-point stencil on an ny x nx grid:
+ * interior out = c0 in + c1 ((N + S) + (W + E)), boundary cells copied.
+ * Tiles of 64 x 16 cells; grid = (ceil(nx/64), ceil(ny/16), 1). */
+typedef struct {
+    const float* in;
+    float* out;
+    uint32_t ny, nx;
+    float c0, c1;
+} kl_stencil_args;
+
+/* bs: Black-Scholes European call and put for n options (S, K, T) at rate
+ * r and volatility sigma.  Four options per thread; grid = ceil(n / 1024).
+ * n a multiple of 4. */
+typedef struct {
+    const float* s;
+    const float* k;
+    const float* t;
+    float* call;
+    float* put;
+    uint32_t n;
+    float r, sigma;
+} kl_bs_args;
+
+/* hist: bins[v] += #{t < n : data[t] == v} for 256 bins (the caller zeroes
+ * bins first; not idempotent).  n a multiple of 16; each workgroup counts
+ * a chunk of 65536 bytes; grid = ceil(n / 65536). */
+typedef struct {
+    const uint8_t* data;
+    uint32_t* bins;
+    uint64_t n;
+} kl_hist_args;
+
+/* lookup: out[t] = lower_bound(keys, q[t]) = smallest i with keys[i] >=
+ * q[t], or nkeys if none; keys strictly increasing.  Four queries per
+ * thread; grid = ceil(nq / 1024).  nq a multiple of 4, nkeys >= 1. */
+typedef struct {
+    const uint32_t* keys;
+    const uint32_t* q;
+    int32_t* out;
+    uint32_t nkeys;
+    uint32_t nq;
+} kl_lookup_args;
+
+/* probe (not a workload): workgroup w adds 1 to visits[w] and writes
+ * info[3w] = (XCC_ID << 32) | HW_ID, info[3w+1] = start, info[3w+2] = end
+ * (wall clock ticks), after `spin` dependent fmas per thread.
+ * grid = n_wg; spin <= 2^24. */
+typedef struct {
+    uint32_t* visits;
+    uint64_t* info;
+    uint32_t n_wg;
+    uint32_t spin;
+} kl_probe_args;
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KERNELET_WORKLOADS_H */

@@ -244,8 +244,10 @@ def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", **kw):
     """Search the feasible (b1, b2) of a pair.
 
     mode "balanced": maximise CP_eff = 1 - max(T1, T2) / (T1s + T2s) with
-      T_i = b_i I_i / cIPC_i (time of one slice of each kernel co-running)
-      and T_is = b_i I_i / IPC_i,solo; at T1 = T2 this is Eq. (1).
+      T_i = n_i / cIPC_i the time of one slice of each kernel co-running
+      (Eq. 8: n_i = instructions of the slice per SIMD = b_i * waves per
+      workgroup * I_K) and T_is = n_i / IPC_i,solo; at T1 = T2 this is
+      Eq. (1).
     mode "cp": maximise Eq. (1) directly.
     mode "literal": minimise Delta T of Eq. (8), ties to the larger CP.
     Returns (b1, b2, cp_value, cipc1, cipc2); first maximum in (b1, b2)
@@ -258,10 +260,12 @@ def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", **kw):
         c1, c2 = ipc_pair(p1.kernel, b1 * p1.wave_per_wg,
                           p2.kernel, b2 * p2.wave_per_wg, beta)
         cpv = cp((c1, c2), (s1, s2))
-        T1 = b1 * p1.instr_per_wave / c1
-        T2 = b2 * p2.instr_per_wave / c2
-        T1s = b1 * p1.instr_per_wave / s1
-        T2s = b2 * p2.instr_per_wave / s2
+        # instructions one SIMD executes for a slice: b workgroups, each
+        # with wave_per_wg waves of I_K instructions
+        n1 = b1 * p1.wave_per_wg * p1.instr_per_wave
+        n2 = b2 * p2.wave_per_wg * p2.instr_per_wave
+        T1, T2 = n1 / c1, n2 / c2
+        T1s, T2s = n1 / s1, n2 / s2
         if mode == "balanced":
             key = (1.0 - max(T1, T2) / (T1s + T2s),)
             val = key[0]

@@ -59,7 +59,7 @@ class Config:
     alpha_m: float = 0.1
     use_prune: bool = True
     beta: float = 0.0
-    mode: str = "balanced"
+    mode: str = "cp"
     cp_min: float = 0.0
     wmax: int = 8
     vgpr_file: int = 512

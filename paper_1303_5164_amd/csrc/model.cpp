@@ -1,0 +1,383 @@
+// Markov-chain performance model, pruning and co-schedule search (host).
+// See model.hpp for the model's definition.
+#include "model.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace kl {
+
+KernelModel kernel_model(const kl_profile& p, const kl_config& cfg) {
+    KernelModel m;
+    m.nclass = 1;
+    m.cls[0] = {p.r_mem, p.lat_mem > 0 ? p.lat_mem : cfg.mem_latency, p.mem_req};
+    if (p.r_comp > 0) {
+        m.cls[1] = {p.r_comp, p.lat_comp, 0.0};
+        m.nclass = 2;
+    }
+    return m;
+}
+
+namespace {
+
+const double kFact[] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880,
+                        3628800, 39916800, 479001600};
+
+double binom(int n, int k, double p) {
+    if (k < 0 || k > n) return 0.0;
+    double c = kFact[n] / (kFact[k] * kFact[n - k]);
+    return c * std::pow(p, k) * std::pow(1.0 - p, n - k);
+}
+
+// Stalled-count tuples of one kernel: (n0) or (n0, n1), sum <= w.
+struct KStates {
+    int nclass, w;
+    std::vector<int> n0, n1;  // per state
+    std::vector<int> index;   // (a * (w + 1) + b) -> state index
+    int size() const { return (int)n0.size(); }
+    int at(int a, int b) const { return index[a * (w + 1) + b]; }
+};
+
+KStates enumerate(int w, int nclass) {
+    KStates s;
+    s.nclass = nclass;
+    s.w = w;
+    s.index.assign((w + 1) * (w + 1), -1);
+    for (int a = 0; a <= w; ++a) {
+        if (nclass == 1) {
+            s.index[a * (w + 1)] = s.size();
+            s.n0.push_back(a);
+            s.n1.push_back(0);
+            continue;
+        }
+        for (int b = 0; a + b <= w; ++b) {
+            s.index[a * (w + 1) + b] = s.size();
+            s.n0.push_back(a);
+            s.n1.push_back(b);
+        }
+    }
+    return s;
+}
+
+// Solve (P^T - I) pi = 0 with the last equation replaced by sum(pi) = 1.
+void stationary(const std::vector<double>& P, int N, std::vector<double>& pi) {
+    std::vector<double> A((size_t)N * N);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            A[(size_t)i * N + j] = P[(size_t)j * N + i] - (i == j ? 1.0 : 0.0);
+    for (int j = 0; j < N; ++j) A[(size_t)(N - 1) * N + j] = 1.0;
+    pi.assign(N, 0.0);
+    pi[N - 1] = 1.0;
+    for (int c = 0; c < N; ++c) {  // Gaussian elimination, partial pivoting
+        int piv = c;
+        double best = std::fabs(A[(size_t)c * N + c]);
+        for (int r = c + 1; r < N; ++r) {
+            double v = std::fabs(A[(size_t)r * N + c]);
+            if (v > best) best = v, piv = r;
+        }
+        if (piv != c) {
+            for (int j = 0; j < N; ++j)
+                std::swap(A[(size_t)c * N + j], A[(size_t)piv * N + j]);
+            std::swap(pi[c], pi[piv]);
+        }
+        double d = A[(size_t)c * N + c];
+        for (int r = c + 1; r < N; ++r) {
+            double f = A[(size_t)r * N + c] / d;
+            if (f == 0.0) continue;
+            double* ar = &A[(size_t)r * N];
+            const double* ac = &A[(size_t)c * N];
+            for (int j = c; j < N; ++j) ar[j] -= f * ac[j];
+            pi[r] -= f * pi[c];
+        }
+    }
+    for (int c = N - 1; c >= 0; --c) {
+        double s = pi[c];
+        for (int j = c + 1; j < N; ++j) s -= A[(size_t)c * N + j] * pi[j];
+        pi[c] = s / A[(size_t)c * N + c];
+    }
+}
+
+}  // namespace
+
+void chain_ipc(const KernelModel* km, const int* w, int nk, double beta,
+               double* ipc_out) {
+    KStates ks[2] = {enumerate(w[0], km[0].nclass),
+                     enumerate(nk > 1 ? w[1] : 0, nk > 1 ? km[1].nclass : 1)};
+    const int S1 = ks[0].size(), S2 = nk > 1 ? ks[1].size() : 1;
+    const int N = S1 * S2;
+    std::vector<double> P((size_t)N * N, 0.0);
+    std::vector<double> mv[2] = {std::vector<double>(S1), std::vector<double>(S2)};
+    for (int i1 = 0; i1 < S1; ++i1) {
+        for (int i2 = 0; i2 < S2; ++i2) {
+            int nst[2][2] = {{ks[0].n0[i1], ks[0].n1[i1]},
+                             {nk > 1 ? ks[1].n0[i2] : 0, nk > 1 ? ks[1].n1[i2] : 0}};
+            int ready[2];
+            double outst = 0.0;
+            int rtot = 0;
+            for (int k = 0; k < nk; ++k) {
+                ready[k] = w[k] - nst[k][0] - nst[k][1];
+                rtot += ready[k];
+                for (int c = 0; c < km[k].nclass; ++c) outst += nst[k][c] * km[k].cls[c].req;
+            }
+            double D = std::max(rtot, 1);
+            for (int k = 0; k < nk; ++k) {
+                const KernelModel& m = km[k];
+                double q[2] = {0, 0};
+                for (int c = 0; c < m.nclass; ++c) {
+                    const StallClass& sc = m.cls[c];
+                    double lat = sc.req > 0 ? sc.base + beta * outst : sc.base;
+                    q[c] = std::min(1.0, D / lat);
+                }
+                std::vector<double>& out = mv[k];
+                std::fill(out.begin(), out.end(), 0.0);
+                int r = ready[k];
+                int n0 = nst[k][0], n1 = nst[k][1];
+                if (m.nclass == 1) {
+                    for (int a = 0; a <= r; ++a) {
+                        double pn = binom(r, a, m.cls[0].r);
+                        if (pn == 0.0) continue;
+                        for (int b = 0; b <= n0; ++b) {
+                            double pb = pn * binom(n0, b, q[0]);
+                            if (pb == 0.0) continue;
+                            out[ks[k].at(n0 - b + a, 0)] += pb;
+                        }
+                    }
+                } else {
+                    double p0 = m.cls[0].r, p1 = m.cls[1].r, pr = 1.0 - p0 - p1;
+                    for (int a0 = 0; a0 <= r; ++a0) {
+                        for (int a1 = 0; a0 + a1 <= r; ++a1) {
+                            int rest = r - a0 - a1;
+                            double c = kFact[r] / (kFact[a0] * kFact[a1] * kFact[rest]);
+                            double pn = c * std::pow(pr, rest) * std::pow(p0, a0) *
+                                        std::pow(p1, a1);
+                            if (pn == 0.0) continue;
+                            for (int b0 = 0; b0 <= n0; ++b0) {
+                                double pb0 = pn * binom(n0, b0, q[0]);
+                                if (pb0 == 0.0) continue;
+                                for (int b1 = 0; b1 <= n1; ++b1) {
+                                    double pb = pb0 * binom(n1, b1, q[1]);
+                                    if (pb == 0.0) continue;
+                                    out[ks[k].at(n0 - b0 + a0, n1 - b1 + a1)] += pb;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+            double* row = &P[(size_t)(i1 * S2 + i2) * N];
+            if (nk == 1) {
+                for (int j1 = 0; j1 < S1; ++j1) row[j1] = mv[0][j1];
+            } else {
+                for (int j1 = 0; j1 < S1; ++j1) {
+                    if (mv[0][j1] == 0.0) continue;
+                    for (int j2 = 0; j2 < S2; ++j2)
+                        row[j1 * S2 + j2] = mv[0][j1] * mv[1][j2];
+                }
+            }
+        }
+    }
+    std::vector<double> pi;
+    stationary(P, N, pi);
+    double den = 0.0, num[2] = {0.0, 0.0};
+    for (int i1 = 0; i1 < S1; ++i1) {
+        for (int i2 = 0; i2 < S2; ++i2) {
+            double g = pi[i1 * S2 + i2];
+            int r1 = w[0] - ks[0].n0[i1] - ks[0].n1[i1];
+            int r2 = nk > 1 ? w[1] - ks[1].n0[i2] - ks[1].n1[i2] : 0;
+            den += g * std::max(r1 + r2, 1);
+            num[0] += g * r1;
+            num[1] += g * r2;
+        }
+    }
+    for (int k = 0; k < nk; ++k) ipc_out[k] = num[k] / den;
+}
+
+double cp_value(const double* cipc, const double* solo, int n) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += cipc[i] / solo[i];
+    return 1.0 - 1.0 / s;
+}
+
+double solo_ipc(const kl_profile& p, const kl_config& cfg) {
+    int w = p.max_wg_per_cu * p.waves_per_simd;
+    if (w <= 0) return 0.0;
+    KernelModel km = kernel_model(p, cfg);
+    double ipc;
+    chain_ipc(&km, &w, 1, cfg.beta, &ipc);
+    return ipc;
+}
+
+static Ratio best_ratio_with(const kl_profile& p1, const kl_profile& p2,
+                             const kl_config& cfg, double s1, double s2) {
+    Ratio best;
+    double bkey0 = 0, bkey1 = 0;
+    KernelModel km[2] = {kernel_model(p1, cfg), kernel_model(p2, cfg)};
+    for (int b1 = 1; b1 <= p1.max_wg_per_cu; ++b1) {
+        for (int b2 = 1; b2 <= p2.max_wg_per_cu; ++b2) {
+            int w[2] = {b1 * p1.waves_per_simd, b2 * p2.waves_per_simd};
+            if (w[0] + w[1] > cfg.wmax) continue;
+            if (w[0] * p1.vgpr + w[1] * p2.vgpr > cfg.vgpr_file) continue;
+            if ((int64_t)b1 * p1.lds_bytes + (int64_t)b2 * p2.lds_bytes > cfg.lds_cu)
+                continue;
+            double c[2];
+            chain_ipc(km, w, 2, cfg.beta, c);
+            double solo[2] = {s1, s2};
+            double cpv = cp_value(c, solo, 2);
+            double n1 = (double)w[0] * p1.instr_per_wave;
+            double n2 = (double)w[1] * p2.instr_per_wave;
+            double T1 = n1 / c[0], T2 = n2 / c[1];
+            double T1s = n1 / s1, T2s = n2 / s2;
+            double k0, k1 = 0, val;
+            if (cfg.ratio_mode == KL_MODE_BALANCED) {
+                k0 = 1.0 - std::max(T1, T2) / (T1s + T2s);
+                val = k0;
+            } else if (cfg.ratio_mode == KL_MODE_CP) {
+                k0 = cpv;
+                val = cpv;
+            } else {
+                k0 = -std::fabs(T1 - T2);
+                k1 = cpv;
+                val = cpv;
+            }
+            bool better = !best.ok || k0 > bkey0 || (k0 == bkey0 && k1 > bkey1);
+            if (better) {
+                best.ok = true;
+                best.b1 = b1;
+                best.b2 = b2;
+                best.value = val;
+                best.cipc1 = c[0];
+                best.cipc2 = c[1];
+                bkey0 = k0;
+                bkey1 = k1;
+            }
+        }
+    }
+    return best;
+}
+
+Ratio best_ratio(const kl_profile& p1, const kl_profile& p2, const kl_config& cfg) {
+    return best_ratio_with(p1, p2, cfg, solo_ipc(p1, cfg), solo_ipc(p2, cfg));
+}
+
+bool pair_pruned(const kl_profile& a, const kl_profile& b, double ap, double am) {
+    return std::fabs(a.pur - b.pur) < ap && std::fabs(a.mur - b.mur) < am;
+}
+
+double wg_rate(const kl_profile& p, double ipc, int n_cu) {
+    return (double)n_cu * ipc / ((double)p.waves_per_simd * p.instr_per_wave);
+}
+
+void Planner::set_types(const std::vector<kl_profile>& t) {
+    std::lock_guard<std::mutex> g(mu_);
+    types_ = t;
+    solo_.clear();
+    pair_.clear();
+}
+
+void Planner::set_type(int idx, const kl_profile& p) {
+    std::lock_guard<std::mutex> g(mu_);
+    if ((int)types_.size() <= idx) types_.resize(idx + 1);
+    types_[idx] = p;
+    solo_.clear();
+    pair_.clear();
+}
+
+double Planner::solo(int t) {
+    auto it = solo_.find(t);
+    if (it != solo_.end()) return it->second;
+    auto t0 = std::chrono::steady_clock::now();
+    double v = solo_ipc(types_[t], cfg_);
+    model_us += std::chrono::duration<double, std::micro>(
+                    std::chrono::steady_clock::now() - t0).count();
+    solo_[t] = v;
+    return v;
+}
+
+Ratio Planner::pair(int t1, int t2) {
+    auto key = std::make_pair(t1, t2);
+    auto it = pair_.find(key);
+    if (it != pair_.end()) {
+        ++cache_hits;
+        return it->second;
+    }
+    double s1 = solo(t1), s2 = solo(t2);
+    auto t0 = std::chrono::steady_clock::now();
+    Ratio r = best_ratio_with(types_[t1], types_[t2], cfg_, s1, s2);
+    model_us += std::chrono::duration<double, std::micro>(
+                    std::chrono::steady_clock::now() - t0).count();
+    pair_[key] = r;
+    return r;
+}
+
+Decision Planner::find(const std::vector<PendingJob>& pending,
+                       const std::vector<std::pair<int, int>>* only_pairs) {
+    std::lock_guard<std::mutex> g(mu_);
+    Decision solo_d;
+    if (pending.empty()) return solo_d;
+    std::vector<PendingJob> v(pending);
+    std::sort(v.begin(), v.end(),
+              [](const PendingJob& a, const PendingJob& b) { return a.id < b.id; });
+    std::vector<PendingJob> order;  // earliest job of each type, by id
+    for (const auto& j : v) {
+        bool seen = false;
+        for (const auto& o : order) seen |= o.type == j.type;
+        if (!seen) order.push_back(j);
+    }
+    const PendingJob& first = order[0];
+    solo_d.j1 = first.id;
+    solo_d.j2 = -1;
+    solo_d.b1 = types_[first.type].max_wg_per_cu;
+    solo_d.cipc1 = solo(first.type);
+    if (order.size() < 2) return solo_d;
+
+    const int n = (int)order.size();
+    std::vector<std::pair<int, int>> pairs;
+    for (int a = 0; a < n; ++a)
+        for (int b = a + 1; b < n; ++b) pairs.emplace_back(a, b);
+    if (cfg_.use_prune) {
+        double ap = cfg_.alpha_p, am = cfg_.alpha_m;
+        std::vector<std::pair<int, int>> keep;
+        for (int it = 0; it <= 4; ++it) {
+            keep.clear();
+            for (auto& pr : pairs)
+                if (!pair_pruned(types_[order[pr.first].type],
+                                 types_[order[pr.second].type], ap, am))
+                    keep.push_back(pr);
+            if (!keep.empty()) break;
+            ap /= 2.0;
+            am /= 2.0;
+        }
+        if (!keep.empty()) pairs.swap(keep);
+    }
+    Decision best;
+    bool have = false;
+    for (auto& pr : pairs) {
+        const PendingJob& a = order[pr.first];
+        const PendingJob& b = order[pr.second];
+        if (only_pairs) {
+            bool listed = false;
+            for (auto& op : *only_pairs)
+                listed |= (op.first == a.type && op.second == b.type) ||
+                          (op.first == b.type && op.second == a.type);
+            if (!listed) continue;
+        }
+        Ratio r = pair(a.type, b.type);
+        if (!r.ok) continue;
+        if (!have || r.value > best.value) {
+            have = true;
+            best.j1 = a.id;
+            best.j2 = b.id;
+            best.b1 = r.b1;
+            best.b2 = r.b2;
+            best.value = r.value;
+            best.cipc1 = r.cipc1;
+            best.cipc2 = r.cipc2;
+        }
+    }
+    if (!have || best.value <= cfg_.cp_min) return solo_d;
+    return best;
+}
+
+}  // namespace kl

@@ -1,0 +1,99 @@
+// Markov-chain performance model, PUR/MUR pruning and greedy co-schedule
+// search of the co-execution engine (host code, double precision).
+//
+// Model (Kernelet, Section 4.4): the state of a virtual SIMD is the number
+// of stalled wavefronts of each kernel in each stall class; one Markov step
+// is one round in which every ready wave issues one instruction.  A ready
+// wave stalls in class c with probability r_c; a stalled wave returns with
+// probability min(1, D / L_c), D = max(#ready, 1) the round length and
+// L_c = base_c + beta * (outstanding memory requests) for memory classes.
+// Stationary vector by a dense solve; per-kernel IPC = E[ready_k] / E[D]
+// (Eqs. 4-6); CP by Eq. (1).
+#pragma once
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "kernelet.h"
+
+namespace kl {
+
+struct StallClass {
+    double r;     // probability per issued instruction
+    double base;  // latency with an idle memory system (issue slots)
+    double req;   // outstanding requests held while stalled (0: compute)
+};
+
+struct KernelModel {
+    int nclass = 0;
+    StallClass cls[2];
+};
+
+// Profile -> stall classes: class 0 is the memory stall (always present),
+// class 1 the compute stall when r_comp > 0.
+KernelModel kernel_model(const kl_profile& p, const kl_config& cfg);
+
+// Per-kernel IPCs of up to two co-resident kernels with w[k] waves each.
+void chain_ipc(const KernelModel* km, const int* w, int nk, double beta,
+               double* ipc_out);
+
+double cp_value(const double* cipc, const double* solo, int n);
+
+struct Ratio {
+    bool ok = false;
+    int b1 = 0, b2 = 0;
+    double value = 0, cipc1 = 0, cipc2 = 0;
+};
+
+double solo_ipc(const kl_profile& p, const kl_config& cfg);
+Ratio best_ratio(const kl_profile& p1, const kl_profile& p2,
+                 const kl_config& cfg);
+
+bool pair_pruned(const kl_profile& a, const kl_profile& b, double ap,
+                 double am);
+
+// One pending job as seen by FindCoSchedule.
+struct PendingJob {
+    int64_t id;    // submission order key (smaller = earlier)
+    int type;      // kernel type index
+};
+
+struct Decision {
+    int64_t j1 = -1, j2 = -1;  // j2 = -1: solo
+    int b1 = 0, b2 = 0;
+    double value = 0, cipc1 = 0, cipc2 = 0;
+};
+
+// Caches solo IPCs and per-type-pair ratio searches; thread-safe.
+class Planner {
+  public:
+    explicit Planner(const kl_config& cfg) : cfg_(cfg) {}
+    void set_types(const std::vector<kl_profile>& t);
+    void set_type(int idx, const kl_profile& p);
+    const kl_config& cfg() const { return cfg_; }
+    double solo(int t);
+    Ratio pair(int t1, int t2);
+    // FindCoSchedule over pending jobs (any order); `score` (optional)
+    // restricts the Markov evaluation to the pairs it ranks highest.
+    Decision find(const std::vector<PendingJob>& pending,
+                  const std::vector<std::pair<int, int>>* only_pairs = nullptr);
+    const kl_profile& prof(int t) const { return types_[t]; }
+    int ntypes() const { return (int)types_.size(); }
+    double model_us = 0;
+    int64_t cache_hits = 0;
+
+  private:
+    kl_config cfg_;
+    std::vector<kl_profile> types_;
+    std::map<int, double> solo_;
+    std::map<std::pair<int, int>, Ratio> pair_;
+    std::mutex mu_;
+};
+
+// Workgroups per issue slot that a kernel finishes chip-wide at IPC `ipc`.
+double wg_rate(const kl_profile& p, double ipc, int n_cu);
+
+}  // namespace kl

@@ -1,0 +1,1276 @@
+// Runtime of the sliced co-execution engine: the C ABI of kernelet.h, the
+// kernel registry, the job table, the dispatcher that executes Algorithm 1
+// (Kernelet, Section 4.2) over HIP streams, and the FIFO baseline.
+//
+// Execution model on the GPU.  The runtime owns `lanes` HIP streams (two by
+// default, each on its own hardware queue) plus the FIFO stream.  A
+// co-schedule <K1, K2, b1, b2> puts K1 on one lane and K2 on the other and
+// launches their slices (b_i workgroups per CU, i.e. b_i * n_cu workgroups
+// per slice) back to back, keeping at most `inflight` slices queued per
+// lane.  Consecutive slices of a lane are ordered by the stream; a job that
+// changes lanes, or depends on a job last launched on another lane, first
+// makes the new lane wait on that job's last event.  When one kernel of the
+// pair has launched all its workgroups the co-schedule ends and
+// FindCoSchedule runs again on the pending set, which holds the other
+// kernel's residual (Section 2.2: residuals and new arrivals are
+// re-optimised together).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernelet.h"
+#include "model.hpp"
+
+namespace kl {
+
+thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+bool builtin_check(const char* name, const void* args, uint32_t bytes, kl_dim3* grid,
+                   std::string* err);
+bool is_builtin_fn(const void* fn, const char** name);
+
+static int64_t now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+#define KL_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));         \
+            return KL_EHIP;                                                       \
+        }                                                                         \
+    } while (0)
+
+// ------------------------------------------------------------ event pool
+struct EvPool {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> refs;
+    std::vector<int> free_;
+    int get() {
+        if (free_.empty()) {
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return -1;
+            ev.push_back(e);
+            refs.push_back(0);
+            free_.push_back((int)ev.size() - 1);
+        }
+        int i = free_.back();
+        free_.pop_back();
+        refs[i] = 1;
+        return i;
+    }
+    void ref(int i) {
+        if (i >= 0) ++refs[i];
+    }
+    void unref(int i) {
+        if (i >= 0 && --refs[i] == 0) free_.push_back(i);
+    }
+    void destroy() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        refs.clear();
+        free_.clear();
+    }
+};
+
+// ------------------------------------------------------------- objects
+struct KernelType {
+    std::string name;
+    const void* fn = nullptr;
+    uint32_t block = 256, args_bytes = 0, flags = 0;
+    const char* builtin = nullptr;
+    kl_profile prof{};
+    bool has_prof = false;
+    int static_lds = 0;
+    // launch timing (kernelet_time_kernel)
+    bool timed = false;
+    double time_ms = 0;
+    int64_t time_launches = 0, time_wgs = 0;
+};
+
+// A timed launch waiting for its end event: (start, end, kernel, wgs).
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int type;
+    uint32_t wgs;
+};
+
+enum JobState { J_WAIT_DEP = 0, J_PENDING, J_LAUNCHED, J_DONE, J_CANCELED };
+
+struct Job {
+    kl_job id = -1;
+    int type = -1;
+    kl_dim3 grid{1, 1, 1};
+    uint32_t total = 0, next = 0, fixed_slice = 0;
+    std::vector<uint8_t> args;
+    kl_job after = KL_NO_JOB;
+    uint32_t client = 0;
+    uint64_t footprint = 0;
+    JobState st = J_PENDING;
+    bool admitted = false;
+    int last_lane = -1;
+    int last_ev = -1;  // event pool index (ref held)
+    std::vector<kl_job> dependents;
+    int64_t t_submit = 0, t_start = 0, t_done = 0;
+    bool error = false;
+};
+
+struct Lane {
+    hipStream_t s = nullptr;
+    std::deque<std::pair<int, kl_job>> inflight;  // (event, job)
+    kl_job job = KL_NO_JOB;
+    uint32_t slice = 0;
+    uint32_t dyn_lds = 0;
+    int barrier_ev = -1;  // wait on this before the next launch (solo runs)
+};
+
+}  // namespace kl
+
+struct kl_runtime {
+    int device = 0;
+    kl_config cfg{};
+    std::unique_ptr<kl::Planner> planner;
+    std::vector<kl::KernelType> kernels;
+    std::map<kl_job, kl::Job> jobs;
+    kl_job next_id = 0;
+    std::vector<kl::Lane> lanes;
+    kl::EvPool pool;
+    std::mutex mu;
+    std::condition_variable cv;  // submissions, launches, completions
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    bool worker_running = false;
+    kl_policy worker_policy = KL_POLICY_MARKOV;
+    uint32_t worker_flags = 0;
+    bool scheduling = false;  // a dispatcher loop is active
+    int64_t resident = 0;     // admitted footprint bytes
+    kl_stats stats{};
+    std::vector<kl_decision> declog;
+    int64_t t0_dec = 0;
+    // co-schedule currently issued
+    bool cs_active = false;
+    kl_job cs_job[2] = {KL_NO_JOB, KL_NO_JOB};
+    // launch timing
+    std::deque<kl::TimedLaunch> timed;
+    std::vector<hipEvent_t> tev_free;
+};
+
+namespace kl {
+
+static kl_config defaults() {
+    kl_config c{};
+    c.n_cu = 0;
+    c.wmax = 8;
+    c.vgpr_file = 512;
+    c.lds_cu = 160 * 1024;
+    c.alpha_p = 0.4;
+    c.alpha_m = 0.1;
+    c.use_prune = 1;
+    c.ratio_mode = KL_MODE_CP;
+    c.cp_min = 0.0;
+    c.mem_latency = 400.0;
+    c.beta = 0.0;
+    c.lanes = 2;
+    c.inflight = 2;
+    c.lds_reserve = 0;
+    c.max_slices = 0;
+    c.hbm_budget = 0;
+    c.surrogate_topk = 4;
+    return c;
+}
+
+static kl_status check_cfg(const kl_config& c) {
+    if (c.wmax < 1 || c.wmax > 64 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
+        c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
+        c.beta < 0 || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2) {
+        set_error("invalid kl_config field");
+        return KL_EINVAL;
+    }
+    return KL_OK;
+}
+
+static kl_status check_profile(const kl_profile& p) {
+    if (!(p.r_mem >= 0 && p.r_comp >= 0 && p.r_mem + p.r_comp <= 1.0) || p.mem_req < 0 ||
+        p.lat_mem < 0 || (p.r_comp > 0 && !(p.lat_comp >= 1.0)) || !(p.instr_per_wave > 0) ||
+        p.max_wg_per_cu < 1 || p.waves_per_simd < 1 || p.vgpr < 0 || p.lds_bytes < 0) {
+        set_error("invalid kl_profile field");
+        return KL_EINVAL;
+    }
+    return KL_OK;
+}
+
+// ---------------------------------------------------------- bookkeeping
+// All helpers below run with rt->mu held.
+
+static void release_dependents(kl_runtime* rt, Job& j) {
+    for (kl_job d : j.dependents) {
+        auto it = rt->jobs.find(d);
+        if (it != rt->jobs.end() && it->second.st == J_WAIT_DEP) it->second.st = J_PENDING;
+    }
+}
+
+static void mark_done(kl_runtime* rt, Job& j, bool error) {
+    if (j.st == J_DONE) return;
+    j.st = J_DONE;
+    j.error = error;
+    j.t_done = now_ns();
+    if (j.admitted) rt->resident -= (int64_t)j.footprint;
+    j.admitted = false;
+    rt->stats.jobs_done++;
+}
+
+static hipEvent_t timing_event(kl_runtime* rt) {
+    if (!rt->tev_free.empty()) {
+        hipEvent_t e = rt->tev_free.back();
+        rt->tev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Accumulate the durations of timed launches that have finished.
+static void poll_timed(kl_runtime* rt) {
+    while (!rt->timed.empty()) {
+        TimedLaunch& t = rt->timed.front();
+        if (hipEventQuery(t.b) == hipErrorNotReady) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+            KernelType& kt = rt->kernels[t.type];
+            kt.time_ms += ms;
+            kt.time_launches++;
+            kt.time_wgs += t.wgs;
+        }
+        rt->tev_free.push_back(t.a);
+        rt->tev_free.push_back(t.b);
+        rt->timed.pop_front();
+    }
+}
+
+// Retire finished slices on every lane and finished jobs.
+static void poll_lanes(kl_runtime* rt) {
+    poll_timed(rt);
+    for (auto& ln : rt->lanes) {
+        while (!ln.inflight.empty()) {
+            int e = ln.inflight.front().first;
+            hipError_t q = hipEventQuery(rt->pool.ev[e]);
+            if (q == hipErrorNotReady) break;
+            kl_job jid = ln.inflight.front().second;
+            ln.inflight.pop_front();
+            auto it = rt->jobs.find(jid);
+            if (it != rt->jobs.end()) {
+                Job& j = it->second;
+                if (q != hipSuccess) j.error = true;
+                if (j.st == J_LAUNCHED && j.last_ev == e) {
+                    mark_done(rt, j, q != hipSuccess);
+                    rt->pool.unref(j.last_ev);
+                    j.last_ev = -1;
+                }
+            }
+            rt->pool.unref(e);
+        }
+        if (ln.barrier_ev >= 0 && hipEventQuery(rt->pool.ev[ln.barrier_ev]) == hipSuccess) {
+            rt->pool.unref(ln.barrier_ev);
+            ln.barrier_ev = -1;
+        }
+    }
+}
+
+static uint32_t dyn_lds_for(kl_runtime* rt, const KernelType& kt, int b_total) {
+    if (!rt->cfg.lds_reserve || b_total <= 0) return 0;
+    int64_t per = rt->cfg.lds_cu / b_total - kt.static_lds;
+    int64_t cap = 65536 - kt.static_lds;
+    if (per > cap) per = cap;
+    return per > 0 ? (uint32_t)(per & ~255ll) : 0u;
+}
+
+// Launch the next slice of job `jid` on lane `li`, `count` workgroups.
+static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count) {
+    Lane& ln = rt->lanes[li];
+    Job& j = rt->jobs.at(jid);
+    const KernelType& kt = rt->kernels[j.type];
+    if (count > j.total - j.next) count = j.total - j.next;
+    if (count == 0) return KL_OK;
+    // ordering against work on other lanes
+    if (ln.barrier_ev >= 0) {
+        KL_HIP(hipStreamWaitEvent(ln.s, rt->pool.ev[ln.barrier_ev], 0));
+        rt->pool.unref(ln.barrier_ev);
+        ln.barrier_ev = -1;
+    }
+    if (j.next == 0 && j.after != KL_NO_JOB) {
+        auto it = rt->jobs.find(j.after);
+        if (it != rt->jobs.end() && it->second.st != J_DONE && it->second.last_ev >= 0 &&
+            it->second.last_lane != li)
+            KL_HIP(hipStreamWaitEvent(ln.s, rt->pool.ev[it->second.last_ev], 0));
+    }
+    if (j.last_ev >= 0 && j.last_lane != li)
+        KL_HIP(hipStreamWaitEvent(ln.s, rt->pool.ev[j.last_ev], 0));
+    kl_slice s;
+    s.offset = j.next;
+    s.count = count;
+    s.gx = j.grid.x;
+    s.gy = j.grid.y;
+    s.gz = j.grid.z;
+    s.reserved = 0;
+    void* params[2] = {j.args.data(), &s};
+    hipEvent_t ta = nullptr, tb = nullptr;
+    if (kt.timed) {
+        ta = timing_event(rt);
+        tb = timing_event(rt);
+        if (!ta || !tb) {
+            set_error("hipEventCreate failed");
+            return KL_EHIP;
+        }
+        KL_HIP(hipEventRecord(ta, ln.s));
+    }
+    hipError_t e = hipLaunchKernel(kt.fn, dim3(count), dim3(kt.block), params,
+                                   ln.dyn_lds, ln.s);
+    if (e != hipSuccess) {
+        set_error(std::string("hipLaunchKernel(") + kt.name + "): " + hipGetErrorString(e));
+        j.error = true;
+        return KL_EHIP;
+    }
+    if (kt.timed) {
+        KL_HIP(hipEventRecord(tb, ln.s));
+        rt->timed.push_back({ta, tb, j.type, count});
+    }
+    int ev = rt->pool.get();
+    if (ev < 0) {
+        set_error("hipEventCreate failed");
+        return KL_EHIP;
+    }
+    KL_HIP(hipEventRecord(rt->pool.ev[ev], ln.s));
+    if (j.next == 0) j.t_start = now_ns();
+    j.next += count;
+    rt->stats.slices_launched++;
+    ln.inflight.emplace_back(ev, jid);
+    rt->pool.ref(ev);  // the job's reference
+    rt->pool.unref(j.last_ev);
+    j.last_ev = ev;
+    j.last_lane = li;
+    if (j.next >= j.total) {
+        j.st = J_LAUNCHED;
+        release_dependents(rt, j);
+    }
+    return KL_OK;
+}
+
+// Admission by the memory budget: jobs in submission order while the
+// admitted footprint fits.
+static void admit(kl_runtime* rt) {
+    for (auto& kv : rt->jobs) {
+        Job& j = kv.second;
+        if (j.admitted || j.st == J_DONE || j.st == J_CANCELED) continue;
+        if (rt->cfg.hbm_budget > 0 &&
+            rt->resident + (int64_t)j.footprint > rt->cfg.hbm_budget)
+            break;  // keep submission order: nothing later overtakes
+        j.admitted = true;
+        rt->resident += (int64_t)j.footprint;
+    }
+}
+
+static bool runnable(const Job& j) {
+    return j.admitted && j.st == J_PENDING && j.next < j.total;
+}
+
+static void log_decision(kl_runtime* rt, const Decision& d, uint32_t s1, uint32_t s2,
+                         double us) {
+    kl_decision x{};
+    x.j1 = d.j1;
+    x.j2 = d.j2;
+    x.b1 = d.b1;
+    x.b2 = d.b2;
+    x.slice1 = s1;
+    x.slice2 = s2;
+    x.value = d.value;
+    x.cipc1 = d.cipc1;
+    x.cipc2 = d.cipc2;
+    if (rt->declog.empty() && rt->t0_dec == 0) rt->t0_dec = now_ns();
+    x.t_us = (now_ns() - rt->t0_dec) / 1e3;
+    rt->declog.push_back(x);
+    rt->stats.decisions++;
+    rt->stats.decision_us_total += us;
+}
+
+static uint32_t slice_size(kl_runtime* rt, const Job& j, int b) {
+    if (j.fixed_slice) return j.fixed_slice;
+    uint64_t s = (uint64_t)b * (uint64_t)rt->cfg.n_cu;
+    const KernelType& kt = rt->kernels[j.type];
+    if (kt.has_prof && kt.prof.min_slice_wgs > 0 && s < (uint64_t)kt.prof.min_slice_wgs)
+        s = (uint64_t)kt.prof.min_slice_wgs;
+    if (rt->cfg.max_slices > 0) {
+        uint64_t floor_s = (j.total + rt->cfg.max_slices - 1) / rt->cfg.max_slices;
+        if (s < floor_s) s = floor_s;
+    }
+    return s > 0xffffffffull ? 0xffffffffu : (uint32_t)std::max<uint64_t>(s, 1);
+}
+
+// One step of the FIFO policy: launch every runnable job whole, in id order,
+// stopping at the first job that is not yet runnable.
+static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
+    Lane& ln = rt->lanes[0];
+    ln.dyn_lds = 0;
+    for (auto& kv : rt->jobs) {
+        Job& j = kv.second;
+        if (j.st == J_DONE || j.st == J_CANCELED || j.st == J_LAUNCHED) continue;
+        if (!runnable(j)) break;
+        kl_status s = launch_slice(rt, 0, j.id, j.total - j.next);
+        if (s) return s;
+        *progressed = true;
+    }
+    return KL_OK;
+}
+
+// Choose the next co-schedule (FindCoSchedule) and bind it to lanes.
+static void decide(kl_runtime* rt, kl_policy policy) {
+    std::vector<PendingJob> pend;
+    for (auto& kv : rt->jobs)
+        if (runnable(kv.second)) pend.push_back({kv.first, kv.second.type});
+    rt->cs_active = false;
+    rt->cs_job[0] = rt->cs_job[1] = KL_NO_JOB;
+    if (pend.empty()) {
+        for (auto& ln : rt->lanes) ln.job = KL_NO_JOB;
+        return;
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    Decision d;
+    if (policy == KL_POLICY_FIXED) {
+        // the two earliest jobs of different kernel types, their own plans
+        std::sort(pend.begin(), pend.end(),
+                  [](const PendingJob& a, const PendingJob& b) { return a.id < b.id; });
+        d.j1 = pend[0].id;
+        d.b1 = 1;
+        for (auto& p : pend)
+            if (p.type != pend[0].type) {
+                d.j2 = p.id;
+                d.b2 = 1;
+                break;
+            }
+    } else {
+        d = rt->planner->find(pend);
+    }
+    double us = std::chrono::duration<double, std::micro>(
+                    std::chrono::steady_clock::now() - t0).count();
+    rt->stats.model_us_total = rt->planner->model_us;
+    rt->stats.cache_hits = rt->planner->cache_hits;
+
+    kl_job want[2] = {d.j1, d.j2};
+    int lane_of[2] = {-1, -1};
+    const int nl = std::min<int>((int)rt->lanes.size(), 2);
+    for (int k = 0; k < 2; ++k)
+        for (int li = 0; li < nl; ++li)
+            if (want[k] != KL_NO_JOB && rt->lanes[li].job == want[k]) lane_of[k] = li;
+    for (int k = 0; k < 2; ++k) {
+        if (want[k] == KL_NO_JOB || lane_of[k] >= 0) continue;
+        int best = -1;
+        for (int li = 0; li < nl; ++li) {
+            if (li == lane_of[0] || li == lane_of[1]) continue;
+            if (best < 0 || rt->lanes[li].inflight.size() < rt->lanes[best].inflight.size())
+                best = li;
+        }
+        lane_of[k] = best;
+    }
+    for (int li = 0; li < (int)rt->lanes.size(); ++li)
+        if (li != lane_of[0] && li != lane_of[1]) rt->lanes[li].job = KL_NO_JOB;
+
+    uint32_t sl[2] = {0, 0};
+    const bool solo = d.j2 == KL_NO_JOB || lane_of[1] < 0;
+    for (int k = 0; k < 2; ++k) {
+        if (want[k] == KL_NO_JOB || lane_of[k] < 0) continue;
+        Job& j = rt->jobs.at(want[k]);
+        Lane& ln = rt->lanes[lane_of[k]];
+        ln.job = want[k];
+        const KernelType& kt = rt->kernels[j.type];
+        if (solo) {
+            // a co-schedule of one kernel: its residual in one launch at full
+            // occupancy; the other lanes wait for it before their next launch
+            sl[k] = j.fixed_slice ? j.fixed_slice : j.total - j.next;
+            ln.dyn_lds = 0;
+        } else {
+            sl[k] = slice_size(rt, j, k == 0 ? d.b1 : d.b2);
+            ln.dyn_lds = dyn_lds_for(rt, kt, d.b1 + d.b2);
+        }
+        ln.slice = sl[k];
+        rt->cs_job[k] = want[k];
+    }
+    rt->cs_active = true;
+    log_decision(rt, d, sl[0], sl[1], us);
+}
+
+// One step of Algorithm 1: decide if needed, then fill the lanes' queues.
+static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed) {
+    bool ended = !rt->cs_active;
+    for (int k = 0; k < 2 && !ended; ++k) {
+        kl_job id = rt->cs_job[k];
+        if (id == KL_NO_JOB) continue;
+        auto it = rt->jobs.find(id);
+        if (it == rt->jobs.end() || it->second.next >= it->second.total ||
+            it->second.st == J_CANCELED)
+            ended = true;
+    }
+    if (ended) {
+        decide(rt, policy);
+        if (!rt->cs_active) return KL_OK;
+        *progressed = true;
+    }
+    const bool solo = rt->cs_job[1] == KL_NO_JOB;
+    for (int li = 0; li < (int)rt->lanes.size(); ++li) {
+        Lane& ln = rt->lanes[li];
+        if (ln.job == KL_NO_JOB) continue;
+        Job& j = rt->jobs.at(ln.job);
+        while ((int)ln.inflight.size() < rt->cfg.inflight && j.next < j.total) {
+            kl_status s = launch_slice(rt, li, j.id, ln.slice);
+            if (s) return s;
+            *progressed = true;
+            if (solo && j.next >= j.total) {
+                // later launches on the other lanes start after this run
+                for (int o = 0; o < (int)rt->lanes.size(); ++o) {
+                    if (o == li) continue;
+                    rt->pool.unref(rt->lanes[o].barrier_ev);
+                    rt->lanes[o].barrier_ev = j.last_ev;
+                    rt->pool.ref(j.last_ev);
+                }
+            }
+        }
+        if (j.next >= j.total) {
+            ln.job = KL_NO_JOB;
+            rt->cs_active = false;  // one kernel ran out: decide again
+        }
+    }
+    return KL_OK;
+}
+
+static bool all_launched(kl_runtime* rt) {
+    for (auto& kv : rt->jobs) {
+        const Job& j = kv.second;
+        if (j.st == J_WAIT_DEP || j.st == J_PENDING) return false;
+    }
+    return true;
+}
+
+static bool any_inflight(kl_runtime* rt) {
+    for (auto& ln : rt->lanes)
+        if (!ln.inflight.empty()) return true;
+    return false;
+}
+
+// The dispatcher loop.  Blocking: until every job is launched.  Worker:
+// until stop.
+static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
+                          bool wait_done) {
+    std::unique_lock<std::mutex> lk(rt->mu);
+    rt->scheduling = true;
+    rt->cs_active = false;
+    kl_status st = KL_OK;
+    while (!rt->stop.load()) {
+        poll_lanes(rt);
+        admit(rt);
+        bool progressed = false;
+        st = policy == KL_POLICY_FIFO ? fifo_step(rt, &progressed)
+                                      : markov_step(rt, policy, &progressed);
+        if (st) break;
+        if (progressed) {
+            rt->cv.notify_all();
+            continue;
+        }
+        if (blocking && all_launched(rt) && (!wait_done || !any_inflight(rt))) break;
+        bool waiting_budget = false;
+        for (auto& kv : rt->jobs)
+            if (!kv.second.admitted && kv.second.st != J_DONE && kv.second.st != J_CANCELED)
+                waiting_budget = true;
+        if (blocking && !any_inflight(rt) && !waiting_budget) {
+            // nothing in flight and nothing runnable: jobs wait on deps that
+            // can never be released (e.g. a cancelled predecessor)
+            bool runnable_any = false;
+            for (auto& kv : rt->jobs) runnable_any |= runnable(kv.second);
+            if (!runnable_any) {
+                set_error("kernelet_schedule: jobs wait on dependencies that cannot finish");
+                st = KL_ESTATE;
+                break;
+            }
+        }
+        // nothing to do now: wait for a slice to finish or a submission
+        rt->cv.wait_for(lk, std::chrono::microseconds(any_inflight(rt) ? 5 : 200));
+    }
+    poll_lanes(rt);
+    rt->scheduling = false;
+    rt->cv.notify_all();
+    return st;
+}
+
+}  // namespace kl
+
+using namespace kl;
+
+// ================================================================= C ABI
+extern "C" {
+
+const char* kernelet_last_error(void) { return g_err.c_str(); }
+
+kl_status kernelet_default_config(kl_config* cfg) {
+    if (!cfg) {
+        set_error("null cfg");
+        return KL_EINVAL;
+    }
+    *cfg = defaults();
+    return KL_OK;
+}
+
+kl_status kernelet_init(kl_runtime** out, int hip_device, const kl_config* cfg) {
+    if (!out) {
+        set_error("kernelet_init: null out");
+        return KL_EINVAL;
+    }
+    *out = nullptr;
+    kl_config c = cfg ? *cfg : defaults();
+    if (kl_status s = check_cfg(c)) return s;
+    int ndev = 0;
+    KL_HIP(hipGetDeviceCount(&ndev));
+    if (hip_device < 0 || hip_device >= ndev) {
+        set_error("kernelet_init: no such HIP device");
+        return KL_EINVAL;
+    }
+    KL_HIP(hipSetDevice(hip_device));
+    hipDeviceProp_t prop;
+    KL_HIP(hipGetDeviceProperties(&prop, hip_device));
+    if (c.n_cu == 0) c.n_cu = prop.multiProcessorCount;
+    auto rt = std::make_unique<kl_runtime>();
+    rt->device = hip_device;
+    rt->cfg = c;
+    rt->planner = std::make_unique<Planner>(c);
+    rt->lanes.resize(c.lanes);
+    for (auto& ln : rt->lanes) KL_HIP(hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking));
+    *out = rt.release();
+    return KL_OK;
+}
+
+kl_status kernelet_shutdown(kl_runtime* rt) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    rt->stop = true;
+    rt->cv.notify_all();
+    if (rt->worker.joinable()) rt->worker.join();
+    (void)hipSetDevice(rt->device);
+    for (auto& ln : rt->lanes) {
+        if (ln.s) (void)hipStreamSynchronize(ln.s);
+    }
+    for (auto& ln : rt->lanes)
+        if (ln.s) (void)hipStreamDestroy(ln.s);
+    rt->pool.destroy();
+    for (auto& t : rt->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : rt->tev_free) (void)hipEventDestroy(e);
+    delete rt;
+    return KL_OK;
+}
+
+kl_status kernelet_register(kl_runtime* rt, const kl_kernel_desc* d, kl_kernel* out) {
+    if (!rt || !d || !out || !d->name || !d->host_fn) {
+        set_error("kernelet_register: null argument");
+        return KL_EINVAL;
+    }
+    if (d->block_threads == 0 || d->block_threads % 256 || d->block_threads > 1024 ||
+        d->args_bytes == 0 || d->args_bytes > 256) {
+        set_error("kernelet_register: block_threads must be 256, 512, 768 or 1024 and "
+                  "args_bytes in [1, 256]");
+        return KL_EINVAL;
+    }
+    if (d->profile) {
+        if (kl_status s = check_profile(*d->profile)) return s;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    for (auto& k : rt->kernels)
+        if (k.name == d->name) {
+            set_error(std::string("kernelet_register: duplicate name ") + d->name);
+            return KL_EEXIST;
+        }
+    KernelType kt;
+    kt.name = d->name;
+    kt.fn = d->host_fn;
+    kt.block = d->block_threads;
+    kt.args_bytes = d->args_bytes;
+    kt.flags = d->flags;
+    const char* bn = nullptr;
+    if (is_builtin_fn(d->host_fn, &bn)) kt.builtin = bn;
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, d->host_fn) == hipSuccess)
+        kt.static_lds = (int)attr.sharedSizeBytes;
+    if (d->profile) {
+        kt.prof = *d->profile;
+        kt.has_prof = true;
+        rt->planner->set_type((int)rt->kernels.size(), kt.prof);
+    }
+    rt->kernels.push_back(kt);
+    *out = (kl_kernel)(rt->kernels.size() - 1);
+    return KL_OK;
+}
+
+kl_status kernelet_set_profile(kl_runtime* rt, kl_kernel k, const kl_profile* p) {
+    if (!rt || !p) {
+        set_error("kernelet_set_profile: null argument");
+        return KL_EINVAL;
+    }
+    if (kl_status s = check_profile(*p)) return s;
+    std::lock_guard<std::mutex> g(rt->mu);
+    if (k < 0 || k >= (int)rt->kernels.size()) {
+        set_error("kernelet_set_profile: unknown kernel");
+        return KL_ENOTFOUND;
+    }
+    rt->kernels[k].prof = *p;
+    rt->kernels[k].has_prof = true;
+    rt->planner->set_type(k, *p);
+    return KL_OK;
+}
+
+kl_status kernelet_get_profile(kl_runtime* rt, kl_kernel k, kl_profile* p) {
+    if (!rt || !p) {
+        set_error("kernelet_get_profile: null argument");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    if (k < 0 || k >= (int)rt->kernels.size() || !rt->kernels[k].has_prof) {
+        set_error("kernelet_get_profile: unknown kernel or no profile");
+        return KL_ENOTFOUND;
+    }
+    *p = rt->kernels[k].prof;
+    return KL_OK;
+}
+
+kl_status kernelet_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid, const void* args,
+                          uint32_t args_bytes, kl_job after, uint32_t client,
+                          uint64_t footprint, kl_job* out) {
+    if (!rt || !args || !out) {
+        set_error("kernelet_submit: null argument");
+        return KL_EINVAL;
+    }
+    std::unique_lock<std::mutex> lk(rt->mu);
+    if (k < 0 || k >= (int)rt->kernels.size()) {
+        set_error("kernelet_submit: unknown kernel");
+        return KL_ENOTFOUND;
+    }
+    const KernelType& kt = rt->kernels[k];
+    if (args_bytes != kt.args_bytes) {
+        set_error("kernelet_submit: args_bytes differs from the registered size");
+        return KL_EINVAL;
+    }
+    uint64_t total = (uint64_t)grid.x * grid.y * grid.z;
+    if (total == 0 || total > 0xffffffffull) {
+        set_error("kernelet_submit: grid must hold 1 .. 2^32-1 workgroups");
+        return KL_EINVAL;
+    }
+    if (kt.builtin) {
+        kl_dim3 need;
+        std::string err;
+        if (!builtin_check(kt.builtin, args, args_bytes, &need, &err)) {
+            set_error(std::string("kernelet_submit(") + kt.builtin + "): " + err);
+            return KL_EINVAL;
+        }
+        if (need.x != grid.x || need.y != grid.y || need.z != grid.z) {
+            set_error(std::string("kernelet_submit(") + kt.builtin +
+                      "): grid differs from the grid the arguments need");
+            return KL_EINVAL;
+        }
+    }
+    if (rt->cfg.hbm_budget > 0 && (int64_t)footprint > rt->cfg.hbm_budget) {
+        set_error("kernelet_submit: footprint exceeds the whole memory budget");
+        return KL_ENOMEM;
+    }
+    Job j;
+    j.id = rt->next_id;
+    j.type = k;
+    j.grid = grid;
+    j.total = (uint32_t)total;
+    j.args.assign((const uint8_t*)args, (const uint8_t*)args + args_bytes);
+    j.client = client;
+    j.footprint = footprint;
+    j.t_submit = now_ns();
+    j.after = after;
+    j.st = J_PENDING;
+    if (after != KL_NO_JOB) {
+        auto it = rt->jobs.find(after);
+        if (it == rt->jobs.end()) {
+            set_error("kernelet_submit: unknown `after` job");
+            return KL_ENOTFOUND;
+        }
+        Job& p = it->second;
+        if (p.st == J_CANCELED) {
+            set_error("kernelet_submit: `after` job was cancelled");
+            return KL_ECANCELED;
+        }
+        if (p.st == J_WAIT_DEP || p.st == J_PENDING) {
+            j.st = J_WAIT_DEP;
+            p.dependents.push_back(j.id);
+        }
+    }
+    rt->next_id++;
+    rt->jobs.emplace(j.id, std::move(j));
+    rt->stats.jobs_submitted++;
+    *out = rt->next_id - 1;
+    lk.unlock();
+    rt->cv.notify_all();
+    return KL_OK;
+}
+
+kl_status kernelet_slice(kl_runtime* rt, kl_job jid, uint32_t wgs, uint32_t* n_slices) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    auto it = rt->jobs.find(jid);
+    if (it == rt->jobs.end()) {
+        set_error("kernelet_slice: unknown job");
+        return KL_ENOTFOUND;
+    }
+    Job& j = it->second;
+    if (j.next > 0 || j.st == J_LAUNCHED || j.st == J_DONE || j.st == J_CANCELED) {
+        set_error("kernelet_slice: job already started");
+        return KL_ESTATE;
+    }
+    if (wgs == 0) {
+        const KernelType& kt = rt->kernels[j.type];
+        wgs = kt.has_prof && kt.prof.min_slice_wgs > 0 ? (uint32_t)kt.prof.min_slice_wgs
+                                                        : j.total;
+    }
+    j.fixed_slice = std::min(wgs, j.total);
+    if (n_slices) *n_slices = (j.total + j.fixed_slice - 1) / j.fixed_slice;
+    return KL_OK;
+}
+
+kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    if (policy < KL_POLICY_FIFO || policy > KL_POLICY_FIXED) {
+        set_error("kernelet_schedule: unknown policy");
+        return KL_EINVAL;
+    }
+    {
+        std::lock_guard<std::mutex> g(rt->mu);
+        if (rt->scheduling || rt->worker_running) {
+            set_error("kernelet_schedule: a scheduler is already running");
+            return KL_ESTATE;
+        }
+        if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED) {
+            for (auto& kv : rt->jobs) {
+                const Job& j = kv.second;
+                if ((j.st == J_PENDING || j.st == J_WAIT_DEP) && !rt->kernels[j.type].has_prof) {
+                    set_error("kernelet_schedule: kernel " + rt->kernels[j.type].name +
+                              " has no profile");
+                    return KL_ESTATE;
+                }
+            }
+        }
+        rt->scheduling = true;  // reserve against a concurrent call
+    }
+    KL_HIP(hipSetDevice(rt->device));
+    if (flags & KL_BLOCKING) {
+        {
+            std::lock_guard<std::mutex> g(rt->mu);
+            rt->scheduling = false;
+        }
+        return dispatch(rt, policy, true, (flags & KL_WAIT_DONE) != 0);
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    rt->scheduling = false;
+    rt->worker_running = true;
+    rt->worker_policy = policy;
+    rt->worker_flags = flags;
+    rt->worker = std::thread([rt, policy]() {
+        (void)hipSetDevice(rt->device);
+        dispatch(rt, policy, false, false);
+    });
+    return KL_OK;
+}
+
+kl_status kernelet_wait(kl_runtime* rt, kl_job jid, int64_t timeout_ns) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    const int64_t deadline = timeout_ns < 0 ? INT64_MAX : now_ns() + timeout_ns;
+    std::unique_lock<std::mutex> lk(rt->mu);
+    for (;;) {
+        auto it = rt->jobs.find(jid);
+        if (it == rt->jobs.end()) {
+            set_error("kernelet_wait: unknown job");
+            return KL_ENOTFOUND;
+        }
+        Job& j = it->second;
+        if (j.st == J_CANCELED) return KL_ECANCELED;
+        if (j.st == J_DONE) {
+            if (j.error) {
+                set_error("kernelet_wait: a slice of the job failed on the device");
+                return KL_EHIP;
+            }
+            return KL_OK;
+        }
+        if (j.st == J_LAUNCHED && j.last_ev >= 0) {
+            hipError_t q = hipEventQuery(rt->pool.ev[j.last_ev]);
+            if (q != hipErrorNotReady) {
+                mark_done(rt, j, q != hipSuccess);
+                rt->pool.unref(j.last_ev);
+                j.last_ev = -1;
+                continue;
+            }
+        }
+        if (now_ns() >= deadline) {
+            set_error("kernelet_wait: timed out");
+            return KL_ETIMEOUT;
+        }
+        rt->cv.wait_for(lk, std::chrono::microseconds(20));
+    }
+}
+
+kl_status kernelet_synchronize(kl_runtime* rt) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    KL_HIP(hipSetDevice(rt->device));
+    for (auto& ln : rt->lanes) KL_HIP(hipStreamSynchronize(ln.s));
+    std::lock_guard<std::mutex> g(rt->mu);
+    poll_lanes(rt);
+    for (auto& kv : rt->jobs) {
+        Job& j = kv.second;
+        if (j.st == J_LAUNCHED) {
+            mark_done(rt, j, false);
+            rt->pool.unref(j.last_ev);
+            j.last_ev = -1;
+        }
+    }
+    return KL_OK;
+}
+
+kl_status kernelet_cancel(kl_runtime* rt, kl_job jid) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    auto it = rt->jobs.find(jid);
+    if (it == rt->jobs.end()) {
+        set_error("kernelet_cancel: unknown job");
+        return KL_ENOTFOUND;
+    }
+    Job& j = it->second;
+    if (j.next > 0 || j.st == J_LAUNCHED || j.st == J_DONE) {
+        set_error("kernelet_cancel: job already started");
+        return KL_ESTATE;
+    }
+    if (j.admitted) rt->resident -= (int64_t)j.footprint;
+    j.admitted = false;
+    j.st = J_CANCELED;
+    // dependants can never run: cancel them too
+    std::vector<kl_job> todo = j.dependents;
+    while (!todo.empty()) {
+        kl_job d = todo.back();
+        todo.pop_back();
+        auto dt = rt->jobs.find(d);
+        if (dt == rt->jobs.end() || dt->second.st == J_CANCELED) continue;
+        if (dt->second.admitted) rt->resident -= (int64_t)dt->second.footprint;
+        dt->second.admitted = false;
+        dt->second.st = J_CANCELED;
+        for (kl_job x : dt->second.dependents) todo.push_back(x);
+    }
+    rt->cv.notify_all();
+    return KL_OK;
+}
+
+kl_status kernelet_job_times(kl_runtime* rt, kl_job jid, int64_t* ts, int64_t* tb,
+                             int64_t* td) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    auto it = rt->jobs.find(jid);
+    if (it == rt->jobs.end()) {
+        set_error("kernelet_job_times: unknown job");
+        return KL_ENOTFOUND;
+    }
+    if (ts) *ts = it->second.t_submit;
+    if (tb) *tb = it->second.t_start;
+    if (td) *td = it->second.t_done;
+    return KL_OK;
+}
+
+kl_status kernelet_reap(kl_runtime* rt) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    for (auto it = rt->jobs.begin(); it != rt->jobs.end();) {
+        Job& j = it->second;
+        if (j.st == J_DONE || j.st == J_CANCELED) {
+            rt->pool.unref(j.last_ev);
+            it = rt->jobs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return KL_OK;
+}
+
+kl_status kernelet_time_kernel(kl_runtime* rt, kl_kernel k, int32_t enable) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    if (k < 0 || k >= (int)rt->kernels.size()) {
+        set_error("kernelet_time_kernel: unknown kernel");
+        return KL_ENOTFOUND;
+    }
+    KernelType& kt = rt->kernels[k];
+    kt.timed = enable != 0;
+    if (kt.timed) {
+        kt.time_ms = 0;
+        kt.time_launches = 0;
+        kt.time_wgs = 0;
+    }
+    return KL_OK;
+}
+
+kl_status kernelet_kernel_time(kl_runtime* rt, kl_kernel k, double* total_ms,
+                               int64_t* launches, int64_t* workgroups) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    if (k < 0 || k >= (int)rt->kernels.size()) {
+        set_error("kernelet_kernel_time: unknown kernel");
+        return KL_ENOTFOUND;
+    }
+    (void)hipSetDevice(rt->device);
+    poll_timed(rt);
+    const KernelType& kt = rt->kernels[k];
+    if (total_ms) *total_ms = kt.time_ms;
+    if (launches) *launches = kt.time_launches;
+    if (workgroups) *workgroups = kt.time_wgs;
+    return KL_OK;
+}
+
+kl_status kernelet_stats(kl_runtime* rt, kl_stats* out) {
+    if (!rt || !out) {
+        set_error("null argument");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    *out = rt->stats;
+    return KL_OK;
+}
+
+kl_status kernelet_decisions(kl_runtime* rt, kl_decision* out, int32_t max, int32_t* n) {
+    if (!rt || !n || (max > 0 && !out)) {
+        set_error("null argument");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    int32_t c = std::min<int32_t>(max, (int32_t)rt->declog.size());
+    for (int32_t i = 0; i < c; ++i) out[i] = rt->declog[i];
+    *n = c;
+    rt->declog.clear();
+    return KL_OK;
+}
+
+// ------------------------------------------------------------ host model
+kl_status kernelet_predict(const kl_config* cfg, const kl_profile* p1, const kl_profile* p2,
+                           int32_t w1, int32_t w2, double* ipc1, double* ipc2, double* cp) {
+    if (!p1 || (w2 > 0 && !p2) || w1 < 0 || w2 < 0 || w1 + w2 < 1 || w1 > 16 || w2 > 16) {
+        set_error("kernelet_predict: bad profile or wave counts");
+        return KL_EINVAL;
+    }
+    kl_config c = cfg ? *cfg : defaults();
+    if (kl_status s = check_cfg(c)) return s;
+    if (kl_status s = check_profile(*p1)) return s;
+    if (p2)
+        if (kl_status s = check_profile(*p2)) return s;
+    double out[2] = {0, 0};
+    if (w2 == 0 || w1 == 0) {
+        const kl_profile& p = w1 ? *p1 : *p2;
+        int w = w1 ? w1 : w2;
+        KernelModel km = kernel_model(p, c);
+        double v;
+        chain_ipc(&km, &w, 1, c.beta, &v);
+        out[w1 ? 0 : 1] = v;
+    } else {
+        KernelModel km[2] = {kernel_model(*p1, c), kernel_model(*p2, c)};
+        int w[2] = {w1, w2};
+        chain_ipc(km, w, 2, c.beta, out);
+    }
+    if (ipc1) *ipc1 = out[0];
+    if (ipc2) *ipc2 = out[1];
+    if (cp) {
+        double solo[2] = {solo_ipc(*p1, c), p2 ? solo_ipc(*p2, c) : 1.0};
+        int n = 0;
+        double ci[2], si[2];
+        if (w1 > 0) ci[n] = out[0], si[n++] = solo[0];
+        if (w2 > 0) ci[n] = out[1], si[n++] = solo[1];
+        *cp = cp_value(ci, si, n);
+    }
+    return KL_OK;
+}
+
+kl_status kernelet_best_ratio(const kl_config* cfg, const kl_profile* p1, const kl_profile* p2,
+                              int32_t* b1, int32_t* b2, double* value, double* c1,
+                              double* c2) {
+    if (!p1 || !p2) {
+        set_error("kernelet_best_ratio: null profile");
+        return KL_EINVAL;
+    }
+    kl_config c = cfg ? *cfg : defaults();
+    if (kl_status s = check_cfg(c)) return s;
+    if (kl_status s = check_profile(*p1)) return s;
+    if (kl_status s = check_profile(*p2)) return s;
+    Ratio r = best_ratio(*p1, *p2, c);
+    if (!r.ok) {
+        set_error("kernelet_best_ratio: no feasible ratio");
+        return KL_ENOTFOUND;
+    }
+    if (b1) *b1 = r.b1;
+    if (b2) *b2 = r.b2;
+    if (value) *value = r.value;
+    if (c1) *c1 = r.cipc1;
+    if (c2) *c2 = r.cipc2;
+    return KL_OK;
+}
+
+kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
+                            int32_t n_profiles, const int32_t* job_profile,
+                            const uint64_t* job_wgs, const double* job_arrival,
+                            int32_t n_jobs, kl_policy policy, kl_decision* dec,
+                            int32_t max_dec, int32_t* n_dec, double* makespan, double* done) {
+    if (!profiles || n_profiles < 1 || !job_profile || !job_wgs || n_jobs < 0 ||
+        (n_jobs > 0 && !done) || !makespan) {
+        set_error("kernelet_simulate: null argument");
+        return KL_EINVAL;
+    }
+    kl_config c = cfg ? *cfg : defaults();
+    if (c.n_cu == 0) c.n_cu = 256;
+    if (kl_status s = check_cfg(c)) return s;
+    std::vector<kl_profile> types(profiles, profiles + n_profiles);
+    for (auto& p : types)
+        if (kl_status s = check_profile(p)) return s;
+    for (int i = 0; i < n_jobs; ++i)
+        if (job_profile[i] < 0 || job_profile[i] >= n_profiles || job_wgs[i] == 0) {
+            set_error("kernelet_simulate: bad job");
+            return KL_EINVAL;
+        }
+    Planner pl(c);
+    pl.set_types(types);
+    auto arrival = [&](int i) { return job_arrival ? job_arrival[i] : 0.0; };
+    int nd = 0;
+    double t = 0.0;
+    if (policy == KL_POLICY_FIFO) {
+        for (int i = 0; i < n_jobs; ++i) {
+            t = std::max(t, arrival(i));
+            const kl_profile& p = types[job_profile[i]];
+            t += (double)job_wgs[i] / wg_rate(p, pl.solo(job_profile[i]), c.n_cu);
+            done[i] = t;
+        }
+        *makespan = t;
+        if (n_dec) *n_dec = 0;
+        return KL_OK;
+    }
+    const double kEps = 1e-6;
+    std::vector<double> rem(n_jobs);
+    std::vector<char> fin(n_jobs, 0);
+    for (int i = 0; i < n_jobs; ++i) rem[i] = (double)job_wgs[i];
+    int ndone = 0;
+    while (ndone < n_jobs) {
+        std::vector<PendingJob> pend;
+        for (int i = 0; i < n_jobs; ++i)
+            if (!fin[i] && arrival(i) <= t) pend.push_back({i, job_profile[i]});
+        if (pend.empty()) {
+            double nt = 1e300;
+            for (int i = 0; i < n_jobs; ++i)
+                if (!fin[i]) nt = std::min(nt, arrival(i));
+            t = nt;
+            continue;
+        }
+        Decision d = pl.find(pend);
+        if (dec && nd < max_dec) {
+            kl_decision& x = dec[nd];
+            x = kl_decision{};
+            x.j1 = d.j1;
+            x.j2 = d.j2;
+            x.b1 = d.b1;
+            x.b2 = d.b2;
+            x.value = d.value;
+            x.cipc1 = d.cipc1;
+            x.cipc2 = d.cipc2;
+            x.t_us = t;
+        }
+        ++nd;
+        int a = (int)d.j1;
+        const kl_profile& pa = types[job_profile[a]];
+        if (d.j2 < 0) {
+            t += rem[a] / wg_rate(pa, d.cipc1, c.n_cu);
+            rem[a] = 0;
+            fin[a] = 1;
+            done[a] = t;
+            ++ndone;
+            continue;
+        }
+        int b = (int)d.j2;
+        const kl_profile& pb = types[job_profile[b]];
+        double r1 = wg_rate(pa, d.cipc1, c.n_cu), r2 = wg_rate(pb, d.cipc2, c.n_cu);
+        double t1 = rem[a] / r1, t2 = rem[b] / r2;
+        double dt = std::min(t1, t2);
+        t += dt;
+        if (t1 <= t2) {
+            rem[b] -= dt * r2;
+            rem[a] = 0;
+            fin[a] = 1;
+            done[a] = t;
+            ++ndone;
+            if (rem[b] <= kEps) {
+                rem[b] = 0;
+                fin[b] = 1;
+                done[b] = t;
+                ++ndone;
+            }
+        } else {
+            rem[a] -= dt * r1;
+            rem[b] = 0;
+            fin[b] = 1;
+            done[b] = t;
+            ++ndone;
+            if (rem[a] <= kEps) {
+                rem[a] = 0;
+                fin[a] = 1;
+                done[a] = t;
+                ++ndone;
+            }
+        }
+    }
+    *makespan = t;
+    if (n_dec) *n_dec = nd;
+    return KL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,481 @@
+// The eight sliceable workload kernels of the co-execution mix, for gfx950.
+//
+// Every kernel is launched on a 1-D grid of slice.count workgroups of 256
+// threads and recovers its workgroup's id in the original grid as
+// slice.offset + blockIdx.x (index rectification, Kernelet Section 4.1).
+// Nothing here reads gridDim.  Argument blocks are declared in
+// kernelet_workloads.h; the host-side checks of each block and the original
+// grid it needs are at the end of this file.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "kernelet.h"
+#include "kernelet_workloads.h"
+
+#define KL_WG 256
+
+__device__ __forceinline__ uint32_t kl_wg_linear(const kl_slice& s) {
+    return s.offset + blockIdx.x;
+}
+
+// ------------------------------------------------------------------ poly
+// Horner's rule, one fma per coefficient from the highest degree down; the
+// coefficient index is uniform across the wave, so coefficients come through
+// scalar loads.
+__global__ __launch_bounds__(KL_WG) void kl_poly(kl_poly_args a, kl_slice s) {
+    uint64_t t = (uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x;
+    if (t >= a.n) return;
+    const float x = a.x[t];
+    const float* __restrict__ c = a.coef;
+    int k = (int)a.ncoef - 1;
+    float acc = c[k];
+#pragma unroll 16
+    for (--k; k >= 0; --k) acc = __builtin_fmaf(acc, x, c[k]);
+    a.y[t] = acc;
+}
+
+// ---------------------------------------------------------------- gather
+__global__ __launch_bounds__(KL_WG) void kl_gather(kl_gather_args a, kl_slice s) {
+    uint64_t t = (uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x;
+    if (t >= a.n) return;
+    int32_t i = a.idx[t];
+    a.out[t] = (uint32_t)i < a.table_n ? a.table[i] : 0;
+}
+
+// ----------------------------------------------------------------- sgemm
+// 128 x 128 output tile per workgroup, K staged through LDS 16 at a time;
+// each of the 4 waves owns a 64 x 64 quadrant computed as 2 x 2 blocks of
+// v_mfma_f32_32x32x2f32 (A: lane l holds A[l%32][l/32]; B: lane l holds
+// B[l/32][l%32]; D register r of lane l is D[8(r/4) + 4(l/32) + r%4][l%32]).
+// The next K-panel is prefetched into registers while the current one is
+// multiplied.  Tiles are assigned XCD by XCD: workgroup i runs on XCD i % 8,
+// so each XCD gets a compact block of tiles that share A rows and B
+// columns in its own L2.
+typedef float kl_f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void sgemm_tile(uint32_t lin, uint32_t tm, uint32_t tn,
+                                           uint32_t* ti, uint32_t* tj) {
+    if (tm % 2 == 0 && tn % 4 == 0) {
+        uint32_t xcd = lin % 8, j = lin / 8;
+        uint32_t rh = tm / 2, rw = tn / 4;
+        *ti = (xcd / 4) * rh + j / rw;
+        *tj = (xcd % 4) * rw + j % rw;
+    } else {
+        *ti = lin / tn;
+        *tj = lin % tn;
+    }
+}
+
+__global__ __launch_bounds__(KL_WG) void kl_sgemm(kl_sgemm_args a, kl_slice s) {
+    constexpr int BM = 128, BN = 128, BK = 16, PAD = 4;
+    __shared__ float As[BK][BM + PAD];
+    __shared__ float Bs[BK][BN + PAD];
+    const uint32_t tm = a.m / BM, tn = a.n / BN;
+    const uint32_t lin = kl_wg_linear(s);
+    if (lin >= tm * tn) return;
+    uint32_t ti, tj;
+    sgemm_tile(lin, tm, tn, &ti, &tj);
+
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int wm = (wave / 2) * 64, wn = (wave % 2) * 64;
+    const float* __restrict__ A = a.a + (size_t)ti * BM * a.k;
+    const float* __restrict__ B = a.b + (size_t)tj * BN;
+    const uint32_t K = a.k, N = a.n;
+
+    kl_f32x16 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    // global -> register mapping of one K-panel
+    const int ar = tid / 4, ac = (tid % 4) * 4;     // A: rows ar, ar+64
+    const int br = tid / 32, bc = (tid % 32) * 4;   // B: rows br, br+8
+    const float* pa0 = A + (size_t)ar * K + ac;
+    const float* pa1 = A + (size_t)(ar + 64) * K + ac;
+    const float* pb0 = B + (size_t)br * N + bc;
+    const float* pb1 = B + (size_t)(br + 8) * N + bc;
+    float4 ra0 = *(const float4*)pa0, ra1 = *(const float4*)pa1;
+    float4 rb0 = *(const float4*)pb0, rb1 = *(const float4*)pb1;
+    for (uint32_t k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        As[ac + 0][ar] = ra0.x;
+        As[ac + 1][ar] = ra0.y;
+        As[ac + 2][ar] = ra0.z;
+        As[ac + 3][ar] = ra0.w;
+        As[ac + 0][ar + 64] = ra1.x;
+        As[ac + 1][ar + 64] = ra1.y;
+        As[ac + 2][ar + 64] = ra1.z;
+        As[ac + 3][ar + 64] = ra1.w;
+        *(float4*)&Bs[br][bc] = rb0;
+        *(float4*)&Bs[br + 8][bc] = rb1;
+        __syncthreads();
+        if (k0 + BK < K) {
+            const size_t kn = k0 + BK;
+            ra0 = *(const float4*)(pa0 + kn);
+            ra1 = *(const float4*)(pa1 + kn);
+            rb0 = *(const float4*)(pb0 + kn * N);
+            rb1 = *(const float4*)(pb1 + kn * N);
+        }
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 2) {
+            const int kr = kk + lane / 32, lc = lane % 32;
+            float av0 = As[kr][wm + lc], av1 = As[kr][wm + 32 + lc];
+            float bv0 = Bs[kr][wn + lc], bv1 = Bs[kr][wn + 32 + lc];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0, bv0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av0, bv1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1, bv0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av1, bv1, acc[1][1], 0, 0, 0);
+        }
+    }
+    float* __restrict__ C = a.c + (size_t)ti * BM * N + (size_t)tj * BN;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 16; ++r) {
+                const int row = wm + 32 * i + 8 * (r / 4) + 4 * (lane / 32) + (r % 4);
+                const int col = wn + 32 * j + lane % 32;
+                C[(size_t)row * N + col] = acc[i][j][r];
+            }
+}
+
+// ------------------------------------------------------------------ spmv
+// 16 lanes per CSR row: strided partial sums, then a butterfly over the 16
+// lanes (fixed order, so every launch gives the same bits).
+__global__ __launch_bounds__(KL_WG) void kl_spmv(kl_spmv_args a, kl_slice s) {
+    const uint32_t row = kl_wg_linear(s) * 16 + threadIdx.x / 16;
+    const int l = threadIdx.x % 16;
+    float sum = 0.0f;
+    if (row < a.nrows) {
+        const uint32_t b = (uint32_t)a.row_ptr[row];
+        uint32_t e = (uint32_t)a.row_ptr[row + 1];
+        if (e > a.nnz) e = a.nnz;
+        for (uint32_t j = b + l; j < e; j += 16) {
+            const int c = a.col[j];
+            if ((uint32_t)c < a.ncols) sum = __builtin_fmaf(a.val[j], a.x[c], sum);
+        }
+    }
+    for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 16);
+    if (row < a.nrows && l == 0) a.y[row] = sum;
+}
+
+// --------------------------------------------------------------- stencil
+// 64 x 16 cells per workgroup; each thread walks 4 rows of one column and
+// keeps the vertical neighbours in registers.  Original grid:
+// (ceil(nx/64), ceil(ny/16), 1).
+__global__ __launch_bounds__(KL_WG) void kl_stencil(kl_stencil_args a, kl_slice s) {
+    const uint32_t lin = kl_wg_linear(s);
+    const uint32_t bx = lin % s.gx, by = lin / s.gx;
+    const uint32_t x = bx * 64 + threadIdx.x % 64;
+    const uint32_t y0 = by * 16 + (threadIdx.x / 64) * 4;
+    const uint32_t nx = a.nx, ny = a.ny;
+    if (x >= nx || y0 >= ny) return;
+    const float* __restrict__ in = a.in;
+    float* __restrict__ out = a.out;
+    const bool xedge = x == 0 || x == nx - 1;
+    float up = y0 > 0 ? in[(size_t)(y0 - 1) * nx + x] : 0.0f;
+    float mid = in[(size_t)y0 * nx + x];
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t y = y0 + r;
+        if (y >= ny) break;
+        const size_t q = (size_t)y * nx + x;
+        const float down = y + 1 < ny ? in[q + nx] : 0.0f;
+        float v;
+        if (xedge || y == 0 || y == ny - 1) {
+            v = mid;
+        } else {
+            const float nsum = (up + down) + (in[q - 1] + in[q + 1]);
+            v = __builtin_fmaf(a.c1, nsum, a.c0 * mid);
+        }
+        out[q] = v;
+        up = mid;
+        mid = down;
+    }
+}
+
+// -------------------------------------------------------- black-scholes
+__device__ __forceinline__ void bs_one(float S, float K, float T, float r, float sig,
+                                       float* call, float* put) {
+    const float rs2 = 0.70710678118654752f;
+    const float sq = sig * sqrtf(T);
+    const float d1 = (logf(S / K) + (r + 0.5f * sig * sig) * T) / sq;
+    const float d2 = d1 - sq;
+    const float disc = K * expf(-r * T);
+    *call = S * (0.5f * erfcf(-d1 * rs2)) - disc * (0.5f * erfcf(-d2 * rs2));
+    *put = disc * (0.5f * erfcf(d2 * rs2)) - S * (0.5f * erfcf(d1 * rs2));
+}
+
+__global__ __launch_bounds__(KL_WG) void kl_bs(kl_bs_args a, kl_slice s) {
+    const uint64_t i = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
+    if (i >= a.n) return;
+    const float4 S = *(const float4*)(a.s + i);
+    const float4 K = *(const float4*)(a.k + i);
+    const float4 T = *(const float4*)(a.t + i);
+    float4 c, p;
+    bs_one(S.x, K.x, T.x, a.r, a.sigma, &c.x, &p.x);
+    bs_one(S.y, K.y, T.y, a.r, a.sigma, &c.y, &p.y);
+    bs_one(S.z, K.z, T.z, a.r, a.sigma, &c.z, &p.z);
+    bs_one(S.w, K.w, T.w, a.r, a.sigma, &c.w, &p.w);
+    *(float4*)(a.call + i) = c;
+    *(float4*)(a.put + i) = p;
+}
+
+// ------------------------------------------------------------- histogram
+// Each workgroup counts a 64 KiB chunk into one LDS copy of the bins per
+// wave, then adds its non-zero totals to the global bins.
+__global__ __launch_bounds__(KL_WG) void kl_hist(kl_hist_args a, kl_slice s) {
+    __shared__ uint32_t h[4][256];
+    const int tid = threadIdx.x, w = tid / 64;
+    for (int i = tid; i < 4 * 256; i += KL_WG) (&h[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)kl_wg_linear(s) * 65536;
+    for (int it = 0; it < 16; ++it) {
+        const uint64_t off = base + ((uint64_t)it * KL_WG + tid) * 16;
+        if (off + 16 <= a.n) {
+            const uint4 v = *(const uint4*)(a.data + off);
+            const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) atomicAdd(&h[w][(wd[q] >> (8 * b)) & 255u], 1u);
+        } else {
+            for (uint64_t o = off; o < a.n && o < off + 16; ++o) atomicAdd(&h[w][a.data[o]], 1u);
+        }
+    }
+    __syncthreads();
+    const uint32_t c = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+    if (c) atomicAdd(&a.bins[tid], c);
+}
+
+// ---------------------------------------------------------------- lookup
+// lower_bound of four queries per thread.  Each workgroup first loads the
+// last key of each of (up to) 1024 equal segments into LDS, finds the
+// segment of each query there, then finishes inside that segment in global
+// memory.  Both searches take a fixed number of steps (binary lifting), so
+// the four searches of a thread advance in lock step.
+__device__ __forceinline__ uint32_t kl_highbit(uint32_t v) {
+    return v ? 1u << (31 - __builtin_clz(v)) : 0u;
+}
+
+__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
+    constexpr uint32_t S = 1024;
+    __shared__ uint32_t sp[S];
+    const uint32_t n = a.nkeys;
+    const uint32_t seg = (n + S - 1) / S;
+    const uint32_t nseg = (n + seg - 1) / seg;
+    for (uint32_t i = threadIdx.x; i < nseg; i += KL_WG) {
+        const uint64_t end = (uint64_t)(i + 1) * seg;
+        sp[i] = a.keys[(end < n ? end : n) - 1];
+    }
+    __syncthreads();
+    const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
+    if (t0 >= a.nq) return;
+    const uint4 qv = *(const uint4*)(a.q + t0);
+    const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
+    uint32_t c[4] = {0, 0, 0, 0};
+    for (uint32_t st = kl_highbit(nseg); st; st >>= 1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (c[i] + st <= nseg && sp[c[i] + st - 1] < q[i]) c[i] += st;
+    uint32_t lo[4], len[4], cnt[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (c[i] >= nseg) {
+            lo[i] = n;
+            len[i] = 0;
+        } else {
+            lo[i] = c[i] * seg;
+            len[i] = n - lo[i] < seg ? n - lo[i] : seg;
+        }
+    }
+    const uint32_t* __restrict__ keys = a.keys;
+    for (uint32_t st = kl_highbit(seg); st; st >>= 1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (cnt[i] + st <= len[i] && keys[lo[i] + cnt[i] + st - 1] < q[i]) cnt[i] += st;
+    int4 o;
+    o.x = (int)(lo[0] + cnt[0]);
+    o.y = (int)(lo[1] + cnt[1]);
+    o.z = (int)(lo[2] + cnt[2]);
+    o.w = (int)(lo[3] + cnt[3]);
+    *(int4*)(a.out + t0) = o;
+}
+
+// ----------------------------------------------------------------- probe
+// Records where and when each workgroup ran and counts its visits; used to
+// check that a slicing plan runs every workgroup exactly once and to see
+// how the dispatcher places co-running slices on CUs.  `spin` dependent
+// fmas per thread stand for work.
+__global__ __launch_bounds__(KL_WG) void kl_probe(kl_probe_args a, kl_slice s) {
+    const uint32_t lin = kl_wg_linear(s);
+    if (lin >= a.n_wg) return;
+    const uint64_t t0 = wall_clock64();
+    float v = (float)threadIdx.x;
+    for (uint32_t i = 0; i < a.spin; ++i) v = __builtin_fmaf(v, 0.999f, 1.0f);
+    asm volatile("" ::"v"(v));
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // HW_ID (hardware register 4): CU_ID 11:8, SH_ID 12, SE_ID 14:13;
+        // XCC_ID (hardware register 20) bits 3:0
+        const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);
+        const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
+        const uint64_t t1 = wall_clock64();
+        atomicAdd(&a.visits[lin], 1u);
+        a.info[3 * (uint64_t)lin] = ((uint64_t)xcc << 32) | hw;
+        a.info[3 * (uint64_t)lin + 1] = t0;
+        a.info[3 * (uint64_t)lin + 2] = t1;
+    }
+}
+
+// ===================================================== host-side registry
+namespace {
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// Validates an argument block and returns its original grid; "" on success.
+std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3* g) {
+    std::string n(name);
+    *g = {1, 1, 1};
+#define KL_ARGS(T)                                                     \
+    if (bytes != sizeof(T)) return "argument block size mismatch";    \
+    T a;                                                               \
+    std::memcpy(&a, args, sizeof(T));
+    if (n == "poly") {
+        KL_ARGS(kl_poly_args);
+        if (!a.x || !a.coef || !a.y || a.n == 0) return "null pointer or n == 0";
+        if (a.ncoef < 1 || a.ncoef > 1024) return "ncoef outside [1, 1024]";
+        g->x = cdiv(a.n, KL_WG);
+    } else if (n == "gather") {
+        KL_ARGS(kl_gather_args);
+        if (!a.idx || !a.table || !a.out || a.n == 0 || a.table_n == 0)
+            return "null pointer or empty input";
+        g->x = cdiv(a.n, KL_WG);
+    } else if (n == "sgemm") {
+        KL_ARGS(kl_sgemm_args);
+        if (!a.a || !a.b || !a.c) return "null pointer";
+        if (a.m == 0 || a.n == 0 || a.k == 0 || a.m % 128 || a.n % 128 || a.k % 16)
+            return "sgemm needs m, n multiples of 128 and k a multiple of 16";
+        if (!aligned16(a.a) || !aligned16(a.b)) return "a, b must be 16-byte aligned";
+        uint64_t tiles = (uint64_t)(a.m / 128) * (a.n / 128);
+        if (tiles > 0xffffffffull) return "too many tiles";
+        g->x = (uint32_t)tiles;
+    } else if (n == "spmv") {
+        KL_ARGS(kl_spmv_args);
+        if (!a.row_ptr || !a.col || !a.val || !a.x || !a.y || a.nrows == 0)
+            return "null pointer or nrows == 0";
+        if (a.nrows > 0xffffffffu - 16) return "nrows too large";
+        g->x = cdiv(a.nrows, 16);
+    } else if (n == "stencil") {
+        KL_ARGS(kl_stencil_args);
+        if (!a.in || !a.out || a.nx == 0 || a.ny == 0) return "null pointer or empty grid";
+        if (a.in == a.out) return "stencil in and out must differ";
+        g->x = cdiv(a.nx, 64);
+        g->y = cdiv(a.ny, 16);
+    } else if (n == "bs") {
+        KL_ARGS(kl_bs_args);
+        if (!a.s || !a.k || !a.t || !a.call || !a.put || a.n == 0 || a.n % 4)
+            return "null pointer, or n not a positive multiple of 4";
+        if (!aligned16(a.s) || !aligned16(a.k) || !aligned16(a.t) || !aligned16(a.call) ||
+            !aligned16(a.put))
+            return "bs arrays must be 16-byte aligned";
+        g->x = cdiv(a.n, 4 * KL_WG);
+    } else if (n == "hist") {
+        KL_ARGS(kl_hist_args);
+        if (!a.data || !a.bins || a.n == 0 || a.n % 16) return "null pointer or n % 16 != 0";
+        if (!aligned16(a.data)) return "hist data must be 16-byte aligned";
+        uint64_t wg = (a.n + 65535) / 65536;
+        if (wg > 0xffffffffull) return "input too large";
+        g->x = (uint32_t)wg;
+    } else if (n == "probe") {
+        KL_ARGS(kl_probe_args);
+        if (!a.visits || !a.info || a.n_wg == 0) return "null pointer or n_wg == 0";
+        if (a.spin > (1u << 24)) return "spin above 2^24";
+        g->x = a.n_wg;
+    } else if (n == "lookup") {
+        KL_ARGS(kl_lookup_args);
+        if (!a.keys || !a.q || !a.out || a.nkeys == 0 || a.nq == 0 || a.nq % 4)
+            return "null pointer, nkeys == 0, or nq not a positive multiple of 4";
+        if (!aligned16(a.q) || !aligned16(a.out)) return "q, out must be 16-byte aligned";
+        g->x = cdiv(a.nq, 4 * KL_WG);
+    } else {
+        return "unknown built-in kernel";
+    }
+#undef KL_ARGS
+    return "";
+}
+
+struct BuiltinEntry {
+    const char* name;
+    const void* fn;
+    uint32_t args_bytes;
+    uint32_t flags;
+};
+
+const BuiltinEntry kBuiltins[] = {
+    {"poly", (const void*)kl_poly, sizeof(kl_poly_args), KL_KF_IDEMPOTENT},
+    {"gather", (const void*)kl_gather, sizeof(kl_gather_args), KL_KF_IDEMPOTENT},
+    {"sgemm", (const void*)kl_sgemm, sizeof(kl_sgemm_args), KL_KF_IDEMPOTENT},
+    {"spmv", (const void*)kl_spmv, sizeof(kl_spmv_args), KL_KF_IDEMPOTENT},
+    {"stencil", (const void*)kl_stencil, sizeof(kl_stencil_args), KL_KF_IDEMPOTENT},
+    {"bs", (const void*)kl_bs, sizeof(kl_bs_args), KL_KF_IDEMPOTENT},
+    {"hist", (const void*)kl_hist, sizeof(kl_hist_args), 0u},
+    {"lookup", (const void*)kl_lookup, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
+    {"probe", (const void*)kl_probe, sizeof(kl_probe_args), 0u},
+};
+
+}  // namespace
+
+namespace kl {
+void set_error(const std::string& msg);
+
+bool builtin_check(const char* name, const void* args, uint32_t bytes, kl_dim3* grid,
+                   std::string* err) {
+    *err = grid_of(name, args, bytes, grid);
+    return err->empty();
+}
+
+bool is_builtin_fn(const void* fn, const char** name) {
+    for (const auto& b : kBuiltins)
+        if (b.fn == fn) {
+            *name = b.name;
+            return true;
+        }
+    return false;
+}
+}  // namespace kl
+
+extern "C" kl_status kernelet_builtin(const char* name, kl_kernel_desc* out) {
+    if (!name || !out) {
+        kl::set_error("kernelet_builtin: null argument");
+        return KL_EINVAL;
+    }
+    for (const auto& b : kBuiltins) {
+        if (std::strcmp(b.name, name) == 0) {
+            out->name = b.name;
+            out->host_fn = b.fn;
+            out->block_threads = KL_WG;
+            out->args_bytes = b.args_bytes;
+            out->flags = b.flags;
+            out->profile = nullptr;
+            return KL_OK;
+        }
+    }
+    kl::set_error(std::string("kernelet_builtin: unknown kernel ") + name);
+    return KL_ENOTFOUND;
+}
+
+extern "C" kl_status kernelet_builtin_grid(const char* name, const void* args,
+                                           uint32_t args_bytes, kl_dim3* grid) {
+    if (!name || !args || !grid) {
+        kl::set_error("kernelet_builtin_grid: null argument");
+        return KL_EINVAL;
+    }
+    std::string err = grid_of(name, args, args_bytes, grid);
+    if (!err.empty()) {
+        kl::set_error(std::string("kernelet_builtin_grid(") + name + "): " + err);
+        return err == "unknown built-in kernel" ? KL_ENOTFOUND : KL_EINVAL;
+    }
+    return KL_OK;
+}

@@ -1,0 +1,195 @@
+"""Python face of libkernelet.so: the calls of include/kernelet.h with the
+same names, taking ctypes structures and torch device pointers (argument
+marshalling only; every step runs in the library)."""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import (Config, Decision, Dim3, KernelDesc, Profile, Stats, call, lib)
+
+PROFILE_FIELDS = [f for f, _ in Profile._fields_ if f != "reserved"]
+CONFIG_FIELDS = [f for f, _ in Config._fields_ if f != "reserved"]
+
+
+def default_config(**over) -> Config:
+    cfg = Config()
+    call("kernelet_default_config", C.byref(cfg))
+    for k, v in over.items():
+        if k not in CONFIG_FIELDS:
+            raise KeyError(k)
+        if k == "ratio_mode" and isinstance(v, str):
+            v = _lib.MODE[v]
+        setattr(cfg, k, v)
+    return cfg
+
+
+def make_profile(d) -> Profile:
+    if isinstance(d, Profile):
+        return d
+    p = Profile()
+    for k, v in d.items():
+        if k in PROFILE_FIELDS:
+            setattr(p, k, v)
+    return p
+
+
+def profile_dict(p: Profile) -> dict:
+    return {f: getattr(p, f) for f in PROFILE_FIELDS}
+
+
+def builtin_desc(name: str) -> KernelDesc:
+    d = KernelDesc()
+    call("kernelet_builtin", name.encode(), C.byref(d))
+    return d
+
+
+def builtin_grid(name: str, args) -> tuple:
+    g = Dim3()
+    call("kernelet_builtin_grid", name.encode(), C.byref(args), C.sizeof(args), C.byref(g))
+    return (g.x, g.y, g.z)
+
+
+def predict(p1, p2=None, w1=1, w2=0, cfg: Config | None = None):
+    """(ipc1, ipc2, cp) of the performance model; no GPU needed."""
+    a = make_profile(p1)
+    b = make_profile(p2) if p2 is not None else None
+    o = [C.c_double() for _ in range(3)]
+    call("kernelet_predict", C.byref(cfg) if cfg else None, C.byref(a),
+         C.byref(b) if b is not None else None, w1, w2, *[C.byref(x) for x in o])
+    return tuple(x.value for x in o)
+
+
+def best_ratio(p1, p2, cfg: Config | None = None):
+    a, b = make_profile(p1), make_profile(p2)
+    b1, b2 = C.c_int32(), C.c_int32()
+    v, c1, c2 = C.c_double(), C.c_double(), C.c_double()
+    call("kernelet_best_ratio", C.byref(cfg) if cfg else None, C.byref(a), C.byref(b),
+         C.byref(b1), C.byref(b2), C.byref(v), C.byref(c1), C.byref(c2))
+    return b1.value, b2.value, v.value, c1.value, c2.value
+
+
+def simulate(profiles, job_profile, job_wgs, job_arrival=None, policy="markov",
+             cfg: Config | None = None, max_dec=100000):
+    """Algorithm 1 (or FIFO) on the model's virtual clock; no GPU needed."""
+    n = len(job_profile)
+    P = (Profile * len(profiles))(*[make_profile(p) for p in profiles])
+    jp = (C.c_int32 * n)(*job_profile)
+    jw = (C.c_uint64 * n)(*job_wgs)
+    ja = (C.c_double * n)(*job_arrival) if job_arrival is not None else None
+    dec = (Decision * max_dec)()
+    nd = C.c_int32()
+    span = C.c_double()
+    done = (C.c_double * max(n, 1))()
+    call("kernelet_simulate", C.byref(cfg) if cfg else None, P, len(profiles), jp, jw, ja,
+         n, _lib.POLICY[policy], dec, max_dec, C.byref(nd), C.byref(span), done)
+    decs = [_dec_dict(dec[i]) for i in range(min(nd.value, max_dec))]
+    return decs, span.value, list(done)[:n]
+
+
+def _dec_dict(d: Decision) -> dict:
+    return {f: getattr(d, f) for f, _ in Decision._fields_}
+
+
+class Runtime:
+    """One kernelet runtime on one HIP device."""
+
+    def __init__(self, device: int = 0, cfg: Config | None = None, **over):
+        lib()
+        self.cfg = cfg if cfg is not None else default_config(**over)
+        h = C.c_void_p()
+        call("kernelet_init", C.byref(h), device, C.byref(self.cfg))
+        self.h = h
+        self.kernels = {}
+
+    # -------------------------------------------------------------- kernels
+    def register(self, desc: KernelDesc, profile=None) -> int:
+        if profile is not None:
+            prof = make_profile(profile)
+            desc.profile = C.pointer(prof)
+        k = C.c_int32()
+        call("kernelet_register", self.h, C.byref(desc), C.byref(k))
+        self.kernels[desc.name.decode()] = k.value
+        return k.value
+
+    def register_builtin(self, name: str, profile=None) -> int:
+        return self.register(builtin_desc(name), profile)
+
+    def set_profile(self, k: int, profile) -> None:
+        p = make_profile(profile)
+        call("kernelet_set_profile", self.h, k, C.byref(p))
+
+    def get_profile(self, k: int) -> dict:
+        p = Profile()
+        call("kernelet_get_profile", self.h, k, C.byref(p))
+        return profile_dict(p)
+
+    # ----------------------------------------------------------------- jobs
+    def submit(self, k: int, grid, args, after: int = -1, client: int = 0,
+               footprint: int = 0) -> int:
+        g = Dim3(*grid) if not isinstance(grid, Dim3) else grid
+        j = C.c_int64()
+        call("kernelet_submit", self.h, k, g, C.byref(args), C.sizeof(args), after,
+             client, footprint, C.byref(j))
+        return j.value
+
+    def slice(self, job: int, wgs_per_slice: int) -> int:
+        n = C.c_uint32()
+        call("kernelet_slice", self.h, job, wgs_per_slice, C.byref(n))
+        return n.value
+
+    def schedule(self, policy: str = "markov", blocking: bool = True,
+                 replan_on_arrival: bool = False, wait_done: bool = False) -> None:
+        flags = (_lib.KL_BLOCKING if blocking else 0) | (
+            _lib.KL_REPLAN_ON_ARRIVAL if replan_on_arrival else 0) | (
+            _lib.KL_WAIT_DONE if wait_done else 0)
+        call("kernelet_schedule", self.h, _lib.POLICY[policy], flags)
+
+    def wait(self, job: int, timeout_ns: int = -1) -> None:
+        call("kernelet_wait", self.h, job, timeout_ns)
+
+    def synchronize(self) -> None:
+        call("kernelet_synchronize", self.h)
+
+    def cancel(self, job: int) -> None:
+        call("kernelet_cancel", self.h, job)
+
+    def job_times(self, job: int):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        call("kernelet_job_times", self.h, job, C.byref(a), C.byref(b), C.byref(c))
+        return a.value, b.value, c.value
+
+    def reap(self) -> None:
+        call("kernelet_reap", self.h)
+
+    # -------------------------------------------------------------- logging
+    def time_kernel(self, k: int, enable: bool = True) -> None:
+        call("kernelet_time_kernel", self.h, k, int(enable))
+
+    def kernel_time(self, k: int):
+        """(total ms, launches, workgroups) of kernel k's timed launches."""
+        ms, n, w = C.c_double(), C.c_int64(), C.c_int64()
+        call("kernelet_kernel_time", self.h, k, C.byref(ms), C.byref(n), C.byref(w))
+        return ms.value, n.value, w.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        call("kernelet_stats", self.h, C.byref(s))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def decisions(self, max_n: int = 1 << 16) -> list:
+        buf = (Decision * max_n)()
+        n = C.c_int32()
+        call("kernelet_decisions", self.h, buf, max_n, C.byref(n))
+        return [_dec_dict(buf[i]) for i in range(n.value)]
+
+    def close(self) -> None:
+        if self.h:
+            call("kernelet_shutdown", self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

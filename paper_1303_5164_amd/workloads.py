@@ -1,0 +1,141 @@
+"""Device instances of the eight built-in workload kernels.
+
+An instance owns its device tensors (inputs shared read-only between the
+instances built from the same host inputs, outputs its own) and the list of
+launches that make it: one launch for every kernel except the stencil,
+whose sweeps are a chain of launches ping-ponging between two buffers.
+Argument marshalling and memory placement only; the arithmetic runs in
+libkernelet.so.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from .runtime import builtin_grid
+
+TYPES = ["poly", "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup"]
+
+
+@dataclass
+class Launch:
+    args: object        # ctypes argument block
+    grid: tuple
+
+
+@dataclass
+class Instance:
+    kind: str
+    launches: list
+    tensors: dict = field(default_factory=dict)
+    outputs: list = field(default_factory=list)
+    footprint: int = 0
+    result: str = ""    # name of the tensor holding the final result
+
+    def reset(self):
+        """Zero what must start at zero before the instance runs again."""
+        if self.kind == "hist":
+            self.tensors["bins"].zero_()
+
+
+def _dev(a, device):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def device_inputs(kind: str, host: dict, device) -> dict:
+    """Upload one set of host inputs (from synth) as device tensors."""
+    d = {}
+    for k, v in host.items():
+        if isinstance(v, np.ndarray):
+            if v.dtype == np.uint32:
+                v = v.view(np.int32)   # torch has no uint32 kernels we need
+            d[k] = _dev(v, device)
+    return d
+
+
+def _ptr(t):
+    return t.data_ptr()
+
+
+def build(kind: str, dev_in: dict, params: dict, device) -> Instance:
+    """One instance over shared device inputs `dev_in` with its own outputs."""
+    A = _lib.ARGS[kind]
+    T = {}
+    if kind == "poly":
+        n = dev_in["x"].numel()
+        T["y"] = torch.empty(n, dtype=torch.float32, device=device)
+        a = A(_ptr(dev_in["x"]), _ptr(dev_in["coef"]), _ptr(T["y"]), n,
+              dev_in["coef"].numel())
+        res = "y"
+    elif kind == "gather":
+        n = dev_in["idx"].numel()
+        T["out"] = torch.empty(n, dtype=torch.int32, device=device)
+        a = A(_ptr(dev_in["idx"]), _ptr(dev_in["table"]), _ptr(T["out"]), n,
+              dev_in["table"].numel())
+        res = "out"
+    elif kind == "sgemm":
+        m, k = dev_in["a"].shape
+        n = dev_in["b"].shape[1]
+        T["c"] = torch.empty((m, n), dtype=torch.float32, device=device)
+        a = A(_ptr(dev_in["a"]), _ptr(dev_in["b"]), _ptr(T["c"]), m, n, k)
+        res = "c"
+    elif kind == "spmv":
+        nrows = dev_in["row_ptr"].numel() - 1
+        T["y"] = torch.empty(nrows, dtype=torch.float32, device=device)
+        a = A(_ptr(dev_in["row_ptr"]), _ptr(dev_in["col"]), _ptr(dev_in["val"]),
+              _ptr(dev_in["x"]), _ptr(T["y"]), nrows, dev_in["x"].numel(),
+              dev_in["col"].numel(), 0)
+        res = "y"
+    elif kind == "stencil":
+        ny, nx = dev_in["u"].shape
+        iters = int(params.get("iters", 10))
+        c0, c1 = float(params.get("c0", 0.5)), float(params.get("c1", 0.125))
+        T["b0"] = torch.empty((ny, nx), dtype=torch.float32, device=device)
+        T["b1"] = torch.empty((ny, nx), dtype=torch.float32, device=device)
+        launches = []
+        src = dev_in["u"]
+        for i in range(iters):
+            dst = T["b0"] if i % 2 == 0 else T["b1"]
+            sa = A(_ptr(src), _ptr(dst), ny, nx, c0, c1)
+            launches.append(Launch(sa, builtin_grid(kind, sa)))
+            src = dst
+        res = "b0" if (iters - 1) % 2 == 0 else "b1"
+        fp = sum(t.numel() * t.element_size() for t in T.values()) + dev_in["u"].numel() * 4
+        return Instance(kind, launches, T, [res], fp, res)
+    elif kind == "bs":
+        n = dev_in["s"].numel()
+        T["call"] = torch.empty(n, dtype=torch.float32, device=device)
+        T["put"] = torch.empty(n, dtype=torch.float32, device=device)
+        a = A(_ptr(dev_in["s"]), _ptr(dev_in["k"]), _ptr(dev_in["t"]), _ptr(T["call"]),
+              _ptr(T["put"]), n, float(params.get("r", 0.02)),
+              float(params.get("sigma", 0.30)))
+        res = "call"
+    elif kind == "hist":
+        T["bins"] = torch.zeros(256, dtype=torch.int32, device=device)
+        a = A(_ptr(dev_in["data"]), _ptr(T["bins"]), dev_in["data"].numel())
+        res = "bins"
+    elif kind == "lookup":
+        nq = dev_in["q"].numel()
+        T["out"] = torch.empty(nq, dtype=torch.int32, device=device)
+        a = A(_ptr(dev_in["keys"]), _ptr(dev_in["q"]), _ptr(T["out"]),
+              dev_in["keys"].numel(), nq)
+        res = "out"
+    else:
+        raise KeyError(kind)
+    fp = sum(t.numel() * t.element_size() for t in T.values()) + sum(
+        t.numel() * t.element_size() for t in dev_in.values())
+    return Instance(kind, [Launch(a, builtin_grid(kind, a))], T, [res], fp, res)
+
+
+def submit(rt, kernel_ids: dict, inst: Instance, client: int = 0, after: int = -1):
+    """Submit an instance's launches (chained in order); returns job ids."""
+    jobs = []
+    prev = after
+    for ln in inst.launches:
+        prev = rt.submit(kernel_ids[inst.kind], ln.grid, ln.args, after=prev,
+                         client=client, footprint=inst.footprint if not jobs else 0)
+        jobs.append(prev)
+    return jobs

@@ -1,0 +1,154 @@
+"""The C-ABI library on the CPU: it loads, exports every symbol of
+include/kernelet.h, and its host-side model, ratio search and virtual-clock
+scheduler agree with the oracle.  No GPU calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1303_5164_amd as K
+from paper_1303_5164_amd import _lib
+from oracle import markov as M
+from oracle import sched as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "kernelet.h")).read()
+    declared = set(re.findall(r"^\s*(?:kl_status|const char\*)\s+(kernelet_\w+)\(", hdr, re.M))
+    assert declared == set(_lib.SYMBOLS)
+    L = _lib.lib()
+    for s in declared:
+        assert hasattr(L, s), s
+
+
+def oracle_kernel(p, mem_latency=400.0):
+    cl = [M.StallClass(p["r_mem"], p.get("lat_mem") or mem_latency, p.get("mem_req", 1.0))]
+    if p.get("r_comp", 0) > 0:
+        cl.append(M.StallClass(p["r_comp"], p["lat_comp"], 0.0))
+    return M.Kernel(tuple(cl))
+
+
+def oracle_kprof(p):
+    return M.KProfile(oracle_kernel(p), p["waves_per_simd"], p["max_wg_per_cu"],
+                      p["instr_per_wave"], vgpr=p.get("vgpr", 0), lds=p.get("lds_bytes", 0))
+
+
+def rand_profile(rng, two_class):
+    p = dict(r_mem=float(rng.uniform(0.002, 0.3)), mem_req=float(rng.choice([1, 4, 16])),
+             lat_mem=float(rng.uniform(50, 800)), instr_per_wave=float(rng.uniform(50, 5000)),
+             max_wg_per_cu=int(rng.integers(1, 9)), waves_per_simd=1,
+             vgpr=int(rng.choice([16, 32, 64, 128])), lds_bytes=int(rng.choice([0, 4096, 32768])),
+             pur=float(rng.uniform(0, 1)), mur=float(rng.uniform(0, 1)))
+    if two_class:
+        p.update(r_comp=float(rng.uniform(0.01, 0.3)), lat_comp=float(rng.uniform(2, 40)))
+    return p
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_predict_matches_oracle(seed):
+    rng = np.random.default_rng(seed)
+    p1, p2 = rand_profile(rng, seed % 2 == 0), rand_profile(rng, seed % 3 == 0)
+    beta = [0.0, 0.5, 2.0][seed % 3]
+    cfg = K.default_config(beta=beta)
+    w1, w2 = int(rng.integers(1, 5)), int(rng.integers(1, 5))
+    i1, i2, cp = K.predict(p1, p2, w1, w2, cfg)
+    o = M.ipc_pair(oracle_kernel(p1), w1, oracle_kernel(p2), w2, beta)
+    s = (M.ipc_homogeneous(oracle_kernel(p1), p1["max_wg_per_cu"], beta),
+         M.ipc_homogeneous(oracle_kernel(p2), p2["max_wg_per_cu"], beta))
+    assert abs(i1 - o[0]) <= 1e-9 * abs(o[0]) and abs(i2 - o[1]) <= 1e-9 * abs(o[1])
+    assert abs(cp - M.cp(o, s)) <= 1e-9 * max(1.0, abs(cp))
+
+
+def test_one_wave_closed_form_through_abi():
+    p = dict(r_mem=0.1, mem_req=1, lat_mem=400, instr_per_wave=100, max_wg_per_cu=1,
+             waves_per_simd=1)
+    i1, _, _ = K.predict(p, None, 1, 0)
+    assert abs(i1 - 1 / (1 + 0.1 * 400)) < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["cp", "balanced", "literal"])
+def test_best_ratio_matches_oracle(mode):
+    rng = np.random.default_rng(11)
+    for _ in range(4):
+        p1, p2 = rand_profile(rng, False), rand_profile(rng, True)
+        cfg = K.default_config(ratio_mode=mode)
+        try:
+            got = K.best_ratio(p1, p2, cfg)
+        except K.KerneletError:
+            got = None
+        ref = M.best_ratio(oracle_kprof(p1), oracle_kprof(p2), 0.0, mode)
+        if ref is None:
+            assert got is None
+            continue
+        assert got[:2] == ref[:2]
+        assert np.allclose(got[2:], ref[2:], rtol=1e-9, atol=1e-12)
+
+
+def _types_and_jobs(seed, n_types=5, n_jobs=30, arrivals=True):
+    rng = np.random.default_rng(seed)
+    profs = [rand_profile(rng, i % 2 == 1) for i in range(n_types)]
+    jp = [int(rng.integers(0, n_types)) for _ in range(n_jobs)]
+    jw = [int(rng.integers(100, 20000)) for _ in range(n_jobs)]
+    ja = [float(i * rng.uniform(0, 3000)) if arrivals else 0.0 for i in range(n_jobs)]
+    return profs, jp, jw, ja
+
+
+@pytest.mark.parametrize("seed,prune", [(1, True), (2, False), (3, True)])
+def test_simulate_matches_oracle(seed, prune):
+    profs, jp, jw, ja = _types_and_jobs(seed)
+    cfg = K.default_config(use_prune=int(prune), n_cu=256)
+    decs, span, done = K.simulate(profs, jp, jw, ja, "markov", cfg)
+    types = {i: S.TypeInfo(oracle_kprof(p), p["pur"], p["mur"]) for i, p in enumerate(profs)}
+    ocfg = S.Config(use_prune=prune, mode="cp", n_cu=256)
+    jobs = [S.Job(i, jp[i], jw[i], ja[i]) for i in range(len(jp))]
+    log, ospan, odone = S.simulate_kernelet(jobs, types, ocfg)
+    assert len(decs) == len(log)
+    for d, o in zip(decs, log):
+        assert (d["j1"], d["j2"], d["b1"], d["b2"]) == (o.j1, o.j2, o.b1, o.b2)
+    assert abs(span - ospan) <= 1e-9 * ospan
+    assert np.allclose(done, [odone[i] for i in range(len(jp))], rtol=1e-9)
+    fspan, fdone = S.simulate_fifo(jobs, types, ocfg)
+    _, span_f, done_f = K.simulate(profs, jp, jw, ja, "fifo", cfg)
+    assert abs(span_f - fspan) <= 1e-9 * fspan
+
+
+def test_host_errors():
+    good = dict(r_mem=0.1, mem_req=1, instr_per_wave=10, max_wg_per_cu=2, waves_per_simd=1)
+    bad = dict(good, r_mem=1.5)
+    with pytest.raises(K.KerneletError) as e:
+        K.predict(bad, None, 1, 0)
+    assert e.value.code == -1
+    with pytest.raises(K.KerneletError):
+        K.predict(good, None, 0, 0)
+    with pytest.raises(K.KerneletError):
+        K.default_config(inflight=0) and K.predict(good, None, 1, 0, K.default_config(inflight=0))
+    # a pair that cannot share a CU
+    big = dict(good, lds_bytes=160 * 1024, max_wg_per_cu=1)
+    with pytest.raises(K.KerneletError) as e:
+        K.best_ratio(big, big)
+    assert e.value.code == -4
+
+
+def test_builtin_descriptors_and_grids():
+    for name in ["poly", "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup"]:
+        d = K.builtin_desc(name)
+        assert d.name.decode() == name and d.block_threads == 256
+        assert d.args_bytes == ctypes.sizeof(_lib.ARGS[name])
+    a = _lib.SgemmArgs(16, 16, 16, 4096, 4096, 4096)
+    assert K.builtin_grid("sgemm", a) == (1024, 1, 1)
+    a = _lib.StencilArgs(16, 32, 8192, 8192, 0.5, 0.125)
+    assert K.builtin_grid("stencil", a) == (128, 512, 1)
+    a = _lib.SgemmArgs(16, 16, 16, 100, 4096, 4096)
+    with pytest.raises(K.KerneletError) as e:
+        K.builtin_grid("sgemm", a)
+    assert e.value.code == -1
+    a = _lib.BsArgs(8, 16, 16, 16, 16, 1024, 0.02, 0.3)   # misaligned pointer
+    with pytest.raises(K.KerneletError):
+        K.builtin_grid("bs", a)
+    with pytest.raises(K.KerneletError) as e:
+        K.builtin_desc("nope")
+    assert e.value.code == -4

@@ -63,7 +63,15 @@ def algorithmic(kind, inst_args):
         return 0.0, 1.0 * a.n + 1024, PEAK_VALU_F32
     if kind == "lookup":
         return 0.0, 8.0 * a.nq + 4.0 * a.nkeys, PEAK_VALU_F32
+    if kind == "lookup_index":
+        ent = float(_index_entries(a.nkeys))
+        return 0.0, 8.0 * ent, PEAK_VALU_F32
     raise KeyError(kind)
+
+
+def _index_entries(n):
+    from paper_1303_5164_amd import _lib
+    return _lib.lib().kernelet_lookup_index_entries(n)
 
 
 def cpu_baseline(hosts):
@@ -173,28 +181,29 @@ def main():
 
     rt = K.Runtime(0)
     prof = profiles.load()
-    kids = {k: rt.register_builtin(k, prof[k]) for k in W.TYPES}
+    kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     setup_s = time.perf_counter() - t_setup
 
-    # algorithmic work per instance and per workgroup
+    # algorithmic work of each kernel per instance (all its launches) and its
+    # workgroups
     work = {}
+    seen = set()
     for inst in insts:
-        if inst.kind in work:
+        if inst.kind in seen:
             continue
-        f = b = 0.0
-        wgs = 0
-        peak = None
+        seen.add(inst.kind)
         for ln in inst.launches:
-            ff, bb, peak = algorithmic(inst.kind, ln.args)
-            f += ff
-            b += bb
-            wgs += ln.grid[0] * ln.grid[1] * ln.grid[2]
-        work[inst.kind] = dict(flops=f, bytes=b, peak=peak, wgs=wgs)
+            kname = ln.kernel or inst.kind
+            ff, bb, peak = algorithmic(kname, ln.args)
+            w = work.setdefault(kname, dict(flops=0.0, bytes=0.0, peak=peak, wgs=0))
+            w["flops"] += ff
+            w["bytes"] += bb
+            w["wgs"] += ln.grid[0] * ln.grid[1] * ln.grid[2]
 
     legs = [l for l in args.legs.split(",") if l]
     times = {l: [] for l in legs}
     turn = {l: [] for l in legs}
-    ktime = {k: [0.0, 0, 0] for k in W.TYPES}
+    ktime = {k: [0.0, 0, 0] for k in W.KERNELS}
     decisions = 0
     for step in range(args.warmup + args.steps):
         timed_step = step >= args.warmup
@@ -202,7 +211,7 @@ def main():
             for inst in insts:
                 inst.reset()
             if timed_step:
-                for k in W.TYPES:
+                for k in W.KERNELS:
                     rt.time_kernel(kids[k], True)
             jobs = [W.submit(rt, kids, inst) for inst in insts]
             torch.cuda.synchronize()
@@ -216,7 +225,7 @@ def main():
                 for js in jobs:
                     _, _, td = rt.job_times(js[-1])
                     turn[leg].append(max(td - t0, 0) / 1e6)
-                for k in W.TYPES:
+                for k in W.KERNELS:
                     ms, n, w = rt.kernel_time(kids[k])
                     ktime[k][0] += ms
                     ktime[k][1] += n
@@ -263,7 +272,7 @@ def main():
     out["decisions_per_step"] = decisions / max(1, args.warmup + args.steps)
 
     # roofline of the dominant kernel: all its launches in the timed region
-    dom = max(W.TYPES, key=lambda k: ktime[k][0])
+    dom = max(W.KERNELS, key=lambda k: ktime[k][0])
     ms, n, wg = ktime[dom]
     wk = work[dom]
     per_wg_f = wk["flops"] / wk["wgs"]
@@ -290,11 +299,11 @@ def main():
                                     * wg / max(n, 1), 1)
     out["roofline"] = roof
     # whole-mix roofline fraction: overlapped bound over measured time
-    comp = sum(work[k]["flops"] / work[k]["peak"] for k in W.TYPES) * args.instances
-    mem = sum(work[k]["bytes"] / PEAK_HBM for k in W.TYPES) * args.instances
+    comp = sum(work[k]["flops"] / work[k]["peak"] for k in W.KERNELS) * args.instances
+    mem = sum(work[k]["bytes"] / PEAK_HBM for k in W.KERNELS) * args.instances
     out["mix_roofline"] = {l: round(max(comp, mem) / med[l], 4) for l in legs}
     out["mix_bound_ms"] = {"compute": round(comp * 1e3, 4), "hbm": round(mem * 1e3, 4)}
-    out["kernel_ms_per_step"] = {k: round(ktime[k][0] / max(1, args.steps), 3) for k in W.TYPES}
+    out["kernel_ms_per_step"] = {k: round(ktime[k][0] / max(1, args.steps), 3) for k in W.KERNELS}
     out["setup_s"] = round(setup_s, 1)
     st = rt.stats()
     out["decision_us_mean"] = round(st["decision_us_total"] / max(1, st["decisions"]), 2)

@@ -188,6 +188,13 @@ kl_status kernelet_builtin(const char* name, kl_kernel_desc* out);
 kl_status kernelet_builtin_grid(const char* name, const void* args,
                                 uint32_t args_bytes, kl_dim3* grid);
 
+/* Resources of kernel k from its code object: workgroups one CU can hold
+ * when the kernel runs alone (hipOccupancyMaxActiveBlocksPerMultiprocessor
+ * with no dynamic LDS), VGPRs + AGPRs per lane, static LDS bytes per
+ * workgroup.  Any output may be NULL. */
+kl_status kernelet_kernel_info(kl_runtime* rt, kl_kernel k, int32_t* max_wg_per_cu,
+                               int32_t* vgpr, int32_t* lds_bytes);
+
 kl_status kernelet_set_profile(kl_runtime* rt, kl_kernel k, const kl_profile* p);
 kl_status kernelet_get_profile(kl_runtime* rt, kl_kernel k, kl_profile* p);
 

@@ -67,7 +67,8 @@ typedef struct {
 
 /* stencil: one Jacobi sweep of the 5-point stencil on an ny x nx grid:
  * interior out = c0 in + c1 ((N + S) + (W + E)), boundary cells copied.
- * Tiles of 64 x 16 cells; grid = (ceil(nx/64), ceil(ny/16), 1). */
+ * nx a multiple of 4, in/out 16-byte aligned.  Tiles of 256 x 32 cells;
+ * grid = (ceil(nx/256), ceil(ny/32), 1). */
 typedef struct {
     const float* in;
     float* out;
@@ -98,15 +99,27 @@ typedef struct {
 } kl_hist_args;
 
 /* lookup: out[t] = lower_bound(keys, q[t]) = smallest i with keys[i] >=
- * q[t], or nkeys if none; keys strictly increasing.  Four queries per
- * thread; grid = ceil(nq / 1024).  nq a multiple of 4, nkeys >= 1. */
+ * q[t], or nkeys if none; keys sorted ascending.  The search descends a
+ * static 16-ary tree over the keys whose nodes are 64-byte lines: level 1
+ * entry i is keys[min(16 i + 15, n - 1)] (the largest key of leaf line i),
+ * level k + 1 entry i is level k entry min(16 i + 15, m_k - 1); level sizes
+ * m_1 = ceil(n / 16), m_{k+1} = ceil(m_k / 16), stopping at the first level
+ * with at most 1024 entries (searched in LDS).  `index` holds the levels
+ * back to back (level 1 first), kernelet_lookup_index_entries(n) entries;
+ * the "lookup_index" kernel writes it (grid = ceil(entries / 256)) and the
+ * "lookup" kernel reads it (four queries per thread, grid = ceil(nq / 1024)).
+ * nq a multiple of 4, nkeys >= 1; keys, q, out, index 16-byte aligned. */
 typedef struct {
     const uint32_t* keys;
     const uint32_t* q;
     int32_t* out;
+    uint32_t* index;
     uint32_t nkeys;
     uint32_t nq;
 } kl_lookup_args;
+
+/* Number of uint32 entries of the lookup tree index for n keys. */
+uint64_t kernelet_lookup_index_entries(uint32_t nkeys);
 
 /* probe (not a workload): workgroup w adds 1 to visits[w] and writes
  * info[3w] = (XCC_ID << 32) | HW_ID, info[3w+1] = start, info[3w+2] = end

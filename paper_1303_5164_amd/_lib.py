@@ -106,7 +106,7 @@ class HistArgs(C.Structure):
 
 
 class LookupArgs(C.Structure):
-    _fields_ = [("keys", P), ("q", P), ("out", P), ("nkeys", C.c_uint32),
+    _fields_ = [("keys", P), ("q", P), ("out", P), ("index", P), ("nkeys", C.c_uint32),
                 ("nq", C.c_uint32)]
 
 
@@ -115,7 +115,8 @@ class ProbeArgs(C.Structure):
 
 
 ARGS = {"probe": ProbeArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
-        "stencil": StencilArgs, "bs": BsArgs, "hist": HistArgs, "lookup": LookupArgs}
+        "stencil": StencilArgs, "bs": BsArgs, "hist": HistArgs, "lookup": LookupArgs,
+        "lookup_index": LookupArgs}
 
 # every symbol include/kernelet.h declares
 SYMBOLS = [
@@ -126,6 +127,7 @@ SYMBOLS = [
     "kernelet_synchronize", "kernelet_cancel", "kernelet_job_times", "kernelet_reap",
     "kernelet_predict", "kernelet_best_ratio", "kernelet_simulate", "kernelet_stats",
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
+    "kernelet_kernel_info",
 ]
 
 _lib = None
@@ -177,12 +179,16 @@ def lib():
         "kernelet_stats": [C.c_void_p, C.POINTER(Stats)],
         "kernelet_decisions": [C.c_void_p, C.POINTER(Decision), i32, C.POINTER(i32)],
         "kernelet_time_kernel": [C.c_void_p, i32, i32],
+        "kernelet_kernel_info": [C.c_void_p, i32, C.POINTER(i32), C.POINTER(i32),
+                                 C.POINTER(i32)],
         "kernelet_kernel_time": [C.c_void_p, i32, PD, C.POINTER(i64), C.POINTER(i64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = i32
+    L.kernelet_lookup_index_entries.argtypes = [C.c_uint32]
+    L.kernelet_lookup_index_entries.restype = C.c_uint64
     L.kernelet_last_error.argtypes = []
     L.kernelet_last_error.restype = C.c_char_p
     _lib = L

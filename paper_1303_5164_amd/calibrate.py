@@ -1,0 +1,221 @@
+"""Measure the model inputs (kl_profile) of the built-in kernels on the GPU.
+
+Kernelet takes its model inputs from profiling a few blocks of each kernel
+alone (Section 4.4: memory-instruction ratio from hardware counters) and its
+pruning features PUR / MUR from solo runs (Section 4.3).  Two steps:
+
+  run:  every kernel alone at full size (FIFO, unsliced), timed by HIP
+        events per launch, and its code-object resources; writes a JSON of
+        solo times.  Run it once plainly (for times) and once per counter
+        pass under `rocprofv3 --pmc ... --output-format csv` (for counts).
+  fit:  combine the solo times and the counter CSVs into kl_profile values:
+          instructions per wave  I   = sum of SQ_INSTS_{VALU,SALU,VMEM,SMEM,
+                                        LDS,BRANCH} / SQ_WAVES
+          memory stall ratio    r_m  = SQ_INSTS_VMEM / total
+          compute stall ratio   r_c  = (SQ_INSTS_MFMA + SQ_INSTS_VALU_TRANS_F32)
+                                        / total, latency 16 issue slots when
+                                        matrix instructions dominate, else 4
+          PUR = waves * I / (time * f * n_cu)     (1.0 = one wave-instruction
+                                                   per issue slot per SIMD)
+          MUR = (FETCH_SIZE + WRITE_SIZE) / time / 8 TB/s
+          requests per memory instruction = DRAM bytes / 64 / VMEM instructions
+        and the memory latency of each kernel is fitted so that the model's
+        solo IPC at the kernel's occupancy equals the measured PUR.
+
+Usage:
+  python -m paper_1303_5164_amd.calibrate run --out gpurun_out/calib_times.json
+  python -m paper_1303_5164_amd.calibrate fit --times T.json --counters A.csv B.csv ...
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import os
+import sys
+import time
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FREQ = 2.4e9
+PEAK_HBM = 8.0e12
+
+# counter passes (each within one run's hardware limits)
+PASSES = {
+    "inst": ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM", "SQ_INSTS_SMEM",
+             "SQ_INSTS_LDS", "SQ_INSTS_MFMA", "SQ_INSTS_BRANCH"],
+    "busy": ["SQ_INSTS_VALU_TRANS_F32", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES",
+             "SQ_WAIT_INST_ANY", "SQ_VALU_MFMA_BUSY_CYCLES", "GRBM_GUI_ACTIVE"],
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE"],
+}
+
+
+def run(out_path: str, reps: int = 3, scale: int = 1) -> dict:
+    import torch
+
+    import synth
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    F = synth.FULL
+    hosts = {
+        "poly": synth.poly(0, **F["poly"]),
+        "gather": synth.gather(0, **F["gather"]),
+        "sgemm": synth.sgemm(0, **F["sgemm"]),
+        "spmv": synth.spmv(0, **F["spmv"]),
+        "stencil": synth.stencil(0, F["stencil"]["ny"], F["stencil"]["nx"]),
+        "bs": synth.bs(0, F["bs"]["n"]),
+        "hist": synth.hist(0, F["hist"]["n"]),
+        "lookup": synth.lookup(0, **F["lookup"]),
+    }
+    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
+                              c1=F["stencil"]["c1"]),
+              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    rt = K.Runtime(0)
+    kids = {k: rt.register_builtin(k) for k in W.KERNELS}
+    out = {"n_cu": rt.cfg.n_cu, "kernels": {}}
+    for kind in W.TYPES:
+        d_in = W.device_inputs(kind, hosts[kind], dev)
+        inst = W.build(kind, d_in, params.get(kind, {}), dev)
+        names = sorted({ln.kernel or kind for ln in inst.launches})
+        for rep in range(reps + 1):
+            inst.reset()
+            torch.cuda.synchronize()
+            if rep == 1:
+                for nm in names:
+                    rt.time_kernel(kids[nm], True)
+            W.submit(rt, kids, inst)
+            rt.schedule("fifo", blocking=True, wait_done=True)
+            rt.synchronize()
+            rt.reap()
+        for nm in names:
+            ms, n, wg = rt.kernel_time(kids[nm])
+            info = rt.kernel_info(kids[nm])
+            out["kernels"][nm] = dict(avg_launch_ms=ms / max(n, 1), launches=n,
+                                      wgs_per_launch=wg / max(n, 1), **info)
+            rt.time_kernel(kids[nm], False)
+        print(f"# {kind}: " + ", ".join(
+            f"{nm} {out['kernels'][nm]['avg_launch_ms']:.4f} ms" for nm in names),
+            file=sys.stderr, flush=True)
+        del inst, d_in
+        torch.cuda.empty_cache()
+    rt.close()
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def read_counters(paths) -> dict:
+    """kernel short name -> counter -> mean value per dispatch."""
+    acc = defaultdict(lambda: defaultdict(list))
+    for p in paths:
+        with open(p) as f:
+            for row in csv.DictReader(f):
+                name = row.get("Kernel_Name", "").split("(")[0].strip()
+                if not name.startswith("kl_"):
+                    continue
+                cn = row.get("Counter_Name")
+                val = float(row.get("Counter_Value", "nan"))
+                acc[name[3:]][cn].append(val)
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+
+
+def fit(times_path: str, counter_paths, out_path: str) -> dict:
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import profiles
+
+    times = json.load(open(times_path))
+    n_cu = times["n_cu"]
+    cnt = read_counters(counter_paths)
+    est = profiles.ESTIMATES
+    prof = {}
+    for name, t in times["kernels"].items():
+        c = cnt.get(name)
+        if not c or "SQ_WAVES" not in c:
+            continue
+        waves = c["SQ_WAVES"]
+        total = sum(c.get(k, 0.0) for k in ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM",
+                                             "SQ_INSTS_SMEM", "SQ_INSTS_LDS", "SQ_INSTS_BRANCH"])
+        I = total / waves
+        T = t["avg_launch_ms"] / 1e3
+        pur = waves * I / (T * FREQ * n_cu)
+        dram = 1024.0 * (c.get("FETCH_SIZE", 0.0) + c.get("WRITE_SIZE", 0.0))
+        mur = dram / T / PEAK_HBM
+        vmem = c.get("SQ_INSTS_VMEM", 0.0)
+        r_mem = vmem / total
+        mfma = c.get("SQ_INSTS_MFMA", 0.0)
+        trans = c.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
+        r_comp = (mfma + trans) / total
+        lat_comp = 16.0 if mfma > trans else 4.0
+        mem_req = max(1.0, dram / 64.0 / vmem) if vmem > 0 else 1.0
+        occ = max(1, int(t["max_wg_per_cu"]))
+        p = dict(est.get(name, {}))
+        p.update(r_mem=r_mem, mem_req=mem_req, r_comp=r_comp if r_comp > 1e-4 else 0.0,
+                 lat_comp=lat_comp if r_comp > 1e-4 else 0.0, instr_per_wave=I,
+                 pur=pur, mur=mur, solo_ipc=pur, max_wg_per_cu=min(occ, 8),
+                 waves_per_simd=1, vgpr=int(t["vgpr"]), lds_bytes=int(t["lds_bytes"]))
+        # fit the memory latency so the model's solo IPC matches the measured
+        target = min(pur, 0.999)
+        w = p["max_wg_per_cu"]
+
+        def ipc_at(L):
+            q = dict(p, lat_mem=L)
+            return K.predict(q, None, w, 0)[0]
+
+        lo, hi = 1.0, 20000.0
+        if ipc_at(lo) <= target:
+            L = lo
+        elif ipc_at(hi) >= target:
+            L = hi
+        else:
+            for _ in range(60):
+                mid = (lo * hi) ** 0.5
+                if ipc_at(mid) > target:
+                    lo = mid
+                else:
+                    hi = mid
+            L = (lo * hi) ** 0.5
+        p["lat_mem"] = L
+        p["model_solo_ipc"] = ipc_at(L)
+        p["solo_ms"] = t["avg_launch_ms"]
+        prof[name] = p
+    meta = {"source": "calibrate.py fit over solo runs on MI355X",
+            "times": os.path.basename(times_path),
+            "counters": [os.path.basename(x) for x in counter_paths],
+            "freq_hz": FREQ, "n_cu": n_cu}
+    with open(out_path, "w") as f:
+        json.dump({"meta": meta, "profiles": prof}, f, indent=1, sort_keys=True)
+    return prof
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--out", required=True)
+    r.add_argument("--reps", type=int, default=3)
+    f = sub.add_parser("fit")
+    f.add_argument("--times", required=True)
+    f.add_argument("--counters", nargs="+", required=True)
+    f.add_argument("--out", default=os.path.join(HERE, "profiles_mi355x.json"))
+    a = ap.parse_args()
+    if a.cmd == "run":
+        t0 = time.time()
+        run(a.out, a.reps)
+        print(f"# calibration run {time.time() - t0:.1f} s", file=sys.stderr)
+    else:
+        prof = fit(a.times, a.counters, a.out)
+        for k, v in prof.items():
+            print(f"{k:13s} I={v['instr_per_wave']:9.1f} r_mem={v['r_mem']:.4f} "
+                  f"r_comp={v['r_comp']:.4f} pur={v['pur']:.3f} mur={v['mur']:.3f} "
+                  f"occ={v['max_wg_per_cu']} L={v['lat_mem']:.1f} req={v['mem_req']:.1f}")
+
+
+if __name__ == "__main__":
+    main()

@@ -725,6 +725,34 @@ kl_status kernelet_register(kl_runtime* rt, const kl_kernel_desc* d, kl_kernel* 
     return KL_OK;
 }
 
+kl_status kernelet_kernel_info(kl_runtime* rt, kl_kernel k, int32_t* max_wg_per_cu,
+                               int32_t* vgpr, int32_t* lds_bytes) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    const void* fn;
+    uint32_t block;
+    {
+        std::lock_guard<std::mutex> g(rt->mu);
+        if (k < 0 || k >= (int)rt->kernels.size()) {
+            set_error("kernelet_kernel_info: unknown kernel");
+            return KL_ENOTFOUND;
+        }
+        fn = rt->kernels[k].fn;
+        block = rt->kernels[k].block;
+    }
+    KL_HIP(hipSetDevice(rt->device));
+    hipFuncAttributes attr;
+    KL_HIP(hipFuncGetAttributes(&attr, fn));
+    int nb = 0;
+    KL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)block, 0));
+    if (max_wg_per_cu) *max_wg_per_cu = nb;
+    if (vgpr) *vgpr = attr.numRegs;
+    if (lds_bytes) *lds_bytes = (int32_t)attr.sharedSizeBytes;
+    return KL_OK;
+}
+
 kl_status kernelet_set_profile(kl_runtime* rt, kl_kernel k, const kl_profile* p) {
     if (!rt || !p) {
         set_error("kernelet_set_profile: null argument");

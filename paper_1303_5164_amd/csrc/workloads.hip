@@ -161,34 +161,51 @@ __global__ __launch_bounds__(KL_WG) void kl_spmv(kl_spmv_args a, kl_slice s) {
 }
 
 // --------------------------------------------------------------- stencil
-// 64 x 16 cells per workgroup; each thread walks 4 rows of one column and
-// keeps the vertical neighbours in registers.  Original grid:
-// (ceil(nx/64), ceil(ny/16), 1).
+// 256 x 32 cells per workgroup.  Each wave covers 256 consecutive cells of a
+// row (four per lane, one 16-byte access) and walks 8 rows, keeping the rows
+// above and below in registers; the west / east neighbours of a lane's four
+// cells come from the adjacent lanes by shuffles, and from memory at the
+// two ends of the wave.  Original grid: (ceil(nx/256), ceil(ny/32), 1).
+__device__ __forceinline__ float st_cell(float c0, float c1, float mid, float n, float s,
+                                         float w, float e) {
+    return __builtin_fmaf(c1, (n + s) + (w + e), c0 * mid);
+}
+
 __global__ __launch_bounds__(KL_WG) void kl_stencil(kl_stencil_args a, kl_slice s) {
     const uint32_t lin = kl_wg_linear(s);
     const uint32_t bx = lin % s.gx, by = lin / s.gx;
-    const uint32_t x = bx * 64 + threadIdx.x % 64;
-    const uint32_t y0 = by * 16 + (threadIdx.x / 64) * 4;
+    const int lane = threadIdx.x & 63;
     const uint32_t nx = a.nx, ny = a.ny;
-    if (x >= nx || y0 >= ny) return;
+    const uint32_t x0 = bx * 256 + lane * 4;
+    const uint32_t y0 = by * 32 + (threadIdx.x >> 6) * 8;
+    if (y0 >= ny) return;                   // uniform over the wave
+    const bool act = x0 < nx;               // nx % 4 == 0: all four cells or none
+    const uint32_t xc = act ? x0 : nx - 4;  // in-range column for idle lanes' loads
     const float* __restrict__ in = a.in;
     float* __restrict__ out = a.out;
-    const bool xedge = x == 0 || x == nx - 1;
-    float up = y0 > 0 ? in[(size_t)(y0 - 1) * nx + x] : 0.0f;
-    float mid = in[(size_t)y0 * nx + x];
-    for (int r = 0; r < 4; ++r) {
+    const float c0 = a.c0, c1 = a.c1;
+    const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 up = y0 > 0 ? *(const float4*)(in + (size_t)(y0 - 1) * nx + xc) : zero;
+    float4 mid = *(const float4*)(in + (size_t)y0 * nx + xc);
+    for (int r = 0; r < 8; ++r) {
         const uint32_t y = y0 + r;
-        if (y >= ny) break;
-        const size_t q = (size_t)y * nx + x;
-        const float down = y + 1 < ny ? in[q + nx] : 0.0f;
-        float v;
-        if (xedge || y == 0 || y == ny - 1) {
-            v = mid;
-        } else {
-            const float nsum = (up + down) + (in[q - 1] + in[q + 1]);
-            v = __builtin_fmaf(a.c1, nsum, a.c0 * mid);
+        if (y >= ny) break;                 // uniform over the wave
+        const size_t row = (size_t)y * nx;
+        const float4 down = y + 1 < ny ? *(const float4*)(in + row + nx + xc) : zero;
+        float w = __shfl_up(mid.w, 1);
+        float e = __shfl_down(mid.x, 1);
+        if (lane == 0) w = (act && x0 > 0) ? in[row + x0 - 1] : 0.0f;
+        if (lane == 63) e = (act && x0 + 4 < nx) ? in[row + x0 + 4] : 0.0f;
+        if (act) {
+            float4 v = mid;
+            if (y != 0 && y != ny - 1) {
+                if (x0 != 0) v.x = st_cell(c0, c1, mid.x, up.x, down.x, w, mid.y);
+                v.y = st_cell(c0, c1, mid.y, up.y, down.y, mid.x, mid.z);
+                v.z = st_cell(c0, c1, mid.z, up.z, down.z, mid.y, mid.w);
+                if (x0 + 3 != nx - 1) v.w = st_cell(c0, c1, mid.w, up.w, down.w, mid.z, e);
+            }
+            *(float4*)(out + row + x0) = v;
         }
-        out[q] = v;
         up = mid;
         mid = down;
     }
@@ -249,56 +266,113 @@ __global__ __launch_bounds__(KL_WG) void kl_hist(kl_hist_args a, kl_slice s) {
 }
 
 // ---------------------------------------------------------------- lookup
-// lower_bound of four queries per thread.  Each workgroup first loads the
-// last key of each of (up to) 1024 equal segments into LDS, finds the
-// segment of each query there, then finishes inside that segment in global
-// memory.  Both searches take a fixed number of steps (binary lifting), so
-// the four searches of a thread advance in lock step.
+// lower_bound through a static 16-ary tree whose nodes are 64-byte lines:
+// the leaves are the keys themselves (16 per line), level 1 holds the
+// largest key of every leaf line, level k + 1 the largest entry of every
+// 16-entry node of level k, up to a top level of at most 1024 entries that
+// each workgroup keeps in LDS.  A query costs a binary search in LDS and
+// then one line per level.  Levels start on 64-byte boundaries; the tail of
+// each level's last node is padded with 0xffffffff.
+struct LkLevels {
+    uint32_t nlev;
+    uint64_t off[8];  // first entry of each level (level 1 first)
+    uint64_t m[8];    // entries of each level
+    uint64_t total;   // entries including padding
+};
+
+__host__ __device__ inline void lk_levels(uint32_t n, LkLevels* L) {
+    uint64_t m = ((uint64_t)n + 15) / 16, off = 0;
+    L->nlev = 0;
+    for (;;) {
+        L->m[L->nlev] = m;
+        L->off[L->nlev] = off;
+        L->nlev++;
+        off += (m + 15) / 16 * 16;
+        if (m <= 1024) break;
+        m = (m + 15) / 16;
+    }
+    L->total = off;
+}
+
 __device__ __forceinline__ uint32_t kl_highbit(uint32_t v) {
     return v ? 1u << (31 - __builtin_clz(v)) : 0u;
 }
 
-__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
-    constexpr uint32_t S = 1024;
-    __shared__ uint32_t sp[S];
-    const uint32_t n = a.nkeys;
-    const uint32_t seg = (n + S - 1) / S;
-    const uint32_t nseg = (n + seg - 1) / seg;
-    for (uint32_t i = threadIdx.x; i < nseg; i += KL_WG) {
-        const uint64_t end = (uint64_t)(i + 1) * seg;
-        sp[i] = a.keys[(end < n ? end : n) - 1];
+__global__ __launch_bounds__(KL_WG) void kl_lookup_index(kl_lookup_args a, kl_slice s) {
+    LkLevels L;
+    lk_levels(a.nkeys, &L);
+    const uint64_t e = (uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x;
+    if (e >= L.total) return;
+    uint32_t k = 0;
+    while (k + 1 < L.nlev && e >= L.off[k + 1]) ++k;
+    const uint64_t i = e - L.off[k];
+    uint32_t v = 0xffffffffu;
+    if (i < L.m[k]) {
+        // entry i of level k + 1 covers keys [16^(k+1) i, 16^(k+1) (i + 1))
+        const uint64_t span = 1ull << (4 * (k + 1));
+        uint64_t last = (i + 1) * span;
+        if (last > a.nkeys) last = a.nkeys;
+        v = a.keys[last - 1];
     }
+    a.index[e] = v;
+}
+
+__device__ __forceinline__ uint32_t lk_count16(const uint32_t* p, uint32_t q) {
+    const uint4* v = (const uint4*)p;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint4 x = v[j];
+        c += (x.x < q) + (x.y < q) + (x.z < q) + (x.w < q);
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
+    __shared__ uint32_t top[1024];
+    LkLevels L;
+    lk_levels(a.nkeys, &L);
+    const uint32_t T = L.nlev - 1;
+    const uint32_t mt = (uint32_t)L.m[T];
+    for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[L.off[T] + i];
     __syncthreads();
     const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
     if (t0 >= a.nq) return;
     const uint4 qv = *(const uint4*)(a.q + t0);
     const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
     uint32_t c[4] = {0, 0, 0, 0};
-    for (uint32_t st = kl_highbit(nseg); st; st >>= 1)
+    for (uint32_t st = kl_highbit(mt); st; st >>= 1)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-            if (c[i] + st <= nseg && sp[c[i] + st - 1] < q[i]) c[i] += st;
-    uint32_t lo[4], len[4], cnt[4] = {0, 0, 0, 0};
+            if (c[i] + st <= mt && top[c[i] + st - 1] < q[i]) c[i] += st;
+    bool past[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) past[i] = c[i] >= mt;  // above every key
+    const uint32_t* __restrict__ idx = a.index;
+    for (int k = (int)T - 1; k >= 0; --k) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (!past[i]) c[i] = 16 * c[i] + lk_count16(idx + L.off[k] + 16 * (uint64_t)c[i], q[i]);
+    }
+    const uint32_t n = a.nkeys;
+    const uint32_t* __restrict__ keys = a.keys;
+    int4 o;
+    int* op = &o.x;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        if (c[i] >= nseg) {
-            lo[i] = n;
-            len[i] = 0;
-        } else {
-            lo[i] = c[i] * seg;
-            len[i] = n - lo[i] < seg ? n - lo[i] : seg;
+        uint32_t r = n;
+        if (!past[i]) {
+            const uint64_t base = 16 * (uint64_t)c[i];
+            if (base + 16 <= n) {
+                r = (uint32_t)base + lk_count16(keys + base, q[i]);
+            } else {
+                uint32_t cnt = 0;
+                for (uint64_t j = base; j < n; ++j) cnt += keys[j] < q[i];
+                r = (uint32_t)base + cnt;
+            }
         }
+        op[i] = (int)r;
     }
-    const uint32_t* __restrict__ keys = a.keys;
-    for (uint32_t st = kl_highbit(seg); st; st >>= 1)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (cnt[i] + st <= len[i] && keys[lo[i] + cnt[i] + st - 1] < q[i]) cnt[i] += st;
-    int4 o;
-    o.x = (int)(lo[0] + cnt[0]);
-    o.y = (int)(lo[1] + cnt[1]);
-    o.z = (int)(lo[2] + cnt[2]);
-    o.w = (int)(lo[3] + cnt[3]);
     *(int4*)(a.out + t0) = o;
 }
 
@@ -371,8 +445,10 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         KL_ARGS(kl_stencil_args);
         if (!a.in || !a.out || a.nx == 0 || a.ny == 0) return "null pointer or empty grid";
         if (a.in == a.out) return "stencil in and out must differ";
-        g->x = cdiv(a.nx, 64);
-        g->y = cdiv(a.ny, 16);
+        if (a.nx % 4) return "stencil nx must be a multiple of 4";
+        if (!aligned16(a.in) || !aligned16(a.out)) return "stencil in, out must be 16-byte aligned";
+        g->x = cdiv(a.nx, 256);
+        g->y = cdiv(a.ny, 32);
     } else if (n == "bs") {
         KL_ARGS(kl_bs_args);
         if (!a.s || !a.k || !a.t || !a.call || !a.put || a.n == 0 || a.n % 4)
@@ -393,12 +469,21 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         if (!a.visits || !a.info || a.n_wg == 0) return "null pointer or n_wg == 0";
         if (a.spin > (1u << 24)) return "spin above 2^24";
         g->x = a.n_wg;
-    } else if (n == "lookup") {
+    } else if (n == "lookup" || n == "lookup_index") {
         KL_ARGS(kl_lookup_args);
-        if (!a.keys || !a.q || !a.out || a.nkeys == 0 || a.nq == 0 || a.nq % 4)
-            return "null pointer, nkeys == 0, or nq not a positive multiple of 4";
-        if (!aligned16(a.q) || !aligned16(a.out)) return "q, out must be 16-byte aligned";
-        g->x = cdiv(a.nq, 4 * KL_WG);
+        if (!a.keys || !a.index || a.nkeys == 0 || a.nkeys > 0x7fffffffu)
+            return "null keys or index, or nkeys outside [1, 2^31 - 1]";
+        if (!aligned16(a.keys) || !aligned16(a.index)) return "keys, index must be 16-byte aligned";
+        if (n == "lookup_index") {
+            LkLevels L;
+            lk_levels(a.nkeys, &L);
+            g->x = cdiv(L.total, KL_WG);
+        } else {
+            if (!a.q || !a.out || a.nq == 0 || a.nq % 4)
+                return "null q or out, or nq not a positive multiple of 4";
+            if (!aligned16(a.q) || !aligned16(a.out)) return "q, out must be 16-byte aligned";
+            g->x = cdiv(a.nq, 4 * KL_WG);
+        }
     } else {
         return "unknown built-in kernel";
     }
@@ -422,10 +507,18 @@ const BuiltinEntry kBuiltins[] = {
     {"bs", (const void*)kl_bs, sizeof(kl_bs_args), KL_KF_IDEMPOTENT},
     {"hist", (const void*)kl_hist, sizeof(kl_hist_args), 0u},
     {"lookup", (const void*)kl_lookup, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
+    {"lookup_index", (const void*)kl_lookup_index, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
     {"probe", (const void*)kl_probe, sizeof(kl_probe_args), 0u},
 };
 
 }  // namespace
+
+extern "C" uint64_t kernelet_lookup_index_entries(uint32_t nkeys) {
+    if (nkeys == 0) return 0;
+    LkLevels L;
+    lk_levels(nkeys, &L);
+    return L.total;
+}
 
 namespace kl {
 void set_error(const std::string& msg);

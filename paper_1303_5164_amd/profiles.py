@@ -35,6 +35,8 @@ ESTIMATES = {
                  lds_bytes=4096, pur=0.50, mur=0.50),
     "lookup": dict(_COMMON, r_mem=0.25, mem_req=64, instr_per_wave=150, max_wg_per_cu=8,
                    lds_bytes=4096, pur=0.10, mur=0.30),
+    "lookup_index": dict(_COMMON, r_mem=0.2, mem_req=64, instr_per_wave=40, max_wg_per_cu=8,
+                         pur=0.1, mur=0.5),
     "probe": dict(_COMMON, r_mem=0.001, mem_req=1, instr_per_wave=1000, max_wg_per_cu=8,
                   pur=0.5, mur=0.0),
 }

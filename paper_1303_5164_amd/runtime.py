@@ -115,6 +115,12 @@ class Runtime:
     def register_builtin(self, name: str, profile=None) -> int:
         return self.register(builtin_desc(name), profile)
 
+    def kernel_info(self, k: int) -> dict:
+        """Workgroups per CU alone, VGPRs per lane and static LDS of kernel k."""
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        call("kernelet_kernel_info", self.h, k, C.byref(a), C.byref(b), C.byref(c))
+        return {"max_wg_per_cu": a.value, "vgpr": b.value, "lds_bytes": c.value}
+
     def set_profile(self, k: int, profile) -> None:
         p = make_profile(profile)
         call("kernelet_set_profile", self.h, k, C.byref(p))

@@ -18,12 +18,15 @@ from . import _lib
 from .runtime import builtin_grid
 
 TYPES = ["poly", "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup"]
+# every built-in kernel the instances launch (the lookup builds its tree first)
+KERNELS = TYPES + ["lookup_index"]
 
 
 @dataclass
 class Launch:
     args: object        # ctypes argument block
     grid: tuple
+    kernel: str = ""    # built-in kernel name ("" = the instance's kind)
 
 
 @dataclass
@@ -34,6 +37,7 @@ class Instance:
     outputs: list = field(default_factory=list)
     footprint: int = 0
     result: str = ""    # name of the tensor holding the final result
+    inputs: dict = field(default_factory=dict)  # kept alive while the instance is
 
     def reset(self):
         """Zero what must start at zero before the instance runs again."""
@@ -104,7 +108,7 @@ def build(kind: str, dev_in: dict, params: dict, device) -> Instance:
             src = dst
         res = "b0" if (iters - 1) % 2 == 0 else "b1"
         fp = sum(t.numel() * t.element_size() for t in T.values()) + dev_in["u"].numel() * 4
-        return Instance(kind, launches, T, [res], fp, res)
+        return Instance(kind, launches, T, [res], fp, res, dict(dev_in))
     elif kind == "bs":
         n = dev_in["s"].numel()
         T["call"] = torch.empty(n, dtype=torch.float32, device=device)
@@ -119,15 +123,22 @@ def build(kind: str, dev_in: dict, params: dict, device) -> Instance:
         res = "bins"
     elif kind == "lookup":
         nq = dev_in["q"].numel()
+        nk = dev_in["keys"].numel()
         T["out"] = torch.empty(nq, dtype=torch.int32, device=device)
-        a = A(_ptr(dev_in["keys"]), _ptr(dev_in["q"]), _ptr(T["out"]),
-              dev_in["keys"].numel(), nq)
-        res = "out"
+        ne = int(_lib.lib().kernelet_lookup_index_entries(nk))
+        T["index"] = torch.empty(max(ne, 4), dtype=torch.int32, device=device)
+        a = A(_ptr(dev_in["keys"]), _ptr(dev_in["q"]), _ptr(T["out"]), _ptr(T["index"]),
+              nk, nq)
+        fp = sum(t.numel() * t.element_size() for t in T.values()) + sum(
+            t.numel() * t.element_size() for t in dev_in.values())
+        launches = [Launch(a, builtin_grid("lookup_index", a), "lookup_index"),
+                    Launch(a, builtin_grid("lookup", a), "lookup")]
+        return Instance(kind, launches, T, ["out"], fp, "out", dict(dev_in))
     else:
         raise KeyError(kind)
     fp = sum(t.numel() * t.element_size() for t in T.values()) + sum(
         t.numel() * t.element_size() for t in dev_in.values())
-    return Instance(kind, [Launch(a, builtin_grid(kind, a))], T, [res], fp, res)
+    return Instance(kind, [Launch(a, builtin_grid(kind, a))], T, [res], fp, res, dict(dev_in))
 
 
 def submit(rt, kernel_ids: dict, inst: Instance, client: int = 0, after: int = -1):
@@ -135,7 +146,7 @@ def submit(rt, kernel_ids: dict, inst: Instance, client: int = 0, after: int = -
     jobs = []
     prev = after
     for ln in inst.launches:
-        prev = rt.submit(kernel_ids[inst.kind], ln.grid, ln.args, after=prev,
+        prev = rt.submit(kernel_ids[ln.kernel or inst.kind], ln.grid, ln.args, after=prev,
                          client=client, footprint=inst.footprint if not jobs else 0)
         jobs.append(prev)
     return jobs

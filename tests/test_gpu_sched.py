@@ -22,6 +22,10 @@ def rtk():
     prof = profiles.load()
     for k, i in kids.items():
         rt.set_profile(i, prof[k])
+    # the probe again under another name: a second kernel type to co-run
+    d = K.builtin_desc("probe")
+    d.name = b"probe2"
+    kids["probe2"] = rt.register(d, prof["probe"])
     yield rt, kids
     rt.close()
 
@@ -56,7 +60,7 @@ def test_coscheduled_probes_run_once_and_overlap(rtk):
     v2, i2, a2 = _probe(rt, kids, 4096, spin=4000)
     torch.cuda.synchronize()
     j1 = rt.submit(kids["probe"], (4096, 1, 1), a1)
-    j2 = rt.submit(kids["probe"], (4096, 1, 1), a2)
+    j2 = rt.submit(kids["probe2"], (4096, 1, 1), a2)
     rt.slice(j1, 512)
     rt.slice(j2, 512)
     rt.schedule("fixed")
@@ -106,8 +110,9 @@ def test_mix_same_bits_as_fifo(rtk, policy):
         rt.synchronize()
         outs[pol] = [result(i) for i in insts]
         rt.reap()
-    for inst, a, b in zip(insts, outs["fifo"], outs[policy]):
-        assert a.tobytes() == b.tobytes(), inst.kind
+    bad = [(i.kind, int(np.sum(a != b))) for i, a, b in zip(insts, outs["fifo"], outs[policy])
+           if not np.array_equal(a, b)]
+    assert not bad, f"outputs differ from FIFO (kind, #elements): {bad}"
     dec = rt.decisions()
     if policy == "markov":
         assert any(d["j2"] >= 0 for d in dec), "no co-schedule was chosen"

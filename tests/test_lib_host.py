@@ -141,7 +141,14 @@ def test_builtin_descriptors_and_grids():
     a = _lib.SgemmArgs(16, 16, 16, 4096, 4096, 4096)
     assert K.builtin_grid("sgemm", a) == (1024, 1, 1)
     a = _lib.StencilArgs(16, 32, 8192, 8192, 0.5, 0.125)
-    assert K.builtin_grid("stencil", a) == (128, 512, 1)
+    assert K.builtin_grid("stencil", a) == (32, 256, 1)
+    a = _lib.StencilArgs(16, 32, 10, 102, 0.5, 0.125)     # nx not a multiple of 4
+    with pytest.raises(K.KerneletError):
+        K.builtin_grid("stencil", a)
+    a = _lib.LookupArgs(16, 16, 16, 16, 1 << 26, 1 << 26)
+    assert K.builtin_grid("lookup", a) == (1 << 16, 1, 1)
+    assert K.builtin_grid("lookup_index", a) == (4473856 // 256, 1, 1)
+    assert _lib.lib().kernelet_lookup_index_entries(1 << 26) == 4473856
     a = _lib.SgemmArgs(16, 16, 16, 100, 4096, 4096)
     with pytest.raises(K.KerneletError) as e:
         K.builtin_grid("sgemm", a)

@@ -162,6 +162,10 @@ kl_status kernelet_default_config(kl_config* cfg);
  * defaults) is copied.  The runtime owns its streams, events and threads. */
 kl_status kernelet_init(kl_runtime** rt, int hip_device, const kl_config* cfg);
 
+/* Copy the runtime's effective configuration (with n_cu filled in from the
+ * device) to *cfg (host). */
+kl_status kernelet_get_config(kl_runtime* rt, kl_config* cfg);
+
 /* Wait for every launched slice, stop the scheduler thread, free all. */
 kl_status kernelet_shutdown(kl_runtime* rt);
 

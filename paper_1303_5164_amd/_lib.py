@@ -120,7 +120,7 @@ ARGS = {"probe": ProbeArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": Sge
 
 # every symbol include/kernelet.h declares
 SYMBOLS = [
-    "kernelet_default_config", "kernelet_init", "kernelet_shutdown",
+    "kernelet_default_config", "kernelet_init", "kernelet_get_config", "kernelet_shutdown",
     "kernelet_last_error", "kernelet_register", "kernelet_builtin",
     "kernelet_builtin_grid", "kernelet_set_profile", "kernelet_get_profile",
     "kernelet_submit", "kernelet_slice", "kernelet_schedule", "kernelet_wait",
@@ -147,12 +147,18 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1303_5164_amd.build`")
-    L = C.CDLL(LIB_PATH)
+    _lib = configure(C.CDLL(LIB_PATH))
+    return _lib
+
+
+def configure(L):
+    """Declare the C signatures of kernelet.h on a loaded library."""
     i32, i64, u32, u64, dbl = C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_double
     PD = C.POINTER(dbl)
     sig = {
         "kernelet_default_config": [C.POINTER(Config)],
         "kernelet_init": [C.POINTER(C.c_void_p), C.c_int, C.POINTER(Config)],
+        "kernelet_get_config": [C.c_void_p, C.POINTER(Config)],
         "kernelet_shutdown": [C.c_void_p],
         "kernelet_register": [C.c_void_p, C.POINTER(KernelDesc), C.POINTER(i32)],
         "kernelet_builtin": [C.c_char_p, C.POINTER(KernelDesc)],
@@ -187,20 +193,24 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = i32
-    L.kernelet_lookup_index_entries.argtypes = [C.c_uint32]
-    L.kernelet_lookup_index_entries.restype = C.c_uint64
+    if hasattr(L, "kernelet_lookup_index_entries"):
+        L.kernelet_lookup_index_entries.argtypes = [C.c_uint32]
+        L.kernelet_lookup_index_entries.restype = C.c_uint64
     L.kernelet_last_error.argtypes = []
     L.kernelet_last_error.restype = C.c_char_p
-    _lib = L
     return L
 
 
-def check(name, code):
+def check(name, code, L=None):
     if code != KL_OK:
-        msg = lib().kernelet_last_error().decode(errors="replace")
+        msg = (L or lib()).kernelet_last_error().decode(errors="replace")
         raise KerneletError(name, code, msg)
     return code
 
 
 def call(name, *args):
     return check(name, getattr(lib(), name)(*args))
+
+
+def call_on(L, name, *args):
+    return check(name, getattr(L, name)(*args), L)

@@ -77,9 +77,19 @@ def run(out_path: str, reps: int = 3, scale: int = 1) -> dict:
     params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
                               c1=F["stencil"]["c1"]),
               "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    # a plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE
+    # readings scale the counters of the kernels below to bytes
+    copy_bytes = 1 << 30
+    src = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
     rt = K.Runtime(0)
     kids = {k: rt.register_builtin(k) for k in W.KERNELS}
-    out = {"n_cu": rt.cfg.n_cu, "kernels": {}}
+    out = {"n_cu": rt.cfg.n_cu, "copy_bytes": copy_bytes, "kernels": {}}
     for kind in W.TYPES:
         d_in = W.device_inputs(kind, hosts[kind], dev)
         inst = W.build(kind, d_in, params.get(kind, {}), dev)
@@ -111,29 +121,115 @@ def run(out_path: str, reps: int = 3, scale: int = 1) -> dict:
     return out
 
 
+def run_slices(out_path: str, reps: int = 5, p: float = 0.02) -> dict:
+    """Minimum slice of each kernel (Section 4.1): the smallest slice of
+    b * n_cu workgroups (b = 1, 2, 4, ...) whose sliced execution takes at
+    most (1 + p) times the unsliced one; 0 when no slice size qualifies."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    F = synth.FULL
+    hosts = {
+        "poly": lambda: synth.poly(0, **F["poly"]),
+        "gather": lambda: synth.gather(0, **F["gather"]),
+        "sgemm": lambda: synth.sgemm(0, **F["sgemm"]),
+        "spmv": lambda: synth.spmv(0, **F["spmv"]),
+        "stencil": lambda: synth.stencil(0, F["stencil"]["ny"], F["stencil"]["nx"]),
+        "bs": lambda: synth.bs(0, F["bs"]["n"]),
+        "hist": lambda: synth.hist(0, F["hist"]["n"]),
+        "lookup": lambda: synth.lookup(0, **F["lookup"]),
+    }
+    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
+                              c1=F["stencil"]["c1"]),
+              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    rt = K.Runtime(0)
+    kids = {k: rt.register_builtin(k) for k in W.KERNELS}
+    n_cu = rt.cfg.n_cu
+    assert n_cu > 0
+
+    def wall(inst, slice_wgs):
+        ts = []
+        for _ in range(reps + 1):
+            inst.reset()
+            torch.cuda.synchronize()
+            jobs = W.submit(rt, kids, inst)
+            if slice_wgs:
+                for j in jobs:
+                    rt.slice(j, slice_wgs)
+            t0 = time.perf_counter()
+            rt.schedule("fixed" if slice_wgs else "fifo", blocking=True, wait_done=True)
+            rt.synchronize()
+            ts.append(time.perf_counter() - t0)
+            rt.reap()
+        return float(np.median(ts[1:]))
+
+    out = {"n_cu": n_cu, "p": p, "kernels": {}}
+    for kind in W.TYPES:
+        d_in = W.device_inputs(kind, hosts[kind](), dev)
+        inst = W.build(kind, d_in, params.get(kind, {}), dev)
+        most = max(ln.grid[0] * ln.grid[1] * ln.grid[2] for ln in inst.launches)
+        t_ns = wall(inst, 0)
+        rows, best = [], 0
+        b = 1
+        while b * n_cu < most and b <= 1024:
+            t_s = wall(inst, b * n_cu)
+            ov = t_s / t_ns - 1.0
+            rows.append({"b": b, "slice_wgs": b * n_cu, "ms": t_s * 1e3, "overhead": ov})
+            if ov <= p and best == 0:
+                best = b * n_cu
+            b *= 2
+        out["kernels"][kind] = {"unsliced_ms": t_ns * 1e3, "largest_launch_wgs": most,
+                                "min_slice_wgs": best, "sweep": rows}
+        print(f"# {kind}: unsliced {t_ns * 1e3:.3f} ms; " + ", ".join(
+            f"{r['slice_wgs']}:{100 * r['overhead']:+.1f}%" for r in rows), file=sys.stderr,
+            flush=True)
+        del inst, d_in
+        torch.cuda.empty_cache()
+    rt.close()
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def read_counters(paths) -> dict:
-    """kernel short name -> counter -> mean value per dispatch."""
+    """kernel short name -> counter -> mean value per dispatch; the largest
+    reading of each counter over copy kernels goes under "_copy"."""
     acc = defaultdict(lambda: defaultdict(list))
+    copy = defaultdict(float)
     for p in paths:
         with open(p) as f:
             for row in csv.DictReader(f):
                 name = row.get("Kernel_Name", "").split("(")[0].strip()
-                if not name.startswith("kl_"):
-                    continue
                 cn = row.get("Counter_Name")
                 val = float(row.get("Counter_Value", "nan"))
-                acc[name[3:]][cn].append(val)
-    return {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+                if name.startswith("kl_"):
+                    acc[name[3:]][cn].append(val)
+                elif "copy" in name.lower():
+                    copy[cn] = max(copy[cn], val)
+    out = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in acc.items()}
+    out["_copy"] = dict(copy)
+    return out
 
 
-def fit(times_path: str, counter_paths, out_path: str) -> dict:
+def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict:
     import paper_1303_5164_amd as K
     from paper_1303_5164_amd import profiles
 
     times = json.load(open(times_path))
+    slices = json.load(open(slices_path))["kernels"] if slices_path else {}
     n_cu = times["n_cu"]
     cnt = read_counters(counter_paths)
     est = profiles.ESTIMATES
+    # bytes per counted KiB, from the copy kernel (copy_bytes read and written)
+    cp = cnt.get("_copy", {})
+    cb = float(times.get("copy_bytes", 0))
+    f_fetch = cb / (1024.0 * cp["FETCH_SIZE"]) if cp.get("FETCH_SIZE") else 1.0
+    f_write = cb / (1024.0 * cp["WRITE_SIZE"]) if cp.get("WRITE_SIZE") else 1.0
     prof = {}
     for name, t in times["kernels"].items():
         c = cnt.get(name)
@@ -145,7 +241,9 @@ def fit(times_path: str, counter_paths, out_path: str) -> dict:
         I = total / waves
         T = t["avg_launch_ms"] / 1e3
         pur = waves * I / (T * FREQ * n_cu)
-        dram = 1024.0 * (c.get("FETCH_SIZE", 0.0) + c.get("WRITE_SIZE", 0.0))
+        fetch_b = 1024.0 * c.get("FETCH_SIZE", 0.0) * f_fetch
+        write_b = 1024.0 * c.get("WRITE_SIZE", 0.0) * f_write
+        dram = fetch_b + write_b
         mur = dram / T / PEAK_HBM
         vmem = c.get("SQ_INSTS_VMEM", 0.0)
         r_mem = vmem / total
@@ -184,11 +282,19 @@ def fit(times_path: str, counter_paths, out_path: str) -> dict:
         p["lat_mem"] = L
         p["model_solo_ipc"] = ipc_at(L)
         p["solo_ms"] = t["avg_launch_ms"]
+        p["fetch_bytes_per_launch"] = fetch_b
+        p["write_bytes_per_launch"] = write_b
+        p["wgs_per_launch"] = t["wgs_per_launch"]
+        kind = "lookup" if name == "lookup_index" else name
+        if kind in slices:
+            # 0 = no slice size met the overhead bound: never slice
+            p["min_slice_wgs"] = int(slices[kind]["min_slice_wgs"]) or 2147483647
         prof[name] = p
     meta = {"source": "calibrate.py fit over solo runs on MI355X",
             "times": os.path.basename(times_path),
             "counters": [os.path.basename(x) for x in counter_paths],
-            "freq_hz": FREQ, "n_cu": n_cu}
+            "freq_hz": FREQ, "n_cu": n_cu, "copy_scale_fetch": f_fetch,
+            "copy_scale_write": f_write, "copy_raw_kib": cp}
     with open(out_path, "w") as f:
         json.dump({"meta": meta, "profiles": prof}, f, indent=1, sort_keys=True)
     return prof
@@ -200,17 +306,23 @@ def main():
     r = sub.add_parser("run")
     r.add_argument("--out", required=True)
     r.add_argument("--reps", type=int, default=3)
+    s = sub.add_parser("slices")
+    s.add_argument("--out", required=True)
+    s.add_argument("--reps", type=int, default=5)
     f = sub.add_parser("fit")
     f.add_argument("--times", required=True)
     f.add_argument("--counters", nargs="+", required=True)
+    f.add_argument("--slices", default=None)
     f.add_argument("--out", default=os.path.join(HERE, "profiles_mi355x.json"))
     a = ap.parse_args()
     if a.cmd == "run":
         t0 = time.time()
         run(a.out, a.reps)
         print(f"# calibration run {time.time() - t0:.1f} s", file=sys.stderr)
+    elif a.cmd == "slices":
+        run_slices(a.out, a.reps)
     else:
-        prof = fit(a.times, a.counters, a.out)
+        prof = fit(a.times, a.counters, a.out, a.slices)
         for k, v in prof.items():
             print(f"{k:13s} I={v['instr_per_wave']:9.1f} r_mem={v['r_mem']:.4f} "
                   f"r_comp={v['r_comp']:.4f} pur={v['pur']:.3f} mur={v['mur']:.3f} "

@@ -660,6 +660,16 @@ kl_status kernelet_init(kl_runtime** out, int hip_device, const kl_config* cfg) 
     return KL_OK;
 }
 
+kl_status kernelet_get_config(kl_runtime* rt, kl_config* cfg) {
+    if (!rt || !cfg) {
+        set_error("kernelet_get_config: null argument");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    *cfg = rt->cfg;
+    return KL_OK;
+}
+
 kl_status kernelet_shutdown(kl_runtime* rt) {
     if (!rt) {
         set_error("null runtime");
@@ -946,7 +956,10 @@ kl_status kernelet_wait(kl_runtime* rt, kl_job jid, int64_t timeout_ns) {
             return KL_ENOTFOUND;
         }
         Job& j = it->second;
-        if (j.st == J_CANCELED) return KL_ECANCELED;
+        if (j.st == J_CANCELED) {
+            set_error("kernelet_wait: the job was cancelled");
+            return KL_ECANCELED;
+        }
         if (j.st == J_DONE) {
             if (j.error) {
                 set_error("kernelet_wait: a slice of the job failed on the device");

@@ -94,13 +94,27 @@ def _dec_dict(d: Decision) -> dict:
 class Runtime:
     """One kernelet runtime on one HIP device."""
 
-    def __init__(self, device: int = 0, cfg: Config | None = None, **over):
-        lib()
-        self.cfg = cfg if cfg is not None else default_config(**over)
+    def __init__(self, device: int = 0, cfg: Config | None = None, lib_handle=None, **over):
+        self._L = lib_handle if lib_handle is not None else lib()
+        if cfg is None:
+            cfg = Config()
+            self._c("kernelet_default_config", C.byref(cfg))
+            for k, v in over.items():
+                if k not in CONFIG_FIELDS:
+                    raise KeyError(k)
+                if k == "ratio_mode" and isinstance(v, str):
+                    v = _lib.MODE[v]
+                setattr(cfg, k, v)
         h = C.c_void_p()
-        call("kernelet_init", C.byref(h), device, C.byref(self.cfg))
+        self._c("kernelet_init", C.byref(h), device, C.byref(cfg))
         self.h = h
+        # the effective configuration (n_cu filled in from the device)
+        self.cfg = Config()
+        self._c("kernelet_get_config", self.h, C.byref(self.cfg))
         self.kernels = {}
+
+    def _c(self, name, *args):
+        return _lib.call_on(self._L, name, *args)
 
     # -------------------------------------------------------------- kernels
     def register(self, desc: KernelDesc, profile=None) -> int:
@@ -108,7 +122,7 @@ class Runtime:
             prof = make_profile(profile)
             desc.profile = C.pointer(prof)
         k = C.c_int32()
-        call("kernelet_register", self.h, C.byref(desc), C.byref(k))
+        self._c("kernelet_register", self.h, C.byref(desc), C.byref(k))
         self.kernels[desc.name.decode()] = k.value
         return k.value
 
@@ -118,16 +132,16 @@ class Runtime:
     def kernel_info(self, k: int) -> dict:
         """Workgroups per CU alone, VGPRs per lane and static LDS of kernel k."""
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        call("kernelet_kernel_info", self.h, k, C.byref(a), C.byref(b), C.byref(c))
+        self._c("kernelet_kernel_info", self.h, k, C.byref(a), C.byref(b), C.byref(c))
         return {"max_wg_per_cu": a.value, "vgpr": b.value, "lds_bytes": c.value}
 
     def set_profile(self, k: int, profile) -> None:
         p = make_profile(profile)
-        call("kernelet_set_profile", self.h, k, C.byref(p))
+        self._c("kernelet_set_profile", self.h, k, C.byref(p))
 
     def get_profile(self, k: int) -> dict:
         p = Profile()
-        call("kernelet_get_profile", self.h, k, C.byref(p))
+        self._c("kernelet_get_profile", self.h, k, C.byref(p))
         return profile_dict(p)
 
     # ----------------------------------------------------------------- jobs
@@ -135,13 +149,13 @@ class Runtime:
                footprint: int = 0) -> int:
         g = Dim3(*grid) if not isinstance(grid, Dim3) else grid
         j = C.c_int64()
-        call("kernelet_submit", self.h, k, g, C.byref(args), C.sizeof(args), after,
+        self._c("kernelet_submit", self.h, k, g, C.byref(args), C.sizeof(args), after,
              client, footprint, C.byref(j))
         return j.value
 
     def slice(self, job: int, wgs_per_slice: int) -> int:
         n = C.c_uint32()
-        call("kernelet_slice", self.h, job, wgs_per_slice, C.byref(n))
+        self._c("kernelet_slice", self.h, job, wgs_per_slice, C.byref(n))
         return n.value
 
     def schedule(self, policy: str = "markov", blocking: bool = True,
@@ -149,49 +163,49 @@ class Runtime:
         flags = (_lib.KL_BLOCKING if blocking else 0) | (
             _lib.KL_REPLAN_ON_ARRIVAL if replan_on_arrival else 0) | (
             _lib.KL_WAIT_DONE if wait_done else 0)
-        call("kernelet_schedule", self.h, _lib.POLICY[policy], flags)
+        self._c("kernelet_schedule", self.h, _lib.POLICY[policy], flags)
 
     def wait(self, job: int, timeout_ns: int = -1) -> None:
-        call("kernelet_wait", self.h, job, timeout_ns)
+        self._c("kernelet_wait", self.h, job, timeout_ns)
 
     def synchronize(self) -> None:
-        call("kernelet_synchronize", self.h)
+        self._c("kernelet_synchronize", self.h)
 
     def cancel(self, job: int) -> None:
-        call("kernelet_cancel", self.h, job)
+        self._c("kernelet_cancel", self.h, job)
 
     def job_times(self, job: int):
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
-        call("kernelet_job_times", self.h, job, C.byref(a), C.byref(b), C.byref(c))
+        self._c("kernelet_job_times", self.h, job, C.byref(a), C.byref(b), C.byref(c))
         return a.value, b.value, c.value
 
     def reap(self) -> None:
-        call("kernelet_reap", self.h)
+        self._c("kernelet_reap", self.h)
 
     # -------------------------------------------------------------- logging
     def time_kernel(self, k: int, enable: bool = True) -> None:
-        call("kernelet_time_kernel", self.h, k, int(enable))
+        self._c("kernelet_time_kernel", self.h, k, int(enable))
 
     def kernel_time(self, k: int):
         """(total ms, launches, workgroups) of kernel k's timed launches."""
         ms, n, w = C.c_double(), C.c_int64(), C.c_int64()
-        call("kernelet_kernel_time", self.h, k, C.byref(ms), C.byref(n), C.byref(w))
+        self._c("kernelet_kernel_time", self.h, k, C.byref(ms), C.byref(n), C.byref(w))
         return ms.value, n.value, w.value
 
     def stats(self) -> dict:
         s = Stats()
-        call("kernelet_stats", self.h, C.byref(s))
+        self._c("kernelet_stats", self.h, C.byref(s))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
 
     def decisions(self, max_n: int = 1 << 16) -> list:
         buf = (Decision * max_n)()
         n = C.c_int32()
-        call("kernelet_decisions", self.h, buf, max_n, C.byref(n))
+        self._c("kernelet_decisions", self.h, buf, max_n, C.byref(n))
         return [_dec_dict(buf[i]) for i in range(n.value)]
 
     def close(self) -> None:
         if self.h:
-            call("kernelet_shutdown", self.h)
+            self._c("kernelet_shutdown", self.h)
             self.h = None
 
     def __enter__(self):

@@ -1,0 +1,251 @@
+// TEST DOUBLE: host-thread implementation of hip_runtime.h (see there).
+#include "hip/hip_runtime.h"
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "kernelet.h"
+
+struct FakeEvent {
+    uint64_t recorded = 0, done = 0;
+    double t_done_ms = 0;
+    bool err = false;  // recorded after a failed kernel on its stream
+};
+
+namespace {
+std::mutex g_mu;                 // guards every stream, event and the kernel table
+std::condition_variable g_cv;
+int g_ncu = 256;
+
+typedef int (*fake_kernel_fn)(const void* args, const kl_slice* s);
+struct FakeKernel {
+    fake_kernel_fn fn;
+    uint32_t args_bytes;
+};
+std::map<const void*, FakeKernel> g_kernels;
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Op {
+    int kind;  // 0 launch, 1 record, 2 wait
+    FakeKernel k;
+    std::vector<uint8_t> args;
+    kl_slice slice;
+    FakeEvent* ev = nullptr;
+    uint64_t gen = 0;
+};
+}  // namespace
+
+struct FakeStream {
+    std::deque<Op> q;
+    bool busy = false, stop = false, failed = false;
+    std::thread th;
+};
+
+namespace {
+void stream_main(FakeStream* s) {
+    std::unique_lock<std::mutex> lk(g_mu);
+    for (;;) {
+        g_cv.wait(lk, [&] { return s->stop || !s->q.empty(); });
+        if (s->q.empty() && s->stop) return;
+        Op op = std::move(s->q.front());
+        s->q.pop_front();
+        s->busy = true;
+        if (op.kind == 0) {
+            lk.unlock();
+            int rc = op.k.fn(op.args.data(), &op.slice);
+            lk.lock();
+            if (rc) s->failed = true;
+        } else if (op.kind == 1) {
+            if (op.gen > op.ev->done) {
+                op.ev->done = op.gen;
+                op.ev->t_done_ms = now_ms();
+                op.ev->err = s->failed;
+            }
+        } else {
+            g_cv.wait(lk, [&] { return op.ev->done >= op.gen; });
+        }
+        s->busy = false;
+        g_cv.notify_all();
+    }
+}
+}  // namespace
+
+extern "C" {
+// Register a host function that stands for a GPU kernel.
+void fake_register_kernel(const void* key, fake_kernel_fn fn, uint32_t args_bytes) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_kernels[key] = FakeKernel{fn, args_bytes};
+}
+void fake_set_cu(int n) { g_ncu = n; }
+}
+
+hipError_t hipGetDeviceCount(int* n) {
+    *n = 1;
+    return hipSuccess;
+}
+hipError_t hipSetDevice(int d) { return d == 0 ? hipSuccess : hipErrorInvalidValue; }
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int) {
+    std::memset(p, 0, sizeof(*p));
+    p->multiProcessorCount = g_ncu;
+    std::strcpy(p->name, "fake");
+    return hipSuccess;
+}
+hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) {
+    auto* st = new FakeStream();
+    st->th = std::thread(stream_main, st);
+    *s = st;
+    return hipSuccess;
+}
+hipError_t hipStreamDestroy(hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        s->stop = true;
+    }
+    g_cv.notify_all();
+    s->th.join();
+    delete s;
+    return hipSuccess;
+}
+hipError_t hipStreamSynchronize(hipStream_t s) {
+    std::unique_lock<std::mutex> lk(g_mu);
+    g_cv.wait(lk, [&] { return s->q.empty() && !s->busy; });
+    return s->failed ? hipErrorLaunchFailure : hipSuccess;
+}
+hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (e->recorded > e->done) {
+        Op op;
+        op.kind = 2;
+        op.ev = e;
+        op.gen = e->recorded;
+        s->q.push_back(std::move(op));
+        g_cv.notify_all();
+    }
+    return hipSuccess;
+}
+hipError_t hipEventCreate(hipEvent_t* e) {
+    *e = new FakeEvent();
+    return hipSuccess;
+}
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { return hipEventCreate(e); }
+hipError_t hipEventDestroy(hipEvent_t e) {
+    delete e;
+    return hipSuccess;
+}
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_mu);
+    Op op;
+    op.kind = 1;
+    op.ev = e;
+    op.gen = ++e->recorded;
+    s->q.push_back(std::move(op));
+    g_cv.notify_all();
+    return hipSuccess;
+}
+hipError_t hipEventQuery(hipEvent_t e) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (e->done < e->recorded) return hipErrorNotReady;
+    return e->err ? hipErrorLaunchFailure : hipSuccess;
+}
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (a->done < a->recorded || b->done < b->recorded) return hipErrorNotReady;
+    *ms = (float)(b->t_done_ms - a->t_done_ms);
+    return hipSuccess;
+}
+hipError_t hipLaunchKernel(const void* fn, dim3 grid, dim3, void** args, size_t,
+                           hipStream_t s) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_kernels.find(fn);
+    if (it == g_kernels.end()) return hipErrorInvalidValue;
+    Op op;
+    op.kind = 0;
+    op.k = it->second;
+    op.args.assign((const uint8_t*)args[0], (const uint8_t*)args[0] + it->second.args_bytes);
+    std::memcpy(&op.slice, args[1], sizeof(kl_slice));
+    if (op.slice.count != grid.x) return hipErrorInvalidValue;
+    s->q.push_back(std::move(op));
+    g_cv.notify_all();
+    return hipSuccess;
+}
+hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void*) {
+    a->sharedSizeBytes = 0;
+    a->numRegs = 32;
+    a->maxThreadsPerBlock = 1024;
+    return hipSuccess;
+}
+hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int, size_t) {
+    *n = 8;
+    return hipSuccess;
+}
+const char* hipGetErrorString(hipError_t e) {
+    switch (e) {
+        case hipSuccess: return "hipSuccess";
+        case hipErrorNotReady: return "hipErrorNotReady";
+        case hipErrorLaunchFailure: return "hipErrorLaunchFailure";
+        default: return "hipErrorInvalidValue";
+    }
+}
+
+// ---------------------------------------------------------------- builtins
+// The fake library has no built-in kernels.
+namespace kl {
+bool builtin_check(const char*, const void*, uint32_t, kl_dim3*, std::string* err) {
+    *err = "no built-in kernels in the fake library";
+    return false;
+}
+bool is_builtin_fn(const void*, const char**) { return false; }
+}  // namespace kl
+
+extern "C" kl_status kernelet_builtin(const char*, kl_kernel_desc*) { return KL_ENOTFOUND; }
+extern "C" kl_status kernelet_builtin_grid(const char*, const void*, uint32_t, kl_dim3*) {
+    return KL_ENOTFOUND;
+}
+
+// ------------------------------------------------------------ fake kernels
+// "visit": every workgroup of the slice adds one to visits[its id] (host
+// memory), then the slice sleeps us_per_wg microseconds per workgroup; the
+// slice is appended to a log (tag, offset, count, start ms, end ms).
+struct FakeVisitArgs {
+    uint32_t* visits;
+    double* log;        // 5 doubles per entry
+    uint32_t* log_len;  // entries written
+    uint32_t log_cap;
+    uint32_t tag;
+    uint32_t us_per_wg;
+    uint32_t fail;      // nonzero: report a device error
+};
+
+extern "C" int fake_visit(const void* a_, const kl_slice* s) {
+    FakeVisitArgs a;
+    std::memcpy(&a, a_, sizeof(a));
+    double t0 = now_ms();
+    for (uint32_t b = 0; b < s->count; ++b) a.visits[s->offset + b]++;
+    if (a.us_per_wg)
+        std::this_thread::sleep_for(std::chrono::microseconds((uint64_t)a.us_per_wg * s->count));
+    double t1 = now_ms();
+    std::lock_guard<std::mutex> g(g_mu);
+    if (a.log && *a.log_len < a.log_cap) {
+        double* e = a.log + 5 * (*a.log_len);
+        e[0] = a.tag;
+        e[1] = s->offset;
+        e[2] = s->count;
+        e[3] = t0;
+        e[4] = t1;
+        ++*a.log_len;
+    }
+    return a.fail ? 1 : 0;
+}
+
+extern "C" uint32_t fake_visit_args_bytes() { return sizeof(FakeVisitArgs); }

@@ -1,0 +1,215 @@
+"""The engine's runtime (dispatcher, lanes, events, dependencies, FIFO and
+Algorithm 1) driven on the CPU: runtime.cpp compiled against a host-thread
+test double of the HIP runtime (tests/fakehip), with host functions standing
+for kernels.  Every workgroup of every job must run exactly once, chained
+jobs in order, and every schedule call must return."""
+import ctypes as C
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "fakehip"))
+
+import build as fake_build  # noqa: E402
+
+import paper_1303_5164_amd as K  # noqa: E402
+from paper_1303_5164_amd import _lib  # noqa: E402
+
+
+class VisitArgs(C.Structure):
+    _fields_ = [("visits", C.c_void_p), ("log", C.c_void_p), ("log_len", C.c_void_p),
+                ("log_cap", C.c_uint32), ("tag", C.c_uint32), ("us_per_wg", C.c_uint32),
+                ("fail", C.c_uint32)]
+
+
+@pytest.fixture(scope="module")
+def L():
+    path = fake_build.build()
+    lib = _lib.configure(C.CDLL(path))
+    lib.fake_register_kernel.argtypes = [C.c_void_p, C.c_void_p, C.c_uint32]
+    lib.fake_visit_args_bytes.restype = C.c_uint32
+    assert lib.fake_visit_args_bytes() == C.sizeof(VisitArgs)
+    fn = C.cast(lib.fake_visit, C.c_void_p).value
+    # two kernel "types" that run the same host function
+    lib._keys = [C.create_string_buffer(1), C.create_string_buffer(1)]
+    for key in lib._keys:
+        lib.fake_register_kernel(C.addressof(key), fn, C.sizeof(VisitArgs))
+    return lib
+
+
+PROF = [dict(r_mem=0.01, mem_req=1, lat_mem=400, instr_per_wave=1000, max_wg_per_cu=8,
+             waves_per_simd=1, pur=0.9, mur=0.05),
+        dict(r_mem=0.2, mem_req=16, lat_mem=400, instr_per_wave=100, max_wg_per_cu=8,
+             waves_per_simd=1, pur=0.1, mur=0.6)]
+
+
+_OPEN = []
+
+
+@pytest.fixture(autouse=True)
+def _close_runtimes():
+    yield
+    while _OPEN:
+        _OPEN.pop().close()
+
+
+class Harness:
+    def __init__(self, lib, n_cu=4, **cfg):
+        _OPEN.append(self)
+        self.lib = lib
+        self.rt = K.Runtime(0, lib_handle=lib, n_cu=n_cu, **cfg)
+        self.kids = []
+        for i, key in enumerate(lib._keys):
+            d = _lib.KernelDesc(f"fake{i}".encode(), C.addressof(key), 256,
+                                C.sizeof(VisitArgs), 0, None)
+            self.kids.append(self.rt.register(d, PROF[i]))
+        self.bufs = []
+
+    def job(self, n_wg, tag, kind=0, us=0, after=-1, fail=0):
+        visits = np.zeros(n_wg, np.uint32)
+        log = np.zeros((4096, 5), np.float64)
+        ln = np.zeros(1, np.uint32)
+        self.bufs.append((visits, log, ln))
+        a = VisitArgs(visits.ctypes.data, log.ctypes.data, ln.ctypes.data, 4096, tag, us, fail)
+        j = self.rt.submit(self.kids[kind], (n_wg, 1, 1), a, after=after)
+        return j, visits, log, ln
+
+    def close(self):
+        if self.rt.h:
+            self.rt.close()
+
+
+def _run_with_deadline(fn, seconds=20):
+    """Run fn in a thread; fail (instead of hanging) if it does not return."""
+    err = []
+
+    def body():
+        try:
+            fn()
+        except BaseException as e:  # noqa: BLE001
+            err.append(e)
+
+    t = threading.Thread(target=body, daemon=True)
+    t.start()
+    t.join(seconds)
+    assert not t.is_alive(), "schedule did not return"
+    if err:
+        raise err[0]
+
+
+def test_fifo_then_fixed_slices_with_wait_done(L):
+    """The sequence of the minimum-slice calibration: the same job unsliced
+    (FIFO) then sliced (FIXED), each waited to completion, then reaped."""
+    h = Harness(L)
+    for slice_wgs in [0, 4, 8, 16]:
+        for rep in range(3):
+            j, visits, _, _ = h.job(64, 1)
+            if slice_wgs:
+                h.rt.slice(j, slice_wgs)
+            _run_with_deadline(lambda: h.rt.schedule("fixed" if slice_wgs else "fifo",
+                                                     blocking=True, wait_done=True))
+            h.rt.synchronize()
+            assert np.all(visits == 1)
+            h.rt.reap()
+    h.close()
+
+
+@pytest.mark.parametrize("policy", ["fifo", "fixed", "markov"])
+def test_every_workgroup_once_and_chains_in_order(L, policy):
+    h = Harness(L)
+    jobs = []
+    for i in range(6):
+        jobs.append(h.job(37 + 11 * i, 10 + i, kind=i % 2, us=20))
+    # a chain of three jobs of alternating kinds
+    c1 = h.job(50, 100, kind=0, us=30)
+    c2 = h.job(50, 101, kind=1, us=30, after=c1[0])
+    c3 = h.job(50, 102, kind=0, us=30, after=c2[0])
+    if policy == "fixed":
+        for j in jobs + [c1, c2, c3]:
+            h.rt.slice(j[0], 8)
+    _run_with_deadline(lambda: h.rt.schedule(policy, blocking=True, wait_done=True))
+    for j in jobs + [c1, c2, c3]:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    # chain order: every slice of c2 starts after every slice of c1 ended
+    end = lambda j: j[2][: j[3][0], 4].max()
+    start = lambda j: j[2][: j[3][0], 3].min()
+    assert start(c2) >= end(c1) and start(c3) >= end(c2)
+    if policy == "markov":
+        assert any(d["j2"] >= 0 for d in h.rt.decisions())
+    h.close()
+
+
+def test_coschedule_overlaps_two_kinds(L):
+    h = Harness(L)
+    a = h.job(64, 1, kind=0, us=200)
+    b = h.job(64, 2, kind=1, us=200)
+    h.rt.slice(a[0], 8)
+    h.rt.slice(b[0], 8)
+    _run_with_deadline(lambda: h.rt.schedule("fixed", blocking=True, wait_done=True))
+    la, lb = a[2][: a[3][0]], b[2][: b[3][0]]
+    assert la[:, 3].min() < lb[:, 4].max() and lb[:, 3].min() < la[:, 4].max()
+    h.close()
+
+
+def test_wait_timeout_cancel_and_device_error(L):
+    h = Harness(L)
+    j, _, _, _ = h.job(16, 1)
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.wait(j, 1_000_000)
+    assert e.value.code == -6
+    d, _, _, _ = h.job(16, 2, after=j)
+    h.rt.cancel(j)
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.wait(d, 1_000_000)
+    assert e.value.code == -8
+    bad, _, _, _ = h.job(8, 3, fail=1)
+    _run_with_deadline(lambda: h.rt.schedule("fifo", blocking=True, wait_done=True))
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.wait(bad, 5_000_000_000)
+    assert e.value.code == -7
+    h.close()
+
+
+def test_background_scheduler_serves_arrivals(L):
+    h = Harness(L)
+    h.rt.schedule("markov", blocking=False)
+    got = []
+    for i in range(20):
+        got.append(h.job(16 + i, i, kind=i % 2, us=10))
+        time.sleep(0.002)
+    for j in got:
+        h.rt.wait(j[0], 10_000_000_000)
+        assert np.all(j[1] == 1)
+    st = h.rt.stats()
+    assert st["jobs_done"] >= 20
+    h.close()
+
+
+def test_memory_budget_admission(L):
+    h = Harness(L, hbm_budget=1000)
+    with pytest.raises(K.KerneletError) as e:
+        visits = np.zeros(4, np.uint32)
+        a = VisitArgs(visits.ctypes.data, None, None, 0, 0, 0, 0)
+        h.rt.submit(h.kids[0], (4, 1, 1), a, footprint=2000)
+    assert e.value.code == -2
+    jobs = []
+    for i in range(6):
+        visits = np.zeros(8, np.uint32)
+        h.bufs.append(visits)
+        a = VisitArgs(visits.ctypes.data, None, None, 0, 0, 200, 0)
+        jobs.append((h.rt.submit(h.kids[i % 2], (8, 1, 1), a, footprint=600), visits))
+    _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+    for j, v in jobs:
+        h.rt.wait(j, 5_000_000_000)
+        assert np.all(v == 1)
+    # with 600-byte jobs under a 1000-byte budget no two jobs overlapped
+    t = sorted(h.rt.job_times(j) for j, _ in jobs)
+    for (s0, b0, d0), (s1, b1, d1) in zip(t, t[1:]):
+        assert b1 >= d0 - 1_000_000   # next start after previous completion (1 ms slack)
+    h.close()

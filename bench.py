@@ -40,6 +40,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="fifo,kernelet")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
+    ap.add_argument("--lds-reserve", type=int, default=None)
+    ap.add_argument("--cp-min", type=float, default=None)
+    ap.add_argument("--estimates", action="store_true",
+                    help="use the first-order profile estimates, not the measured table")
     return ap.parse_args()
 
 
@@ -179,8 +184,15 @@ def main():
     insts = [insts[i] for i in order]
     torch.cuda.synchronize()
 
-    rt = K.Runtime(0)
-    prof = profiles.load()
+    over = {}
+    if args.inflight is not None:
+        over["inflight"] = args.inflight
+    if args.lds_reserve is not None:
+        over["lds_reserve"] = args.lds_reserve
+    if args.cp_min is not None:
+        over["cp_min"] = args.cp_min
+    rt = K.Runtime(0, **over)
+    prof = profiles.load(prefer_measured=not args.estimates)
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     setup_s = time.perf_counter() - t_setup
 
@@ -205,6 +217,7 @@ def main():
     turn = {l: [] for l in legs}
     ktime = {k: [0.0, 0, 0] for k in W.KERNELS}
     decisions = 0
+    pairs = {}
     for step in range(args.warmup + args.steps):
         timed_step = step >= args.warmup
         for leg in legs:
@@ -232,7 +245,14 @@ def main():
                     ktime[k][2] += w
                     rt.time_kernel(kids[k], False)
             if leg != "fifo":
-                decisions += len(rt.decisions())
+                kind_of = {j: (inst.launches[i].kernel or inst.kind)
+                           for inst, js in zip(insts, jobs) for i, j in enumerate(js)}
+                for d in rt.decisions():
+                    decisions += 1
+                    if timed_step:
+                        key = kind_of.get(d["j1"], "?") + (
+                            "+" + kind_of.get(d["j2"], "?") if d["j2"] >= 0 else "")
+                        pairs[key] = pairs.get(key, 0) + 1
             rt.reap()
             print(f"# step {step} {leg}: {(t1 - t0) / 1e6:.2f} ms", file=sys.stderr,
                   flush=True)
@@ -259,7 +279,10 @@ def main():
                                "2^26 in 2^26, polynomial 2^20 x256 fma, gather 2^22 of "
                                "2^24), seed %d" % args.seed,
                    "instances_per_type": args.instances, "instances": n_inst,
-                   "policy": args.policy, "parallelism": "single GPU, 2 co-execution lanes"},
+                   "policy": args.policy, "parallelism": "single GPU, 2 co-execution lanes",
+                   "inflight": rt.cfg.inflight, "lds_reserve": rt.cfg.lds_reserve,
+                   "cp_min": rt.cfg.cp_min,
+                   "profiles": "estimates" if args.estimates else "measured"},
     }
     if "fifo" in legs:
         out["fifo_kernels_per_s"] = round(n_inst / med["fifo"], 3)
@@ -270,6 +293,7 @@ def main():
         out[f"{l}_p50_turnaround_ms"] = round(nearest_rank(turn[l], 0.5), 3)
         out[f"{l}_p99_turnaround_ms"] = round(nearest_rank(turn[l], 0.99), 3)
     out["decisions_per_step"] = decisions / max(1, args.warmup + args.steps)
+    out["coschedules"] = dict(sorted(pairs.items(), key=lambda kv: -kv[1]))
 
     # roofline of the dominant kernel: all its launches in the timed region
     dom = max(W.KERNELS, key=lambda k: ktime[k][0])

@@ -43,6 +43,7 @@ if ROOT not in sys.path:
 
 FREQ = 2.4e9
 PEAK_HBM = 8.0e12
+MFMA_SLOTS = 16.0   # issue slots (4 cycles) of one v_mfma_f32_32x32x2f32
 
 # counter passes (each within one run's hardware limits)
 PASSES = {
@@ -240,7 +241,12 @@ def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict
                                              "SQ_INSTS_SMEM", "SQ_INSTS_LDS", "SQ_INSTS_BRANCH"])
         I = total / waves
         T = t["avg_launch_ms"] / 1e3
-        pur = waves * I / (T * FREQ * n_cu)
+        # instructions issued per issue slot (the model's IPC) ...
+        ipc_instr = waves * I / (T * FREQ * n_cu)
+        # ... and the pipeline utilisation, an FP32 32x32x2 matrix instruction
+        # holding its SIMD's matrix pipe for 16 issue slots (64 cycles)
+        mf = c.get("SQ_INSTS_MFMA", 0.0) / waves
+        pur = waves * (I - mf + MFMA_SLOTS * mf) / (T * FREQ * n_cu)
         fetch_b = 1024.0 * c.get("FETCH_SIZE", 0.0) * f_fetch
         write_b = 1024.0 * c.get("WRITE_SIZE", 0.0) * f_write
         dram = fetch_b + write_b
@@ -250,16 +256,16 @@ def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict
         mfma = c.get("SQ_INSTS_MFMA", 0.0)
         trans = c.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
         r_comp = (mfma + trans) / total
-        lat_comp = 16.0 if mfma > trans else 4.0
+        lat_comp = MFMA_SLOTS if mfma > trans else 4.0
         mem_req = max(1.0, dram / 64.0 / vmem) if vmem > 0 else 1.0
         occ = max(1, int(t["max_wg_per_cu"]))
         p = dict(est.get(name, {}))
         p.update(r_mem=r_mem, mem_req=mem_req, r_comp=r_comp if r_comp > 1e-4 else 0.0,
                  lat_comp=lat_comp if r_comp > 1e-4 else 0.0, instr_per_wave=I,
-                 pur=pur, mur=mur, solo_ipc=pur, max_wg_per_cu=min(occ, 8),
+                 pur=min(pur, 1.0), mur=mur, solo_ipc=ipc_instr, max_wg_per_cu=min(occ, 8),
                  waves_per_simd=1, vgpr=int(t["vgpr"]), lds_bytes=int(t["lds_bytes"]))
         # fit the memory latency so the model's solo IPC matches the measured
-        target = min(pur, 0.999)
+        target = min(ipc_instr, 0.999)
         w = p["max_wg_per_cu"]
 
         def ipc_at(L):

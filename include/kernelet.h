@@ -128,7 +128,13 @@ typedef struct {
     double beta;           /* latency added per outstanding request, slots */
     int32_t lanes;         /* co-execution streams (2) */
     int32_t inflight;      /* slices queued per lane ahead of the GPU (2) */
-    int32_t lds_reserve;   /* 1: reserve LDS so a CU holds <= b1+b2 slices' WGs */
+    int32_t lds_reserve;   /* occupancy control by LDS reservation (dynamic LDS
+                              added to each workgroup of a co-schedule):
+                              0 none; 1 every WG reserves LDS_CU/(b1+b2), so a
+                              CU holds at most b1+b2 of them; 2 only the kernel
+                              with the larger register footprint reserves just
+                              over LDS_CU/(b+1), capping it at b per CU while
+                              its partner fills the rest (b >= 2) */
     int32_t max_slices;    /* cap on slices per co-schedule of one kernel (0: none) */
     int64_t hbm_budget;    /* bytes of job footprint admitted at once (0: none) */
     int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE) */
@@ -225,6 +231,11 @@ kl_status kernelet_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid,
  * by tests.  KL_ESTATE if the job has started. */
 kl_status kernelet_slice(kl_runtime* rt, kl_job j, uint32_t wgs_per_slice,
                          uint32_t* n_slices);
+
+/* Workgroups per CU the FIXED policy runs job j at (1..64): its slices are
+ * sized b * n_cu unless kernelet_slice fixed them, and LDS reservation, when
+ * enabled, is computed for it.  KL_ESTATE if the job has started. */
+kl_status kernelet_job_occupancy(kl_runtime* rt, kl_job j, int32_t wg_per_cu);
 
 /* Run the scheduler with `policy` over the pending jobs.  With KL_BLOCKING
  * the call returns once every pending job (including dependants released

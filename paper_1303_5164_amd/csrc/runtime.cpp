@@ -117,6 +117,7 @@ struct Job {
     int type = -1;
     kl_dim3 grid{1, 1, 1};
     uint32_t total = 0, next = 0, fixed_slice = 0;
+    int occ = 0;  // FIXED policy: workgroups per CU (0: the kernel's maximum)
     std::vector<uint8_t> args;
     kl_job after = KL_NO_JOB;
     uint32_t client = 0;
@@ -197,7 +198,8 @@ static kl_config defaults() {
 static kl_status check_cfg(const kl_config& c) {
     if (c.wmax < 1 || c.wmax > 64 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
-        c.beta < 0 || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2) {
+        c.beta < 0 || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
+        c.lds_reserve < 0 || c.lds_reserve > 2) {
         set_error("invalid kl_config field");
         return KL_EINVAL;
     }
@@ -292,12 +294,32 @@ static void poll_lanes(kl_runtime* rt) {
     }
 }
 
-static uint32_t dyn_lds_for(kl_runtime* rt, const KernelType& kt, int b_total) {
-    if (!rt->cfg.lds_reserve || b_total <= 0) return 0;
-    int64_t per = rt->cfg.lds_cu / b_total - kt.static_lds;
-    int64_t cap = 65536 - kt.static_lds;
+// Largest LDS one workgroup may allocate, static plus dynamic.
+static const int64_t kLdsPerWg = 65536;
+
+// Dynamic LDS for kernel `kt` in a co-schedule where it runs at b_self
+// workgroups per CU beside a partner at b_other (static LDS other_lds).
+static uint32_t dyn_lds_for(kl_runtime* rt, const KernelType& kt, int b_self, int b_other,
+                            const KernelType* other, bool capped) {
+    const int64_t lds = rt->cfg.lds_cu;
+    int64_t per = 0;
+    if (rt->cfg.lds_reserve == 1) {
+        if (b_self + b_other <= 0) return 0;
+        per = lds / (b_self + b_other) - kt.static_lds;
+    } else if (rt->cfg.lds_reserve == 2) {
+        if (!capped || b_self < 1) return 0;
+        // (b_self + 1) workgroups must not fit, b_self must leave room for the
+        // partner's static LDS
+        int64_t total = lds / (b_self + 1) + 256;
+        int64_t room = lds - (other ? (int64_t)b_other * other->static_lds : 0);
+        if ((int64_t)b_self * total > room || total > kLdsPerWg) return 0;  // cannot cap
+        per = total - kt.static_lds;
+    } else {
+        return 0;
+    }
+    int64_t cap = kLdsPerWg - kt.static_lds;
     if (per > cap) per = cap;
-    return per > 0 ? (uint32_t)(per & ~255ll) : 0u;
+    return per > 0 ? (uint32_t)((per + 255) & ~255ll) : 0u;
 }
 
 // Launch the next slice of job `jid` on lane `li`, `count` workgroups.
@@ -454,12 +476,18 @@ static void decide(kl_runtime* rt, kl_policy policy) {
         // the two earliest jobs of different kernel types, their own plans
         std::sort(pend.begin(), pend.end(),
                   [](const PendingJob& a, const PendingJob& b) { return a.id < b.id; });
+        auto occ = [&](kl_job id) {
+            const Job& j = rt->jobs.at(id);
+            if (j.occ > 0) return j.occ;
+            const KernelType& kt = rt->kernels[j.type];
+            return kt.has_prof ? kt.prof.max_wg_per_cu : 8;
+        };
         d.j1 = pend[0].id;
-        d.b1 = 1;
+        d.b1 = occ(d.j1);
         for (auto& p : pend)
             if (p.type != pend[0].type) {
                 d.j2 = p.id;
-                d.b2 = 1;
+                d.b2 = occ(d.j2);
                 break;
             }
     } else {
@@ -491,6 +519,20 @@ static void decide(kl_runtime* rt, kl_policy policy) {
 
     uint32_t sl[2] = {0, 0};
     const bool solo = d.j2 == KL_NO_JOB || lane_of[1] < 0;
+    // the kernel capped by LDS reservation (mode 2): the larger register
+    // footprint at its target occupancy
+    int capped = -1;
+    const KernelType* kts[2] = {nullptr, nullptr};
+    for (int k = 0; k < 2; ++k)
+        if (want[k] != KL_NO_JOB) kts[k] = &rt->kernels[rt->jobs.at(want[k]).type];
+    if (!solo) {
+        auto foot = [&](int k) {
+            const KernelType* t = kts[k];
+            int v = t->has_prof ? t->prof.vgpr : 0;
+            return (int64_t)(k == 0 ? d.b1 : d.b2) * v;
+        };
+        capped = foot(0) >= foot(1) ? 0 : 1;
+    }
     for (int k = 0; k < 2; ++k) {
         if (want[k] == KL_NO_JOB || lane_of[k] < 0) continue;
         Job& j = rt->jobs.at(want[k]);
@@ -503,8 +545,9 @@ static void decide(kl_runtime* rt, kl_policy policy) {
             sl[k] = j.fixed_slice ? j.fixed_slice : j.total - j.next;
             ln.dyn_lds = 0;
         } else {
-            sl[k] = slice_size(rt, j, k == 0 ? d.b1 : d.b2);
-            ln.dyn_lds = dyn_lds_for(rt, kt, d.b1 + d.b2);
+            const int bs = k == 0 ? d.b1 : d.b2, bo = k == 0 ? d.b2 : d.b1;
+            sl[k] = slice_size(rt, j, bs);
+            ln.dyn_lds = dyn_lds_for(rt, kt, bs, bo, kts[1 - k], capped == k);
         }
         ln.slice = sl[k];
         rt->cs_job[k] = want[k];
@@ -892,6 +935,26 @@ kl_status kernelet_slice(kl_runtime* rt, kl_job jid, uint32_t wgs, uint32_t* n_s
     }
     j.fixed_slice = std::min(wgs, j.total);
     if (n_slices) *n_slices = (j.total + j.fixed_slice - 1) / j.fixed_slice;
+    return KL_OK;
+}
+
+kl_status kernelet_job_occupancy(kl_runtime* rt, kl_job jid, int32_t wg_per_cu) {
+    if (!rt || wg_per_cu < 1 || wg_per_cu > 64) {
+        set_error("kernelet_job_occupancy: null runtime or occupancy outside [1, 64]");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    auto it = rt->jobs.find(jid);
+    if (it == rt->jobs.end()) {
+        set_error("kernelet_job_occupancy: unknown job");
+        return KL_ENOTFOUND;
+    }
+    Job& j = it->second;
+    if (j.next > 0 || j.st == J_LAUNCHED || j.st == J_DONE || j.st == J_CANCELED) {
+        set_error("kernelet_job_occupancy: job already started");
+        return KL_ESTATE;
+    }
+    j.occ = wg_per_cu;
     return KL_OK;
 }
 

@@ -158,6 +158,9 @@ class Runtime:
         self._c("kernelet_slice", self.h, job, wgs_per_slice, C.byref(n))
         return n.value
 
+    def job_occupancy(self, job: int, wg_per_cu: int) -> None:
+        self._c("kernelet_job_occupancy", self.h, job, wg_per_cu)
+
     def schedule(self, policy: str = "markov", blocking: bool = True,
                  replan_on_arrival: bool = False, wait_done: bool = False) -> None:
         flags = (_lib.KL_BLOCKING if blocking else 0) | (

@@ -1,0 +1,184 @@
+"""Co-schedule sweep: measured against predicted co-run performance.
+
+For every pair of the eight workload kernels and a set of slice ratios
+(b1, b2 workgroups per CU), the two kernels run concurrently on the two
+lanes, each as a stream of back-to-back slices of b_i * n_cu workgroups,
+long enough (about `window_ms` of solo work each) that they overlap for
+most of the run.  Reported per pair and ratio:
+
+  * measured weighted speedup S = (sum of the kernels' solo times for the
+    same work) / co-run wall time, and CP = 1 - 1/S (Eq. 1 with measured
+    rates);
+  * measured per-kernel slowdown cIPC_i / IPC_i = solo time of kernel i's
+    work / kernel i's busy time in the co-run;
+  * the Markov model's predicted cIPC_i / IPC_i and CP at the same ratio.
+
+The stencil runs single sweeps and the lookup its query kernel over an index
+built beforehand, so every job is one launch.
+
+Usage: python -m paper_1303_5164_amd.sweep --out gpurun_out/sweep.json
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+RATIOS = [(1, 7), (2, 6), (3, 5), (4, 4), (5, 3), (6, 2), (7, 1)]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--window-ms", type=float, default=4.0)
+    ap.add_argument("--ratios", default="all", help="'all' or e.g. 2:6,4:4,6:2")
+    ap.add_argument("--kinds", default="poly,gather,sgemm,spmv,stencil,bs,hist,lookup")
+    ap.add_argument("--slicing", default="exact", choices=["exact", "min", "none"],
+                    help="exact: slices of b*n_cu WGs; min: max(b*n_cu, calibrated minimum "
+                         "slice); none: whole launches")
+    ap.add_argument("--lds-reserve", type=int, default=0)
+    a = ap.parse_args()
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import profiles
+    from paper_1303_5164_amd import workloads as W
+
+    ratios = RATIOS if a.ratios == "all" else [tuple(map(int, r.split(":")))
+                                              for r in a.ratios.split(",")]
+    kinds = a.kinds.split(",")
+    dev = torch.device("cuda:0")
+    F = synth.FULL
+    gen = {
+        "poly": lambda: synth.poly(0, **F["poly"]),
+        "gather": lambda: synth.gather(0, **F["gather"]),
+        "sgemm": lambda: synth.sgemm(0, **F["sgemm"]),
+        "spmv": lambda: synth.spmv(0, **F["spmv"]),
+        "stencil": lambda: synth.stencil(0, F["stencil"]["ny"], F["stencil"]["nx"]),
+        "bs": lambda: synth.bs(0, F["bs"]["n"]),
+        "hist": lambda: synth.hist(0, F["hist"]["n"]),
+        "lookup": lambda: synth.lookup(0, **F["lookup"]),
+    }
+    params = {"stencil": dict(iters=1, c0=F["stencil"]["c0"], c1=F["stencil"]["c1"]),
+              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    prof = profiles.load()
+    rt = K.Runtime(0, lds_reserve=a.lds_reserve)
+    n_cu = rt.cfg.n_cu
+    kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
+    launch = {}   # kind -> (kernel name, args, grid): the one launch a job makes
+    keep = []
+    for kind in kinds:
+        d_in = W.device_inputs(kind, gen[kind](), dev)
+        inst = W.build(kind, d_in, params.get(kind, {}), dev)
+        keep.append(inst)
+        if kind == "lookup":   # build the index once; jobs run the query kernel
+            j = W.submit(rt, kids, W.Instance("lookup", inst.launches[:1], inst.tensors))
+            rt.schedule("fifo", blocking=True, wait_done=True)
+            rt.reap()
+        ln = inst.launches[-1]
+        launch[kind] = (ln.kernel or kind, ln.args, ln.grid)
+    torch.cuda.synchronize()
+
+    def run(jobs_spec):
+        """jobs_spec: list of (kind, count, slice_wgs, wg_per_cu); returns wall
+        s and per-kernel (busy ms, workgroups)."""
+        for kind, _, _, _ in jobs_spec:
+            rt.time_kernel(kids[launch[kind][0]], True)
+        ids = []
+        # interleave submissions so FIXED pairs the two kinds from the start
+        counts = {k: c for k, c, _, _ in jobs_spec}
+        for i in range(max(counts.values())):
+            for kind, cnt, sl, occ in jobs_spec:
+                if i < cnt:
+                    kn, args, grid = launch[kind]
+                    j = rt.submit(kids[kn], grid, args)
+                    if sl:
+                        rt.slice(j, sl)
+                    if occ:
+                        rt.job_occupancy(j, occ)
+                    ids.append(j)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rt.schedule("fixed", blocking=True, wait_done=True)
+        rt.synchronize()
+        wall = time.perf_counter() - t0
+        busy = {}
+        for kind, _, _, _ in jobs_spec:
+            ms, n, wg = rt.kernel_time(kids[launch[kind][0]])
+            busy[kind] = (ms, wg)
+            rt.time_kernel(kids[launch[kind][0]], False)
+        rt.reap()
+        return wall, busy
+
+    # solo: one launch time per kind (unsliced), median of 5
+    solo = {}
+    for kind in kinds:
+        ts = []
+        for _ in range(6):
+            _, busy = run([(kind, 1, 0, 0)])
+            ts.append(busy[kind][0])
+        solo[kind] = float(np.median(ts[1:]))
+        print(f"# solo {kind}: {solo[kind]:.4f} ms", file=sys.stderr, flush=True)
+
+    rows = []
+    for ka, kb in itertools.combinations(kinds, 2):
+        pa, pb = prof[launch[ka][0]], prof[launch[kb][0]]
+        na = max(1, round(a.window_ms / solo[ka]))
+        nb = max(1, round(a.window_ms / solo[kb]))
+        wga = launch[ka][2][0] * launch[ka][2][1] * launch[ka][2][2]
+        wgb = launch[kb][2][0] * launch[kb][2][1] * launch[kb][2][2]
+        seq_ms = na * solo[ka] + nb * solo[kb]
+        for b1, b2 in ratios:
+            if b1 > pa["max_wg_per_cu"] or b2 > pb["max_wg_per_cu"]:
+                continue
+            if b1 * pa["vgpr"] + b2 * pb["vgpr"] > 512 or \
+                    b1 * pa["lds_bytes"] + b2 * pb["lds_bytes"] > 160 * 1024:
+                continue
+            def sl(b, wg, p):
+                if a.slicing == "none":
+                    return 0
+                s = b * n_cu
+                if a.slicing == "min":
+                    s = max(s, min(int(p.get("min_slice_wgs") or 0), wg))
+                return min(s, wg)
+
+            wall, busy = run([(ka, na, sl(b1, wga, pa), b1), (kb, nb, sl(b2, wgb, pb), b2)])
+            co_ms = wall * 1e3
+            S = seq_ms / co_ms
+            sa = (na * solo[ka]) / max(busy[ka][0], 1e-9)
+            sb = (nb * solo[kb]) / max(busy[kb][0], 1e-9)
+            try:
+                i1, i2, _ = K.predict(pa, pb, b1, b2)
+                s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0)[0]
+                s2 = K.predict(pb, None, pb["max_wg_per_cu"], 0)[0]
+                pr1, pr2 = i1 / s1, i2 / s2
+                pcp = 1.0 - 1.0 / (pr1 + pr2)
+            except K.KerneletError:
+                pr1 = pr2 = pcp = float("nan")
+            row = dict(a=ka, b=kb, b1=b1, b2=b2, na=na, nb=nb, seq_ms=seq_ms, co_ms=co_ms,
+                       speedup=S, cp=1.0 - 1.0 / S, rel_a=sa, rel_b=sb,
+                       pred_rel_a=pr1, pred_rel_b=pr2, pred_cp=pcp,
+                       busy_a_ms=busy[ka][0], busy_b_ms=busy[kb][0])
+            rows.append(row)
+            print(f"# {ka}+{kb} ({b1},{b2}): S={S:.3f} rel=({sa:.2f},{sb:.2f}) "
+                  f"pred=({pr1:.2f},{pr2:.2f}) cp={row['cp']:+.3f} pred_cp={pcp:+.3f}",
+                  file=sys.stderr, flush=True)
+    rt.close()
+    with open(a.out, "w") as f:
+        json.dump({"n_cu": n_cu, "solo_ms": solo, "window_ms": a.window_ms, "rows": rows},
+                  f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,7 +134,7 @@ typedef struct {
                               CU holds at most b1+b2 of them; 2 only the kernel
                               with the larger register footprint reserves just
                               over LDS_CU/(b+1), capping it at b per CU while
-                              its partner fills the rest (b >= 2) */
+                              its partner fills the rest (b >= 2); default 2 */
     int32_t max_slices;    /* cap on slices per co-schedule of one kernel (0: none) */
     int64_t hbm_budget;    /* bytes of job footprint admitted at once (0: none) */
     int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE) */
@@ -293,6 +293,31 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
                             int32_t n_jobs, kl_policy policy,
                             kl_decision* decisions, int32_t max_dec,
                             int32_t* n_dec, double* makespan, double* done);
+
+/* ------------------------------------------------------------- surrogate */
+/* The learned pair ranker: a 16 -> 64 -> 64 -> 1 ReLU network (parameters
+ * one device fp32 array of 5313 values: W1 [16][64], b1 [64], W2 [64][64],
+ * b2 [64], W3 [64], b3) trained by mean-squared error and Adam on co-run
+ * speedups.  Kernels run on `stream` (a hipStream_t; NULL = the default
+ * stream) and are asynchronous.  All arrays are device memory. */
+
+/* Floats of scratch a training step over `batch` samples needs. */
+uint64_t kernelet_mlp_workspace_floats(uint32_t batch);
+
+/* y[s] = net(x[s]) for s < n; x is n x 16 row-major. */
+kl_status kernelet_mlp_forward(const float* params, const float* x, uint32_t n, float* y,
+                               void* stream);
+
+/* One step on the samples idx[0..batch) (idx NULL: rows 0..batch) of
+ * (x, t): the gradient of mean((net(x) - t)^2) is written to grad_out (if
+ * not NULL) and, when m and v (first and second moments, 5313 each) are
+ * given, Adam (beta 0.9, 0.999, eps 1e-8, bias-corrected at `step` >= 1)
+ * updates params in place.  workspace: kernelet_mlp_workspace_floats(batch)
+ * floats. */
+kl_status kernelet_mlp_train_step(float* params, float* m, float* v, const float* x,
+                                  const float* t, const int32_t* idx, uint32_t batch,
+                                  uint32_t step, float lr, float* grad_out, float* workspace,
+                                  void* stream);
 
 /* --------------------------------------------------------------- logging */
 

@@ -128,7 +128,8 @@ SYMBOLS = [
     "kernelet_synchronize", "kernelet_cancel", "kernelet_job_times", "kernelet_reap",
     "kernelet_predict", "kernelet_best_ratio", "kernelet_simulate", "kernelet_stats",
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
-    "kernelet_kernel_info",
+    "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
+    "kernelet_mlp_train_step",
 ]
 
 _lib = None
@@ -195,6 +196,15 @@ def configure(L):
         f = getattr(L, name)
         f.argtypes = args
         f.restype = i32
+    if hasattr(L, "kernelet_mlp_forward"):
+        f32p = C.c_void_p
+        L.kernelet_mlp_workspace_floats.argtypes = [u32]
+        L.kernelet_mlp_workspace_floats.restype = u64
+        L.kernelet_mlp_forward.argtypes = [f32p, f32p, u32, f32p, C.c_void_p]
+        L.kernelet_mlp_forward.restype = i32
+        L.kernelet_mlp_train_step.argtypes = [f32p, f32p, f32p, f32p, f32p, f32p, u32, u32,
+                                              C.c_float, f32p, f32p, C.c_void_p]
+        L.kernelet_mlp_train_step.restype = i32
     if hasattr(L, "kernelet_lookup_index_entries"):
         L.kernelet_lookup_index_entries.argtypes = [C.c_uint32]
         L.kernelet_lookup_index_entries.restype = C.c_uint64

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libkernelet.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["workloads.hip", "model.cpp", "runtime.cpp"]
+SOURCES = ["workloads.hip", "mlp.hip", "model.cpp", "runtime.cpp"]
 
 # Packed FP32 instructions are disabled: the compiler would otherwise form
 # them from ordinary float code.

@@ -188,7 +188,7 @@ static kl_config defaults() {
     c.beta = 0.0;
     c.lanes = 2;
     c.inflight = 2;
-    c.lds_reserve = 0;
+    c.lds_reserve = 2;
     c.max_slices = 0;
     c.hbm_budget = 0;
     c.surrogate_topk = 4;
@@ -543,7 +543,10 @@ static void decide(kl_runtime* rt, kl_policy policy) {
             // a co-schedule of one kernel: its residual in one launch at full
             // occupancy; the other lanes wait for it before their next launch
             sl[k] = j.fixed_slice ? j.fixed_slice : j.total - j.next;
-            ln.dyn_lds = 0;
+            // a requested occupancy below the kernel's own is held by LDS
+            ln.dyn_lds = j.occ > 0 && rt->cfg.lds_reserve == 2
+                             ? dyn_lds_for(rt, kt, j.occ, 0, nullptr, true)
+                             : 0;
         } else {
             const int bs = k == 0 ? d.b1 : d.b2, bo = k == 0 ? d.b2 : d.b1;
             sl[k] = slice_size(rt, j, bs);

@@ -147,6 +147,8 @@ typedef struct {
     double decision_us_total;   /* host time spent in FindCoSchedule */
     double model_us_total;      /* of which Markov solves */
     int64_t cache_hits;
+    int64_t resident_bytes;     /* footprint admitted and not yet released */
+    int64_t resident_peak;      /* largest resident_bytes so far */
 } kl_stats;
 
 /* One scheduling decision, as logged (Algorithm 1, one co-schedule). */
@@ -216,8 +218,12 @@ kl_status kernelet_get_profile(kl_runtime* rt, kl_kernel k, kl_profile* p);
  * alive until kernelet_wait on this job returns KL_OK.  `after` (or
  * KL_NO_JOB) names a job that must finish before this one starts.
  * `client` tags the submitting client; `footprint` is the device memory the
- * job holds (for the memory budget).  A job becomes pending at once (and
- * is scheduled by the next or the running kernelet_schedule).  Errors:
+ * job holds (for the memory budget): it is charged when the job is admitted
+ * and released when the job finishes, or, if jobs submitted `after` it
+ * have yet to finish, when the last job of that chain does (an instance of
+ * several dependent launches passes its footprint with the first launch).
+ * A job becomes pending at once (and is scheduled by the next or the
+ * running kernelet_schedule).  Errors:
  * KL_EINVAL (grid of zero workgroups or > 2^32-1, size mismatch, grid not
  * the built-in kernel's required grid), KL_ENOTFOUND (k or after),
  * KL_ENOMEM (footprint above the whole budget). */

@@ -57,7 +57,8 @@ class Stats(C.Structure):
     _fields_ = [("jobs_submitted", C.c_int64), ("jobs_done", C.c_int64),
                 ("slices_launched", C.c_int64), ("decisions", C.c_int64),
                 ("decision_us_total", C.c_double), ("model_us_total", C.c_double),
-                ("cache_hits", C.c_int64)]
+                ("cache_hits", C.c_int64), ("resident_bytes", C.c_int64),
+                ("resident_peak", C.c_int64)]
 
 
 class Decision(C.Structure):

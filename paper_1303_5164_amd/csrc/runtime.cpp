@@ -20,6 +20,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <set>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -122,6 +123,7 @@ struct Job {
     kl_job after = KL_NO_JOB;
     uint32_t client = 0;
     uint64_t footprint = 0;
+    int64_t carry = 0;  // footprint of finished predecessors released with this job
     JobState st = J_PENDING;
     bool admitted = false;
     int last_lane = -1;
@@ -148,6 +150,7 @@ struct kl_runtime {
     std::unique_ptr<kl::Planner> planner;
     std::vector<kl::KernelType> kernels;
     std::map<kl_job, kl::Job> jobs;
+    std::set<kl_job> live;  // jobs neither finished nor cancelled, in submission order
     kl_job next_id = 0;
     std::vector<kl::Lane> lanes;
     kl::EvPool pool;
@@ -160,6 +163,7 @@ struct kl_runtime {
     uint32_t worker_flags = 0;
     bool scheduling = false;  // a dispatcher loop is active
     int64_t resident = 0;     // admitted footprint bytes
+    int64_t resident_peak = 0;
     kl_stats stats{};
     std::vector<kl_decision> declog;
     int64_t t0_dec = 0;
@@ -229,11 +233,24 @@ static void release_dependents(kl_runtime* rt, Job& j) {
 static void mark_done(kl_runtime* rt, Job& j, bool error) {
     if (j.st == J_DONE) return;
     j.st = J_DONE;
+    rt->live.erase(j.id);
     j.error = error;
     j.t_done = now_ns();
-    if (j.admitted) rt->resident -= (int64_t)j.footprint;
+    int64_t rel = j.carry + (j.admitted ? (int64_t)j.footprint : 0);
+    j.carry = 0;
     j.admitted = false;
     rt->stats.jobs_done++;
+    if (rel == 0) return;
+    // the memory of a chain of dependent launches stays charged until its
+    // last launch: hand the release on to a dependant that is still to run
+    for (kl_job d : j.dependents) {
+        auto it = rt->jobs.find(d);
+        if (it != rt->jobs.end() && it->second.st != J_DONE && it->second.st != J_CANCELED) {
+            it->second.carry += rel;
+            return;
+        }
+    }
+    rt->resident -= rel;
 }
 
 static hipEvent_t timing_event(kl_runtime* rt) {
@@ -396,14 +413,15 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
 // Admission by the memory budget: jobs in submission order while the
 // admitted footprint fits.
 static void admit(kl_runtime* rt) {
-    for (auto& kv : rt->jobs) {
-        Job& j = kv.second;
-        if (j.admitted || j.st == J_DONE || j.st == J_CANCELED) continue;
+    for (kl_job id : rt->live) {
+        Job& j = rt->jobs.at(id);
+        if (j.admitted) continue;
         if (rt->cfg.hbm_budget > 0 &&
             rt->resident + (int64_t)j.footprint > rt->cfg.hbm_budget)
             break;  // keep submission order: nothing later overtakes
         j.admitted = true;
         rt->resident += (int64_t)j.footprint;
+        rt->resident_peak = std::max(rt->resident_peak, rt->resident);
     }
 }
 
@@ -448,9 +466,9 @@ static uint32_t slice_size(kl_runtime* rt, const Job& j, int b) {
 static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
     Lane& ln = rt->lanes[0];
     ln.dyn_lds = 0;
-    for (auto& kv : rt->jobs) {
-        Job& j = kv.second;
-        if (j.st == J_DONE || j.st == J_CANCELED || j.st == J_LAUNCHED) continue;
+    for (kl_job id : rt->live) {
+        Job& j = rt->jobs.at(id);
+        if (j.st == J_LAUNCHED) continue;
         if (!runnable(j)) break;
         kl_status s = launch_slice(rt, 0, j.id, j.total - j.next);
         if (s) return s;
@@ -462,8 +480,10 @@ static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
 // Choose the next co-schedule (FindCoSchedule) and bind it to lanes.
 static void decide(kl_runtime* rt, kl_policy policy) {
     std::vector<PendingJob> pend;
-    for (auto& kv : rt->jobs)
-        if (runnable(kv.second)) pend.push_back({kv.first, kv.second.type});
+    for (kl_job id : rt->live) {
+        const Job& j = rt->jobs.at(id);
+        if (runnable(j)) pend.push_back({id, j.type});
+    }
     rt->cs_active = false;
     rt->cs_job[0] = rt->cs_job[1] = KL_NO_JOB;
     if (pend.empty()) {
@@ -603,8 +623,8 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
 }
 
 static bool all_launched(kl_runtime* rt) {
-    for (auto& kv : rt->jobs) {
-        const Job& j = kv.second;
+    for (kl_job id : rt->live) {
+        const Job& j = rt->jobs.at(id);
         if (j.st == J_WAIT_DEP || j.st == J_PENDING) return false;
     }
     return true;
@@ -637,14 +657,13 @@ static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
         }
         if (blocking && all_launched(rt) && (!wait_done || !any_inflight(rt))) break;
         bool waiting_budget = false;
-        for (auto& kv : rt->jobs)
-            if (!kv.second.admitted && kv.second.st != J_DONE && kv.second.st != J_CANCELED)
-                waiting_budget = true;
+        for (kl_job id : rt->live)
+            if (!rt->jobs.at(id).admitted) waiting_budget = true;
         if (blocking && !any_inflight(rt) && !waiting_budget) {
             // nothing in flight and nothing runnable: jobs wait on deps that
             // can never be released (e.g. a cancelled predecessor)
             bool runnable_any = false;
-            for (auto& kv : rt->jobs) runnable_any |= runnable(kv.second);
+            for (kl_job id : rt->live) runnable_any |= runnable(rt->jobs.at(id));
             if (!runnable_any) {
                 set_error("kernelet_schedule: jobs wait on dependencies that cannot finish");
                 st = KL_ESTATE;
@@ -901,12 +920,11 @@ kl_status kernelet_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid, const void*
             set_error("kernelet_submit: `after` job was cancelled");
             return KL_ECANCELED;
         }
-        if (p.st == J_WAIT_DEP || p.st == J_PENDING) {
-            j.st = J_WAIT_DEP;
-            p.dependents.push_back(j.id);
-        }
+        if (p.st == J_WAIT_DEP || p.st == J_PENDING) j.st = J_WAIT_DEP;
+        if (p.st != J_DONE) p.dependents.push_back(j.id);
     }
     rt->next_id++;
+    rt->live.insert(j.id);
     rt->jobs.emplace(j.id, std::move(j));
     rt->stats.jobs_submitted++;
     *out = rt->next_id - 1;
@@ -977,8 +995,8 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
             return KL_ESTATE;
         }
         if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED) {
-            for (auto& kv : rt->jobs) {
-                const Job& j = kv.second;
+            for (kl_job id : rt->live) {
+                const Job& j = rt->jobs.at(id);
                 if ((j.st == J_PENDING || j.st == J_WAIT_DEP) && !rt->kernels[j.type].has_prof) {
                     set_error("kernelet_schedule: kernel " + rt->kernels[j.type].name +
                               " has no profile");
@@ -1059,8 +1077,9 @@ kl_status kernelet_synchronize(kl_runtime* rt) {
     for (auto& ln : rt->lanes) KL_HIP(hipStreamSynchronize(ln.s));
     std::lock_guard<std::mutex> g(rt->mu);
     poll_lanes(rt);
-    for (auto& kv : rt->jobs) {
-        Job& j = kv.second;
+    const std::vector<kl_job> ids(rt->live.begin(), rt->live.end());
+    for (kl_job id : ids) {
+        Job& j = rt->jobs.at(id);
         if (j.st == J_LAUNCHED) {
             mark_done(rt, j, false);
             rt->pool.unref(j.last_ev);
@@ -1087,8 +1106,11 @@ kl_status kernelet_cancel(kl_runtime* rt, kl_job jid) {
         return KL_ESTATE;
     }
     if (j.admitted) rt->resident -= (int64_t)j.footprint;
+    rt->resident -= j.carry;
+    j.carry = 0;
     j.admitted = false;
     j.st = J_CANCELED;
+    rt->live.erase(j.id);
     // dependants can never run: cancel them too
     std::vector<kl_job> todo = j.dependents;
     while (!todo.empty()) {
@@ -1097,8 +1119,11 @@ kl_status kernelet_cancel(kl_runtime* rt, kl_job jid) {
         auto dt = rt->jobs.find(d);
         if (dt == rt->jobs.end() || dt->second.st == J_CANCELED) continue;
         if (dt->second.admitted) rt->resident -= (int64_t)dt->second.footprint;
+        rt->resident -= dt->second.carry;
+        dt->second.carry = 0;
         dt->second.admitted = false;
         dt->second.st = J_CANCELED;
+        rt->live.erase(d);
         for (kl_job x : dt->second.dependents) todo.push_back(x);
     }
     rt->cv.notify_all();
@@ -1188,6 +1213,8 @@ kl_status kernelet_stats(kl_runtime* rt, kl_stats* out) {
     }
     std::lock_guard<std::mutex> g(rt->mu);
     *out = rt->stats;
+    out->resident_bytes = rt->resident;
+    out->resident_peak = rt->resident_peak;
     return KL_OK;
 }
 

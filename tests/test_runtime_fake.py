@@ -213,3 +213,48 @@ def test_memory_budget_admission(L):
     for (s0, b0, d0), (s1, b1, d1) in zip(t, t[1:]):
         assert b1 >= d0 - 1_000_000   # next start after previous completion (1 ms slack)
     h.close()
+
+
+def test_memory_budget_held_until_chain_ends(L):
+    """An instance of three chained launches passes its footprint with the
+    first launch; the budget stays charged until the last one finishes, so a
+    second instance that does not fit beside it starts only after that."""
+    h = Harness(L, hbm_budget=1000)
+    chains = []
+    for c in range(2):
+        prev, jobs = -1, []
+        for k in range(3):
+            visits = np.zeros(8, np.uint32)
+            h.bufs.append(visits)
+            a = VisitArgs(visits.ctypes.data, None, None, 0, 0, 300, 0)
+            prev = h.rt.submit(h.kids[k % 2], (8, 1, 1), a, after=prev,
+                               footprint=600 if k == 0 else 0)
+            jobs.append((prev, visits))
+        chains.append(jobs)
+    _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+    for jobs in chains:
+        for j, v in jobs:
+            h.rt.wait(j, 5_000_000_000)
+            assert np.all(v == 1)
+    first_done = h.rt.job_times(chains[0][-1][0])[2]
+    second_start = h.rt.job_times(chains[1][0][0])[1]
+    assert second_start >= first_done - 1_000_000
+    st = h.rt.stats()
+    assert st["resident_peak"] == 600 and st["resident_bytes"] == 0
+    h.close()
+
+
+def test_many_small_jobs_through_background_scheduler(L):
+    """Finished jobs leave the dispatcher's working set: a long stream of
+    tiny jobs keeps flowing while earlier ones are neither waited on nor
+    reaped."""
+    h = Harness(L)
+    h.rt.schedule("markov", blocking=False)
+    got = [h.job(4, i, kind=i % 2) for i in range(1500)]
+    t0 = time.time()
+    for j in got:
+        h.rt.wait(j[0], 20_000_000_000)
+        assert np.all(j[1] == 1)
+    assert h.rt.stats()["jobs_done"] == 1500
+    assert time.time() - t0 < 20
+    h.close()

@@ -231,6 +231,20 @@ kl_status kernelet_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid,
                           const void* args, uint32_t args_bytes, kl_job after,
                           uint32_t client, uint64_t footprint, kl_job* out);
 
+/* Submit an instance made of `n` dependent launches at once: launch i is
+ * kernel k[i] over the original grid grid[i] with argument block args[i]
+ * (args_bytes[i] bytes, copied), and runs after launch i-1 (launch 0 after
+ * `after`, or KL_NO_JOB).  `footprint` is charged when launch 0 is admitted
+ * and released when launch n-1 finishes: the chain is created under the
+ * runtime's lock, so no launch of it starts before all of them exist.
+ * out[0..n-1] (host) receive the job ids.  All launches are checked first;
+ * on an error none is submitted.  Errors as kernelet_submit, and KL_EINVAL
+ * for n == 0. */
+kl_status kernelet_submit_chain(kl_runtime* rt, uint32_t n, const kl_kernel* k,
+                                const kl_dim3* grid, const void* const* args,
+                                const uint32_t* args_bytes, kl_job after,
+                                uint32_t client, uint64_t footprint, kl_job* out);
+
 /* Fix the slicing plan of a job before it starts: slices of `wgs_per_slice`
  * workgroups (0: the calibrated minimum of its kernel, else its whole
  * grid); *n_slices receives the slice count.  Used by the FIXED policy and

@@ -124,7 +124,7 @@ SYMBOLS = [
     "kernelet_default_config", "kernelet_init", "kernelet_get_config", "kernelet_shutdown",
     "kernelet_last_error", "kernelet_register", "kernelet_builtin",
     "kernelet_builtin_grid", "kernelet_set_profile", "kernelet_get_profile",
-    "kernelet_submit", "kernelet_slice", "kernelet_job_occupancy", "kernelet_schedule",
+    "kernelet_submit", "kernelet_submit_chain", "kernelet_slice", "kernelet_job_occupancy", "kernelet_schedule",
     "kernelet_wait",
     "kernelet_synchronize", "kernelet_cancel", "kernelet_job_times", "kernelet_reap",
     "kernelet_predict", "kernelet_best_ratio", "kernelet_simulate", "kernelet_stats",
@@ -170,6 +170,9 @@ def configure(L):
         "kernelet_get_profile": [C.c_void_p, i32, C.POINTER(Profile)],
         "kernelet_submit": [C.c_void_p, i32, Dim3, C.c_void_p, u32, i64, u32, u64,
                             C.POINTER(i64)],
+        "kernelet_submit_chain": [C.c_void_p, u32, C.POINTER(i32), C.POINTER(Dim3),
+                                  C.POINTER(C.c_void_p), C.POINTER(u32), i64, u32, u64,
+                                  C.POINTER(i64)],
         "kernelet_slice": [C.c_void_p, i64, u32, C.POINTER(u32)],
         "kernelet_job_occupancy": [C.c_void_p, i64, i32],
         "kernelet_schedule": [C.c_void_p, C.c_int, u32],

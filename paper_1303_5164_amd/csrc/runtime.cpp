@@ -679,6 +679,85 @@ static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
     return st;
 }
 
+
+// ------------------------------------------------------------- submission
+// Checks of one launch submitted by the caller (runtime lock held).
+static kl_status check_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid, const void* args,
+                              uint32_t args_bytes, uint64_t footprint, const char* fn) {
+    const std::string f(fn);
+    if (k < 0 || k >= (int)rt->kernels.size()) {
+        set_error(f + ": unknown kernel");
+        return KL_ENOTFOUND;
+    }
+    const KernelType& kt = rt->kernels[k];
+    if (args_bytes != kt.args_bytes) {
+        set_error(f + ": args_bytes differs from the registered size");
+        return KL_EINVAL;
+    }
+    uint64_t total = (uint64_t)grid.x * grid.y * grid.z;
+    if (total == 0 || total > 0xffffffffull) {
+        set_error(f + ": grid must hold 1 .. 2^32-1 workgroups");
+        return KL_EINVAL;
+    }
+    if (kt.builtin) {
+        kl_dim3 need;
+        std::string err;
+        if (!builtin_check(kt.builtin, args, args_bytes, &need, &err)) {
+            set_error(f + "(" + kt.builtin + "): " + err);
+            return KL_EINVAL;
+        }
+        if (need.x != grid.x || need.y != grid.y || need.z != grid.z) {
+            set_error(f + "(" + kt.builtin + "): grid differs from the grid the arguments need");
+            return KL_EINVAL;
+        }
+    }
+    if (rt->cfg.hbm_budget > 0 && (int64_t)footprint > rt->cfg.hbm_budget) {
+        set_error(f + ": footprint exceeds the whole memory budget");
+        return KL_ENOMEM;
+    }
+    return KL_OK;
+}
+
+static kl_status check_after(kl_runtime* rt, kl_job after, const char* fn) {
+    if (after == KL_NO_JOB) return KL_OK;
+    auto it = rt->jobs.find(after);
+    if (it == rt->jobs.end()) {
+        set_error(std::string(fn) + ": unknown `after` job");
+        return KL_ENOTFOUND;
+    }
+    if (it->second.st == J_CANCELED) {
+        set_error(std::string(fn) + ": `after` job was cancelled");
+        return KL_ECANCELED;
+    }
+    return KL_OK;
+}
+
+// Create a checked job (runtime lock held); returns its id.
+static kl_job add_job(kl_runtime* rt, kl_kernel k, kl_dim3 grid, const void* args,
+                      uint32_t args_bytes, kl_job after, uint32_t client, uint64_t footprint) {
+    Job j;
+    j.id = rt->next_id++;
+    j.type = k;
+    j.grid = grid;
+    j.total = (uint32_t)((uint64_t)grid.x * grid.y * grid.z);
+    j.args.assign((const uint8_t*)args, (const uint8_t*)args + args_bytes);
+    j.client = client;
+    j.footprint = footprint;
+    j.t_submit = now_ns();
+    j.after = after;
+    j.st = J_PENDING;
+    if (after != KL_NO_JOB) {
+        Job& p = rt->jobs.at(after);
+        if (p.st == J_WAIT_DEP || p.st == J_PENDING) j.st = J_WAIT_DEP;
+        if (p.st != J_DONE) p.dependents.push_back(j.id);
+    }
+    const kl_job id = j.id;
+    rt->live.insert(id);
+    rt->jobs.emplace(id, std::move(j));
+    rt->stats.jobs_submitted++;
+    return id;
+}
+
 }  // namespace kl
 
 using namespace kl;
@@ -867,67 +946,42 @@ kl_status kernelet_submit(kl_runtime* rt, kl_kernel k, kl_dim3 grid, const void*
         return KL_EINVAL;
     }
     std::unique_lock<std::mutex> lk(rt->mu);
-    if (k < 0 || k >= (int)rt->kernels.size()) {
-        set_error("kernelet_submit: unknown kernel");
-        return KL_ENOTFOUND;
-    }
-    const KernelType& kt = rt->kernels[k];
-    if (args_bytes != kt.args_bytes) {
-        set_error("kernelet_submit: args_bytes differs from the registered size");
+    if (kl_status s = check_submit(rt, k, grid, args, args_bytes, footprint, "kernelet_submit"))
+        return s;
+    if (kl_status s = check_after(rt, after, "kernelet_submit")) return s;
+    *out = add_job(rt, k, grid, args, args_bytes, after, client, footprint);
+    lk.unlock();
+    rt->cv.notify_all();
+    return KL_OK;
+}
+
+kl_status kernelet_submit_chain(kl_runtime* rt, uint32_t n, const kl_kernel* k,
+                                const kl_dim3* grid, const void* const* args,
+                                const uint32_t* args_bytes, kl_job after, uint32_t client,
+                                uint64_t footprint, kl_job* out) {
+    if (!rt || n == 0 || !k || !grid || !args || !args_bytes || !out) {
+        set_error("kernelet_submit_chain: null argument or empty chain");
         return KL_EINVAL;
     }
-    uint64_t total = (uint64_t)grid.x * grid.y * grid.z;
-    if (total == 0 || total > 0xffffffffull) {
-        set_error("kernelet_submit: grid must hold 1 .. 2^32-1 workgroups");
-        return KL_EINVAL;
-    }
-    if (kt.builtin) {
-        kl_dim3 need;
-        std::string err;
-        if (!builtin_check(kt.builtin, args, args_bytes, &need, &err)) {
-            set_error(std::string("kernelet_submit(") + kt.builtin + "): " + err);
+    std::unique_lock<std::mutex> lk(rt->mu);
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!args[i]) {
+            set_error("kernelet_submit_chain: null argument block");
             return KL_EINVAL;
         }
-        if (need.x != grid.x || need.y != grid.y || need.z != grid.z) {
-            set_error(std::string("kernelet_submit(") + kt.builtin +
-                      "): grid differs from the grid the arguments need");
-            return KL_EINVAL;
-        }
+        if (kl_status s = check_submit(rt, k[i], grid[i], args[i], args_bytes[i],
+                                       i == 0 ? footprint : 0, "kernelet_submit_chain"))
+            return s;
     }
-    if (rt->cfg.hbm_budget > 0 && (int64_t)footprint > rt->cfg.hbm_budget) {
-        set_error("kernelet_submit: footprint exceeds the whole memory budget");
-        return KL_ENOMEM;
+    if (kl_status s = check_after(rt, after, "kernelet_submit_chain")) return s;
+    // every launch exists before the dispatcher (which needs this lock) can
+    // start the first, so the footprint always travels to the last one
+    kl_job prev = after;
+    for (uint32_t i = 0; i < n; ++i) {
+        prev = add_job(rt, k[i], grid[i], args[i], args_bytes[i], prev, client,
+                       i == 0 ? footprint : 0);
+        out[i] = prev;
     }
-    Job j;
-    j.id = rt->next_id;
-    j.type = k;
-    j.grid = grid;
-    j.total = (uint32_t)total;
-    j.args.assign((const uint8_t*)args, (const uint8_t*)args + args_bytes);
-    j.client = client;
-    j.footprint = footprint;
-    j.t_submit = now_ns();
-    j.after = after;
-    j.st = J_PENDING;
-    if (after != KL_NO_JOB) {
-        auto it = rt->jobs.find(after);
-        if (it == rt->jobs.end()) {
-            set_error("kernelet_submit: unknown `after` job");
-            return KL_ENOTFOUND;
-        }
-        Job& p = it->second;
-        if (p.st == J_CANCELED) {
-            set_error("kernelet_submit: `after` job was cancelled");
-            return KL_ECANCELED;
-        }
-        if (p.st == J_WAIT_DEP || p.st == J_PENDING) j.st = J_WAIT_DEP;
-        if (p.st != J_DONE) p.dependents.push_back(j.id);
-    }
-    rt->next_id++;
-    rt->live.insert(j.id);
-    rt->jobs.emplace(j.id, std::move(j));
-    rt->stats.jobs_submitted++;
-    *out = rt->next_id - 1;
     lk.unlock();
     rt->cv.notify_all();
     return KL_OK;

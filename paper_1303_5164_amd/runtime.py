@@ -153,6 +153,20 @@ class Runtime:
              client, footprint, C.byref(j))
         return j.value
 
+    def submit_chain(self, launches, after: int = -1, client: int = 0,
+                     footprint: int = 0) -> list:
+        """Submit dependent launches [(kernel id, grid, args), ...] as one
+        instance; the footprint is held from the first to the last."""
+        n = len(launches)
+        ks = (C.c_int32 * n)(*[k for k, _, _ in launches])
+        gs = (Dim3 * n)(*[g if isinstance(g, Dim3) else Dim3(*g) for _, g, _ in launches])
+        ps = (C.c_void_p * n)(*[C.addressof(a) for _, _, a in launches])
+        bs = (C.c_uint32 * n)(*[C.sizeof(a) for _, _, a in launches])
+        out = (C.c_int64 * n)()
+        self._c("kernelet_submit_chain", self.h, n, ks, gs, ps, bs, after, client, footprint,
+                out)
+        return list(out)
+
     def slice(self, job: int, wgs_per_slice: int) -> int:
         n = C.c_uint32()
         self._c("kernelet_slice", self.h, job, wgs_per_slice, C.byref(n))

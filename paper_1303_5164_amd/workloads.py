@@ -142,11 +142,8 @@ def build(kind: str, dev_in: dict, params: dict, device) -> Instance:
 
 
 def submit(rt, kernel_ids: dict, inst: Instance, client: int = 0, after: int = -1):
-    """Submit an instance's launches (chained in order); returns job ids."""
-    jobs = []
-    prev = after
-    for ln in inst.launches:
-        prev = rt.submit(kernel_ids[ln.kernel or inst.kind], ln.grid, ln.args, after=prev,
-                         client=client, footprint=inst.footprint if not jobs else 0)
-        jobs.append(prev)
-    return jobs
+    """Submit an instance's launches as one chain (each after the previous;
+    the footprint held until the last finishes); returns the job ids."""
+    return rt.submit_chain([(kernel_ids[ln.kernel or inst.kind], ln.grid, ln.args)
+                            for ln in inst.launches], after=after, client=client,
+                           footprint=inst.footprint)

@@ -258,3 +258,43 @@ def test_many_small_jobs_through_background_scheduler(L):
     assert h.rt.stats()["jobs_done"] == 1500
     assert time.time() - t0 < 20
     h.close()
+
+
+def test_submit_chain_is_atomic_and_holds_the_footprint(L):
+    """A chain submitted while the background scheduler runs: the first
+    launch cannot finish before the rest exist, so the footprint is released
+    only by the last; a chain with one bad launch submits nothing."""
+    h = Harness(L, hbm_budget=1000)
+    h.rt.schedule("markov", blocking=False)
+    chains = []
+    for c in range(4):
+        launches, vis = [], []
+        for k in range(3):
+            visits = np.zeros(8, np.uint32)
+            h.bufs.append(visits)
+            vis.append(visits)
+            a = VisitArgs(visits.ctypes.data, None, None, 0, 0, 0 if k == 0 else 300, 0)
+            h.bufs.append(a)
+            launches.append((h.kids[k % 2], (8, 1, 1), a))
+        chains.append((h.rt.submit_chain(launches, footprint=600), vis))
+    for ids, vis in chains:
+        for j in ids:
+            h.rt.wait(j, 10_000_000_000)
+        assert all(np.all(v == 1) for v in vis)
+    # 600-byte instances under a 1000-byte budget never overlapped
+    spans = sorted((h.rt.job_times(ids[0])[1], h.rt.job_times(ids[-1])[2]) for ids, _ in chains)
+    for (s0, d0), (s1, d1) in zip(spans, spans[1:]):
+        assert s1 >= d0 - 1_000_000
+    st = h.rt.stats()
+    assert st["resident_peak"] == 600 and st["resident_bytes"] == 0
+    before = st["jobs_submitted"]
+    visits = np.zeros(8, np.uint32)
+    good = VisitArgs(visits.ctypes.data, None, None, 0, 0, 0, 0)
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.submit_chain([(h.kids[0], (8, 1, 1), good), (h.kids[1], (0, 1, 1), good)])
+    assert e.value.code == -1
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.submit_chain([(h.kids[0], (8, 1, 1), good)], footprint=5000)
+    assert e.value.code == -2
+    assert h.rt.stats()["jobs_submitted"] == before
+    h.close()

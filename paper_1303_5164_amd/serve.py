@@ -157,12 +157,14 @@ class Server:
         self.log(f"inputs of {len(self.inputs)} (kind, size) classes on the device")
 
     def new_instance(self, kind, c, stream=None):
-        inst = self.W.build(kind, self.inputs[kind, c], params_of(kind), self.dev)
-        if kind == "hist":   # the bins start at zero before the kernel runs
-            s = stream or self.torch.cuda.current_stream()
-            with self.torch.cuda.stream(s):
-                inst.tensors["bins"].zero_()
-            s.synchronize()
+        """A new instance over the shared inputs of (kind, size class).  Its
+        outputs are allocated, and the histogram's bins zeroed, on `stream`
+        (default: the current one), which is synchronised before return: the
+        runtime's lanes do not wait for torch's streams."""
+        s = stream or self.torch.cuda.current_stream()
+        with self.torch.cuda.stream(s):
+            inst = self.W.build(kind, self.inputs[kind, c], params_of(kind), self.dev)
+        s.synchronize()
         return inst
 
     def runtime(self, **cfg):
@@ -236,7 +238,8 @@ class Server:
         for th in threads:
             th.start()
         recs = []
-        n_verified = n_mismatch = 0
+        n_verified = 0
+        bad = []
         try:
             for i in range(n):
                 ready[i].wait()
@@ -256,7 +259,8 @@ class Server:
                                             self.ref[r["kind"], r["size"]]))
                     rec["verified"] = same
                     n_verified += 1
-                    n_mismatch += 0 if same else 1
+                    if not same:
+                        bad.append({"i": i, "kind": r["kind"], "size": r["size"]})
                 recs.append(rec)
                 slots[i] = None
             for th in threads:
@@ -276,7 +280,7 @@ class Server:
             "max_client_lag_ms": max(r["lag_ms"] for r in recs),
             "resident_peak_bytes": st["resident_peak"],
             "decisions": st["decisions"], "slices": st["slices_launched"],
-            "verified": n_verified, "mismatches": n_mismatch,
+            "verified": n_verified, "mismatches": len(bad), "mismatched": bad[:20],
         }
         return recs, summary
 

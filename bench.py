@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cp-min", type=float, default=None)
     ap.add_argument("--estimates", action="store_true",
                     help="use the first-order profile estimates, not the measured table")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 1 GiB once before the steps (a kernel of known traffic that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
     return ap.parse_args()
 
 
@@ -211,6 +214,13 @@ def main():
             w["flops"] += ff
             w["bytes"] += bb
             w["wgs"] += ln.grid[0] * ln.grid[1] * ln.grid[2]
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     legs = [l for l in args.legs.split(",") if l]
     times = {l: [] for l in legs}

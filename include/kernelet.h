@@ -81,7 +81,8 @@ typedef struct {
     int32_t vgpr;          /* VGPRs per lane (0: not limiting)             */
     int32_t lds_bytes;     /* static LDS bytes per workgroup               */
     int32_t min_slice_wgs; /* calibrated minimum slice (0: unknown)        */
-    int32_t reserved;
+    int32_t access;        /* dominant access pattern: 0 coalesced,
+                              1 strided, 2 random (a surrogate feature)    */
 } kl_profile;
 
 #define KL_KF_IDEMPOTENT 1u /* re-running a slice gives the same result */
@@ -149,6 +150,9 @@ typedef struct {
     int64_t cache_hits;
     int64_t resident_bytes;     /* footprint admitted and not yet released */
     int64_t resident_peak;      /* largest resident_bytes so far */
+    double surrogate_us_total;  /* host time of surrogate scoring (SURROGATE) */
+    int64_t surrogate_candidates; /* (pair, ratio) candidates scored */
+    int64_t surrogate_pairs;    /* pairs ranked by the surrogate */
 } kl_stats;
 
 /* One scheduling decision, as logged (Algorithm 1, one co-schedule). */
@@ -320,6 +324,28 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
  * b2 [64], W3 [64], b3) trained by mean-squared error and Adam on co-run
  * speedups.  Kernels run on `stream` (a hipStream_t; NULL = the default
  * stream) and are asynchronous.  All arrays are device memory. */
+
+#define KL_MLP_PARAMS 5313
+
+/* Load trained surrogate parameters (host, n_params == KL_MLP_PARAMS floats,
+ * copied) into the runtime; required by KL_POLICY_SURROGATE.  In that
+ * policy each decision scores every feasible slice ratio of every pair that
+ * survives pruning in one batched inference on the device (its own
+ * stream), keeps the cfg.surrogate_topk pairs of highest predicted weighted
+ * speedup and lets the Markov model choose among them (Kernelet, Section
+ * 4.3 with the model of Section 4.4 as the judge).  Errors: KL_EINVAL,
+ * KL_EHIP. */
+kl_status kernelet_set_surrogate(kl_runtime* rt, const float* params, uint32_t n_params);
+
+/* The 16 input features of a candidate (kernel a at b1, kernel b at b2
+ * workgroups per CU; host arrays): per kernel the memory-instruction ratio
+ * r_mem, log2(clamp((1 - r_mem) / r_mem, 1, 64)) / 6, lds_bytes / 65536,
+ * vgpr / 256, the access one-hot (coalesced, strided, random) and
+ * b / cfg->wmax (cfg NULL: defaults).  KL_EINVAL for a bad profile or a
+ * ratio that does not fit on one CU. */
+kl_status kernelet_surrogate_features(const kl_config* cfg, const kl_profile* a,
+                                      const kl_profile* b, int32_t b1, int32_t b2,
+                                      float* out16);
 
 /* Floats of scratch a training step over `batch` samples needs. */
 uint64_t kernelet_mlp_workspace_floats(uint32_t batch);

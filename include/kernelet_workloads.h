@@ -132,6 +132,28 @@ typedef struct {
     uint32_t spin;
 } kl_probe_args;
 
+/* synthk_v<V>_l<L> (synthetic kernels of known character, the training
+ * population of the surrogate model): thread t (t < n_threads) runs `iters`
+ * iterations of one load of src[addr] followed by a chain of `alu`
+ * dependent fmas on it; dst[t] receives the result.  addr is
+ *   pattern 0 (coalesced): (t + it * n_threads) & mask,
+ *   pattern 1 (strided):   (32 t + 7919 it) & mask (one 128-byte line per lane),
+ *   pattern 2 (random):    a per-thread linear congruential sequence & mask.
+ * The compile-time classes hold about V in {32, 64, 128, 256} VGPRs per lane
+ * live across the loop and L in {0, 16, 32, 64} KiB of static LDS per
+ * workgroup.  src holds mask + 1 floats (a power of two); dst n_threads;
+ * grid = ceil(n_threads / 256); alu <= 4096, iters <= 2^20. */
+typedef struct {
+    const float* src;
+    float* dst;
+    uint32_t mask;
+    uint32_t n_threads;
+    uint32_t iters;
+    uint32_t alu;
+    uint32_t pattern;
+    uint32_t reserved;
+} kl_synthk_args;
+
 #ifdef __cplusplus
 }
 #endif

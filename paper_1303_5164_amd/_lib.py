@@ -33,7 +33,7 @@ class Profile(C.Structure):
                 ("pur", C.c_double), ("mur", C.c_double), ("solo_ipc", C.c_double),
                 ("max_wg_per_cu", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("vgpr", C.c_int32), ("lds_bytes", C.c_int32),
-                ("min_slice_wgs", C.c_int32), ("reserved", C.c_int32)]
+                ("min_slice_wgs", C.c_int32), ("access", C.c_int32)]
 
 
 class KernelDesc(C.Structure):
@@ -58,7 +58,8 @@ class Stats(C.Structure):
                 ("slices_launched", C.c_int64), ("decisions", C.c_int64),
                 ("decision_us_total", C.c_double), ("model_us_total", C.c_double),
                 ("cache_hits", C.c_int64), ("resident_bytes", C.c_int64),
-                ("resident_peak", C.c_int64)]
+                ("resident_peak", C.c_int64), ("surrogate_us_total", C.c_double),
+                ("surrogate_candidates", C.c_int64), ("surrogate_pairs", C.c_int64)]
 
 
 class Decision(C.Structure):
@@ -111,13 +112,24 @@ class LookupArgs(C.Structure):
                 ("nq", C.c_uint32)]
 
 
+class SynthkArgs(C.Structure):
+    _fields_ = [("src", P), ("dst", P), ("mask", C.c_uint32), ("n_threads", C.c_uint32),
+                ("iters", C.c_uint32), ("alu", C.c_uint32), ("pattern", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+SYNTHK_VGPR = (32, 64, 128, 256)
+SYNTHK_LDS_KB = (0, 16, 32, 64)
+SYNTHK = [f"synthk_v{v}_l{l}" for v in SYNTHK_VGPR for l in SYNTHK_LDS_KB]
+
+
 class ProbeArgs(C.Structure):
     _fields_ = [("visits", P), ("info", P), ("n_wg", C.c_uint32), ("spin", C.c_uint32)]
 
 
 ARGS = {"probe": ProbeArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
         "stencil": StencilArgs, "bs": BsArgs, "hist": HistArgs, "lookup": LookupArgs,
-        "lookup_index": LookupArgs}
+        "lookup_index": LookupArgs, **{k: SynthkArgs for k in SYNTHK}}
 
 # every symbol include/kernelet.h declares
 SYMBOLS = [
@@ -130,7 +142,7 @@ SYMBOLS = [
     "kernelet_predict", "kernelet_best_ratio", "kernelet_simulate", "kernelet_stats",
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
-    "kernelet_mlp_train_step",
+    "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
 ]
 
 _lib = None
@@ -195,20 +207,24 @@ def configure(L):
         "kernelet_kernel_info": [C.c_void_p, i32, C.POINTER(i32), C.POINTER(i32),
                                  C.POINTER(i32)],
         "kernelet_kernel_time": [C.c_void_p, i32, PD, C.POINTER(i64), C.POINTER(i64)],
+        "kernelet_set_surrogate": [C.c_void_p, C.c_void_p, u32],
+        "kernelet_surrogate_features": [C.POINTER(Config), C.POINTER(Profile),
+                                        C.POINTER(Profile), i32, i32, C.c_void_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = i32
-    if hasattr(L, "kernelet_mlp_forward"):
-        f32p = C.c_void_p
-        L.kernelet_mlp_workspace_floats.argtypes = [u32]
-        L.kernelet_mlp_workspace_floats.restype = u64
-        L.kernelet_mlp_forward.argtypes = [f32p, f32p, u32, f32p, C.c_void_p]
-        L.kernelet_mlp_forward.restype = i32
-        L.kernelet_mlp_train_step.argtypes = [f32p, f32p, f32p, f32p, f32p, f32p, u32, u32,
-                                              C.c_float, f32p, f32p, C.c_void_p]
-        L.kernelet_mlp_train_step.restype = i32
+    # the network's device entry points (absent from a CPU test double)
+    f32p = C.c_void_p
+    opt = {"kernelet_mlp_workspace_floats": ([u32], u64),
+           "kernelet_mlp_forward": ([f32p, f32p, u32, f32p, C.c_void_p], i32),
+           "kernelet_mlp_train_step": ([f32p, f32p, f32p, f32p, f32p, f32p, u32, u32,
+                                        C.c_float, f32p, f32p, C.c_void_p], i32)}
+    for name, (args, res) in opt.items():
+        if hasattr(L, name):
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = res
     if hasattr(L, "kernelet_lookup_index_entries"):
         L.kernelet_lookup_index_entries.argtypes = [C.c_uint32]
         L.kernelet_lookup_index_entries.restype = C.c_uint64

@@ -209,6 +209,28 @@ double solo_ipc(const kl_profile& p, const kl_config& cfg) {
     return ipc;
 }
 
+bool ratio_feasible(const kl_profile& p1, const kl_profile& p2, const kl_config& cfg,
+                    int b1, int b2) {
+    if (b1 < 1 || b2 < 1 || b1 > p1.max_wg_per_cu || b2 > p2.max_wg_per_cu) return false;
+    const int w1 = b1 * p1.waves_per_simd, w2 = b2 * p2.waves_per_simd;
+    if (w1 + w2 > cfg.wmax) return false;
+    if (w1 * p1.vgpr + w2 * p2.vgpr > cfg.vgpr_file) return false;
+    return (int64_t)b1 * p1.lds_bytes + (int64_t)b2 * p2.lds_bytes <= cfg.lds_cu;
+}
+
+void surrogate_features(const kl_profile& p, int b, int wmax, float* f) {
+    const double r = p.r_mem;
+    const double alu = r > 0 ? (1.0 - r) / r : 64.0;
+    f[0] = (float)r;
+    f[1] = (float)(std::log2(std::min(64.0, std::max(1.0, alu))) / 6.0);
+    f[2] = (float)(p.lds_bytes / 65536.0);
+    f[3] = (float)(p.vgpr / 256.0);
+    f[4] = p.access == 0 ? 1.f : 0.f;
+    f[5] = p.access == 1 ? 1.f : 0.f;
+    f[6] = p.access == 2 ? 1.f : 0.f;
+    f[7] = (float)b / (float)(wmax > 0 ? wmax : 8);
+}
+
 static Ratio best_ratio_with(const kl_profile& p1, const kl_profile& p2,
                              const kl_config& cfg, double s1, double s2) {
     Ratio best;
@@ -216,11 +238,8 @@ static Ratio best_ratio_with(const kl_profile& p1, const kl_profile& p2,
     KernelModel km[2] = {kernel_model(p1, cfg), kernel_model(p2, cfg)};
     for (int b1 = 1; b1 <= p1.max_wg_per_cu; ++b1) {
         for (int b2 = 1; b2 <= p2.max_wg_per_cu; ++b2) {
+            if (!ratio_feasible(p1, p2, cfg, b1, b2)) continue;
             int w[2] = {b1 * p1.waves_per_simd, b2 * p2.waves_per_simd};
-            if (w[0] + w[1] > cfg.wmax) continue;
-            if (w[0] * p1.vgpr + w[1] * p2.vgpr > cfg.vgpr_file) continue;
-            if ((int64_t)b1 * p1.lds_bytes + (int64_t)b2 * p2.lds_bytes > cfg.lds_cu)
-                continue;
             double c[2];
             chain_ipc(km, w, 2, cfg.beta, c);
             double solo[2] = {s1, s2};
@@ -313,6 +332,17 @@ Ratio Planner::pair(int t1, int t2) {
 
 Decision Planner::find(const std::vector<PendingJob>& pending,
                        const std::vector<std::pair<int, int>>* only_pairs) {
+    return search(pending, only_pairs, 0, nullptr);
+}
+
+Decision Planner::find_ranked(const std::vector<PendingJob>& pending, int k,
+                              const Scorer& score) {
+    return search(pending, nullptr, k, &score);
+}
+
+Decision Planner::search(const std::vector<PendingJob>& pending,
+                         const std::vector<std::pair<int, int>>* only_pairs, int k,
+                         const Scorer* score) {
     std::lock_guard<std::mutex> g(mu_);
     Decision solo_d;
     if (pending.empty()) return solo_d;
@@ -350,6 +380,23 @@ Decision Planner::find(const std::vector<PendingJob>& pending,
             am /= 2.0;
         }
         if (!keep.empty()) pairs.swap(keep);
+    }
+    if (score && k > 0 && (int)pairs.size() > k) {
+        std::vector<std::pair<const kl_profile*, const kl_profile*>> pp;
+        for (auto& pr : pairs)
+            pp.emplace_back(&types_[order[pr.first].type], &types_[order[pr.second].type]);
+        std::vector<double> sc;
+        if ((*score)(pp, &sc) && sc.size() == pairs.size()) {
+            scored_pairs += (int64_t)pairs.size();
+            std::vector<int> idx(pairs.size());
+            for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+            // best scores first; ties keep submission order
+            std::stable_sort(idx.begin(), idx.end(),
+                             [&](int x, int y) { return sc[x] > sc[y]; });
+            std::vector<std::pair<int, int>> top;
+            for (int i = 0; i < k; ++i) top.push_back(pairs[idx[i]]);
+            pairs.swap(top);
+        }
     }
     Decision best;
     bool have = false;

@@ -12,6 +12,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -55,6 +56,17 @@ Ratio best_ratio(const kl_profile& p1, const kl_profile& p2,
 bool pair_pruned(const kl_profile& a, const kl_profile& b, double ap,
                  double am);
 
+// Whether b1 and b2 workgroups per CU of two kernels fit on one CU
+// together: wave slots per SIMD, VGPR file and LDS.
+bool ratio_feasible(const kl_profile& p1, const kl_profile& p2, const kl_config& cfg,
+                    int b1, int b2);
+
+// The surrogate network's eight input features of one kernel at b
+// workgroups per CU: memory-instruction ratio, log2(ALU instructions per
+// memory instruction, clamped to [1, 64]) / 6, LDS bytes / 64 KiB,
+// VGPRs / 256, access pattern one-hot (coalesced, strided, random), b / wmax.
+void surrogate_features(const kl_profile& p, int b, int wmax, float* out8);
+
 // One pending job as seen by FindCoSchedule.
 struct PendingJob {
     int64_t id;    // submission order key (smaller = earlier)
@@ -76,16 +88,28 @@ class Planner {
     const kl_config& cfg() const { return cfg_; }
     double solo(int t);
     Ratio pair(int t1, int t2);
-    // FindCoSchedule over pending jobs (any order); `score` (optional)
-    // restricts the Markov evaluation to the pairs it ranks highest.
+    // FindCoSchedule over pending jobs (any order); `only_pairs` (optional)
+    // restricts the search to the listed type pairs.
     Decision find(const std::vector<PendingJob>& pending,
                   const std::vector<std::pair<int, int>>* only_pairs = nullptr);
+    // Scores candidate pairs given their two profiles (higher = better);
+    // false if it could not (then every pair is evaluated).
+    using Scorer = std::function<bool(
+        const std::vector<std::pair<const kl_profile*, const kl_profile*>>&,
+        std::vector<double>*)>;
+    // FindCoSchedule in which the pairs surviving pruning are ranked by
+    // `score` and only the best `k` are evaluated by the Markov model.
+    Decision find_ranked(const std::vector<PendingJob>& pending, int k, const Scorer& score);
+    int64_t scored_pairs = 0;
     const kl_profile& prof(int t) const { return types_[t]; }
     int ntypes() const { return (int)types_.size(); }
     double model_us = 0;
     int64_t cache_hits = 0;
 
   private:
+    Decision search(const std::vector<PendingJob>& pending,
+                    const std::vector<std::pair<int, int>>* only_pairs, int k,
+                    const Scorer* score);
     kl_config cfg_;
     std::vector<kl_profile> types_;
     std::map<int, double> solo_;

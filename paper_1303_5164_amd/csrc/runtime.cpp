@@ -173,6 +173,15 @@ struct kl_runtime {
     // launch timing
     std::deque<kl::TimedLaunch> timed;
     std::vector<hipEvent_t> tev_free;
+    // surrogate network (kernelet_set_surrogate): parameters and batch
+    // buffers on the device, staging in pinned host memory, its own stream
+    float* sur_params = nullptr;
+    float* sur_x = nullptr;
+    float* sur_y = nullptr;
+    float* sur_hx = nullptr;
+    float* sur_hy = nullptr;
+    uint32_t sur_cap = 0;
+    hipStream_t sur_stream = nullptr;
 };
 
 namespace kl {
@@ -213,7 +222,8 @@ static kl_status check_cfg(const kl_config& c) {
 static kl_status check_profile(const kl_profile& p) {
     if (!(p.r_mem >= 0 && p.r_comp >= 0 && p.r_mem + p.r_comp <= 1.0) || p.mem_req < 0 ||
         p.lat_mem < 0 || (p.r_comp > 0 && !(p.lat_comp >= 1.0)) || !(p.instr_per_wave > 0) ||
-        p.max_wg_per_cu < 1 || p.waves_per_simd < 1 || p.vgpr < 0 || p.lds_bytes < 0) {
+        p.max_wg_per_cu < 1 || p.waves_per_simd < 1 || p.vgpr < 0 || p.lds_bytes < 0 ||
+        p.access < 0 || p.access > 2) {
         set_error("invalid kl_profile field");
         return KL_EINVAL;
     }
@@ -477,6 +487,67 @@ static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
     return KL_OK;
 }
 
+// Surrogate scores of candidate pairs: one batched inference over every
+// feasible slice ratio of every pair; a pair's score is its best predicted
+// weighted speedup.  False (the caller then evaluates every pair with the
+// Markov model) on a device error.
+static bool surrogate_scores(
+    kl_runtime* rt, const std::vector<std::pair<const kl_profile*, const kl_profile*>>& pp,
+    std::vector<double>* scores) {
+    auto t0 = std::chrono::steady_clock::now();
+    const kl_config& c = rt->cfg;
+    std::vector<int> owner;  // candidate -> pair
+    std::vector<float> feat;
+    for (size_t i = 0; i < pp.size(); ++i) {
+        const kl_profile& a = *pp[i].first;
+        const kl_profile& b = *pp[i].second;
+        for (int b1 = 1; b1 <= a.max_wg_per_cu; ++b1)
+            for (int b2 = 1; b2 <= b.max_wg_per_cu; ++b2) {
+                if (!ratio_feasible(a, b, c, b1, b2)) continue;
+                float f[16];
+                surrogate_features(a, b1, c.wmax, f);
+                surrogate_features(b, b2, c.wmax, f + 8);
+                feat.insert(feat.end(), f, f + 16);
+                owner.push_back((int)i);
+            }
+    }
+    const uint32_t n = (uint32_t)owner.size();
+    scores->assign(pp.size(), -1e30);
+    if (n == 0) return true;
+    if (n > rt->sur_cap) {
+        uint32_t cap = 1024;
+        while (cap < n) cap *= 2;
+        (void)hipFree(rt->sur_x);
+        (void)hipFree(rt->sur_y);
+        (void)hipHostFree(rt->sur_hx);
+        (void)hipHostFree(rt->sur_hy);
+        rt->sur_x = rt->sur_y = rt->sur_hx = rt->sur_hy = nullptr;
+        rt->sur_cap = 0;
+        if (hipMalloc((void**)&rt->sur_x, (size_t)cap * 16 * sizeof(float)) != hipSuccess ||
+            hipMalloc((void**)&rt->sur_y, (size_t)cap * sizeof(float)) != hipSuccess ||
+            hipHostMalloc((void**)&rt->sur_hx, (size_t)cap * 16 * sizeof(float)) != hipSuccess ||
+            hipHostMalloc((void**)&rt->sur_hy, (size_t)cap * sizeof(float)) != hipSuccess)
+            return false;
+        rt->sur_cap = cap;
+    }
+    std::memcpy(rt->sur_hx, feat.data(), feat.size() * sizeof(float));
+    if (hipMemcpyAsync(rt->sur_x, rt->sur_hx, feat.size() * sizeof(float),
+                       hipMemcpyHostToDevice, rt->sur_stream) != hipSuccess)
+        return false;
+    if (kernelet_mlp_forward(rt->sur_params, rt->sur_x, n, rt->sur_y, rt->sur_stream) != KL_OK)
+        return false;
+    if (hipMemcpyAsync(rt->sur_hy, rt->sur_y, n * sizeof(float), hipMemcpyDeviceToHost,
+                       rt->sur_stream) != hipSuccess ||
+        hipStreamSynchronize(rt->sur_stream) != hipSuccess)
+        return false;
+    for (uint32_t k = 0; k < n; ++k)
+        (*scores)[owner[k]] = std::max((*scores)[owner[k]], (double)rt->sur_hy[k]);
+    rt->stats.surrogate_us_total +=
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    rt->stats.surrogate_candidates += n;
+    return true;
+}
+
 // Choose the next co-schedule (FindCoSchedule) and bind it to lanes.
 static void decide(kl_runtime* rt, kl_policy policy) {
     std::vector<PendingJob> pend;
@@ -510,6 +581,11 @@ static void decide(kl_runtime* rt, kl_policy policy) {
                 d.b2 = occ(d.j2);
                 break;
             }
+    } else if (policy == KL_POLICY_SURROGATE) {
+        d = rt->planner->find_ranked(
+            pend, std::max(1, rt->cfg.surrogate_topk),
+            [rt](const std::vector<std::pair<const kl_profile*, const kl_profile*>>& pp,
+                 std::vector<double>* sc) { return surrogate_scores(rt, pp, sc); });
     } else {
         d = rt->planner->find(pend);
     }
@@ -834,6 +910,12 @@ kl_status kernelet_shutdown(kl_runtime* rt) {
         (void)hipEventDestroy(t.b);
     }
     for (auto e : rt->tev_free) (void)hipEventDestroy(e);
+    if (rt->sur_stream) (void)hipStreamDestroy(rt->sur_stream);
+    (void)hipFree(rt->sur_params);
+    (void)hipFree(rt->sur_x);
+    (void)hipFree(rt->sur_y);
+    (void)hipHostFree(rt->sur_hx);
+    (void)hipHostFree(rt->sur_hy);
     delete rt;
     return KL_OK;
 }
@@ -1046,6 +1128,10 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
         std::lock_guard<std::mutex> g(rt->mu);
         if (rt->scheduling || rt->worker_running) {
             set_error("kernelet_schedule: a scheduler is already running");
+            return KL_ESTATE;
+        }
+        if (policy == KL_POLICY_SURROGATE && !rt->sur_params) {
+            set_error("kernelet_schedule: the surrogate policy needs kernelet_set_surrogate");
             return KL_ESTATE;
         }
         if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED) {
@@ -1267,8 +1353,48 @@ kl_status kernelet_stats(kl_runtime* rt, kl_stats* out) {
     }
     std::lock_guard<std::mutex> g(rt->mu);
     *out = rt->stats;
+    out->surrogate_pairs = rt->planner->scored_pairs;
     out->resident_bytes = rt->resident;
     out->resident_peak = rt->resident_peak;
+    return KL_OK;
+}
+
+kl_status kernelet_set_surrogate(kl_runtime* rt, const float* params, uint32_t n_params) {
+    if (!rt || !params) {
+        set_error("kernelet_set_surrogate: null argument");
+        return KL_EINVAL;
+    }
+    if (n_params != KL_MLP_PARAMS) {
+        set_error("kernelet_set_surrogate: the network has KL_MLP_PARAMS parameters");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    KL_HIP(hipSetDevice(rt->device));
+    if (!rt->sur_stream) KL_HIP(hipStreamCreateWithFlags(&rt->sur_stream, hipStreamNonBlocking));
+    if (!rt->sur_params)
+        KL_HIP(hipMalloc((void**)&rt->sur_params, KL_MLP_PARAMS * sizeof(float)));
+    KL_HIP(hipMemcpyAsync(rt->sur_params, params, KL_MLP_PARAMS * sizeof(float),
+                          hipMemcpyHostToDevice, rt->sur_stream));
+    KL_HIP(hipStreamSynchronize(rt->sur_stream));
+    return KL_OK;
+}
+
+kl_status kernelet_surrogate_features(const kl_config* cfg, const kl_profile* a,
+                                      const kl_profile* b, int32_t b1, int32_t b2,
+                                      float* out16) {
+    if (!a || !b || !out16) {
+        set_error("kernelet_surrogate_features: null argument");
+        return KL_EINVAL;
+    }
+    const kl_config c = cfg ? *cfg : defaults();
+    if (kl_status s = check_profile(*a)) return s;
+    if (kl_status s = check_profile(*b)) return s;
+    if (!ratio_feasible(*a, *b, c, b1, b2)) {
+        set_error("kernelet_surrogate_features: the ratio does not fit on one CU");
+        return KL_EINVAL;
+    }
+    surrogate_features(*a, b1, c.wmax, out16);
+    surrogate_features(*b, b2, c.wmax, out16 + 8);
     return KL_OK;
 }
 

@@ -185,13 +185,15 @@ __global__ __launch_bounds__(KL_WG) void kl_stencil(kl_stencil_args a, kl_slice 
     float* __restrict__ out = a.out;
     const float c0 = a.c0, c1 = a.c1;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    float4 up = y0 > 0 ? *(const float4*)(in + (size_t)(y0 - 1) * nx + xc) : zero;
+    float4 up = zero;
+    if (y0 > 0) up = *(const float4*)(in + (size_t)(y0 - 1) * nx + xc);
     float4 mid = *(const float4*)(in + (size_t)y0 * nx + xc);
     for (int r = 0; r < 8; ++r) {
         const uint32_t y = y0 + r;
         if (y >= ny) break;                 // uniform over the wave
         const size_t row = (size_t)y * nx;
-        const float4 down = y + 1 < ny ? *(const float4*)(in + row + nx + xc) : zero;
+        float4 down = zero;
+        if (y + 1 < ny) down = *(const float4*)(in + row + nx + xc);
         float w = __shfl_up(mid.w, 1);
         float e = __shfl_down(mid.x, 1);
         if (lane == 0) w = (act && x0 > 0) ? in[row + x0 - 1] : 0.0f;
@@ -280,16 +282,24 @@ struct LkLevels {
     uint64_t total;   // entries including padding
 };
 
+// Fully unrolled so that every array index is a constant: the level
+// tables stay in registers (n < 2^31 needs at most 6 levels).
 __host__ __device__ inline void lk_levels(uint32_t n, LkLevels* L) {
     uint64_t m = ((uint64_t)n + 15) / 16, off = 0;
+    bool done = false;
     L->nlev = 0;
-    for (;;) {
-        L->m[L->nlev] = m;
-        L->off[L->nlev] = off;
-        L->nlev++;
-        off += (m + 15) / 16 * 16;
-        if (m <= 1024) break;
-        m = (m + 15) / 16;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        L->m[k] = done ? 0 : m;
+        L->off[k] = off;
+        if (!done) {
+            L->nlev = k + 1;
+            off += (m + 15) / 16 * 16;
+            if (m <= 1024)
+                done = true;
+            else
+                m = (m + 15) / 16;
+        }
     }
     L->total = off;
 }
@@ -303,11 +313,19 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup_index(kl_lookup_args a, kl_sl
     lk_levels(a.nkeys, &L);
     const uint64_t e = (uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x;
     if (e >= L.total) return;
+    // the level holding entry e, by constant-index selects
     uint32_t k = 0;
-    while (k + 1 < L.nlev && e >= L.off[k + 1]) ++k;
-    const uint64_t i = e - L.off[k];
+    uint64_t base = L.off[0], mk = L.m[0];
+#pragma unroll
+    for (int j = 1; j < 8; ++j)
+        if (j < (int)L.nlev && e >= L.off[j]) {
+            k = j;
+            base = L.off[j];
+            mk = L.m[j];
+        }
+    const uint64_t i = e - base;
     uint32_t v = 0xffffffffu;
-    if (i < L.m[k]) {
+    if (i < mk) {
         // entry i of level k + 1 covers keys [16^(k+1) i, 16^(k+1) (i + 1))
         const uint64_t span = 1ull << (4 * (k + 1));
         uint64_t last = (i + 1) * span;
@@ -333,8 +351,15 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
     LkLevels L;
     lk_levels(a.nkeys, &L);
     const uint32_t T = L.nlev - 1;
-    const uint32_t mt = (uint32_t)L.m[T];
-    for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[L.off[T] + i];
+    uint32_t mt = 0;
+    uint64_t top_off = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        if (j == (int)T) {
+            mt = (uint32_t)L.m[j];
+            top_off = L.off[j];
+        }
+    for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[top_off + i];
     __syncthreads();
     const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
     if (t0 >= a.nq) return;
@@ -349,7 +374,9 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
 #pragma unroll
     for (int i = 0; i < 4; ++i) past[i] = c[i] >= mt;  // above every key
     const uint32_t* __restrict__ idx = a.index;
-    for (int k = (int)T - 1; k >= 0; --k) {
+#pragma unroll
+    for (int k = 6; k >= 0; --k) {
+        if (k >= (int)T) continue;   // uniform: levels below the top only
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (!past[i]) c[i] = 16 * c[i] + lk_count16(idx + L.off[k] + 16 * (uint64_t)c[i], q[i]);
@@ -375,6 +402,73 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
     }
     *(int4*)(a.out + t0) = o;
 }
+
+
+// ------------------------------------------------------ synthetic kernels
+// One load and a chain of dependent fmas per iteration; NACC values made
+// opaque to the compiler stay live across the loop (register pressure
+// class) and LDSB bytes of static LDS are touched (LDS class).
+template <int NACC, int LDSB>
+__device__ __forceinline__ void synthk_body(const kl_synthk_args& a, const kl_slice& s) {
+    constexpr int NL = LDSB > 0 ? LDSB / 4 : 1;
+    __shared__ float lds[NL];
+    const uint32_t t = kl_wg_linear(s) * KL_WG + threadIdx.x;
+    const bool active = t < a.n_threads;
+    float keep[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        keep[k] = (float)(t ^ (uint32_t)(k * 2654435761u)) * 1e-9f;
+        asm volatile("" : "+v"(keep[k]));
+    }
+    float x = (float)(t & 1023u) * 1e-3f;
+    uint32_t h = t * 2654435761u + 12345u;
+    if (active) {
+        for (uint32_t it = 0; it < a.iters; ++it) {
+            uint32_t addr;
+            if (a.pattern == 0) {
+                addr = (t + it * a.n_threads) & a.mask;
+            } else if (a.pattern == 1) {
+                addr = (32u * t + 7919u * it) & a.mask;
+            } else {
+                h = h * 1664525u + 1013904223u;
+                addr = (h ^ (h >> 13)) & a.mask;
+            }
+            const float v = a.src[addr];
+            for (uint32_t j = 0; j < a.alu; ++j) x = __builtin_fmaf(x, v, 0.5f);
+        }
+    }
+    if (LDSB > 0) {
+        lds[threadIdx.x % NL] = x;
+        __syncthreads();
+        x += lds[(threadIdx.x + 1) % NL];
+    }
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) {
+        asm volatile("" : "+v"(keep[k]));
+        x += keep[k];
+    }
+    if (active) a.dst[t] = x;
+}
+
+#define KL_SYNTHK_CLASSES(X) \
+    X(32, 0) X(32, 16) X(32, 32) X(32, 64) \
+    X(64, 0) X(64, 16) X(64, 32) X(64, 64) \
+    X(128, 0) X(128, 16) X(128, 32) X(128, 64) \
+    X(256, 0) X(256, 16) X(256, 32) X(256, 64)
+
+// live values per VGPR class: the class less what the loop itself needs
+template <int V>
+constexpr int synthk_nacc() { return V == 32 ? 16 : V == 64 ? 48 : V == 128 ? 112 : 236; }
+
+// one kernel per class (where LDS already limits occupancy the compiler
+// may reserve more VGPRs than the loop keeps live)
+#define KL_SYNTHK_DEF(V, L)                                                              \
+    __global__ __launch_bounds__(KL_WG) void kl_synthk_v##V##_l##L(kl_synthk_args a,     \
+                                                                   kl_slice s) {         \
+        synthk_body<synthk_nacc<V>(), (L) * 1024>(a, s);                                 \
+    }
+KL_SYNTHK_CLASSES(KL_SYNTHK_DEF)
+#undef KL_SYNTHK_DEF
 
 // ----------------------------------------------------------------- probe
 // Records where and when each workgroup ran and counts its visits; used to
@@ -464,6 +558,13 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         uint64_t wg = (a.n + 65535) / 65536;
         if (wg > 0xffffffffull) return "input too large";
         g->x = (uint32_t)wg;
+    } else if (n.rfind("synthk_", 0) == 0) {
+        KL_ARGS(kl_synthk_args);
+        if (!a.src || !a.dst || a.n_threads == 0) return "null pointer or n_threads == 0";
+        if ((a.mask & (a.mask + 1)) != 0) return "mask + 1 must be a power of two";
+        if (a.pattern > 2 || a.alu > 4096 || a.iters > (1u << 20))
+            return "pattern > 2, alu > 4096 or iters > 2^20";
+        g->x = cdiv(a.n_threads, KL_WG);
     } else if (n == "probe") {
         KL_ARGS(kl_probe_args);
         if (!a.visits || !a.info || a.n_wg == 0) return "null pointer or n_wg == 0";
@@ -509,6 +610,11 @@ const BuiltinEntry kBuiltins[] = {
     {"lookup", (const void*)kl_lookup, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
     {"lookup_index", (const void*)kl_lookup_index, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
     {"probe", (const void*)kl_probe, sizeof(kl_probe_args), 0u},
+#define KL_SYNTHK_ENTRY(V, L)                                                 \
+    {"synthk_v" #V "_l" #L, (const void*)kl_synthk_v##V##_l##L, sizeof(kl_synthk_args), \
+     KL_KF_IDEMPOTENT},
+    KL_SYNTHK_CLASSES(KL_SYNTHK_ENTRY)
+#undef KL_SYNTHK_ENTRY
 };
 
 }  // namespace

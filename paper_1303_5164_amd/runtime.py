@@ -144,6 +144,13 @@ class Runtime:
         self._c("kernelet_get_profile", self.h, k, C.byref(p))
         return profile_dict(p)
 
+    def set_surrogate(self, params) -> None:
+        """Load surrogate network parameters (5313 floats) for the SURROGATE
+        policy."""
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._c("kernelet_set_surrogate", self.h, p.ctypes.data, p.size)
+
     # ----------------------------------------------------------------- jobs
     def submit(self, k: int, grid, args, after: int = -1, client: int = 0,
                footprint: int = 0) -> int:

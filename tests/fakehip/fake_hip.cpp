@@ -3,6 +3,7 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -189,6 +190,20 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void*, int
     *n = 8;
     return hipSuccess;
 }
+hipError_t hipMalloc(void** p, size_t n) {
+    *p = std::malloc(n ? n : 1);
+    return *p ? hipSuccess : hipErrorInvalidValue;
+}
+hipError_t hipFree(void* p) {
+    std::free(p);
+    return hipSuccess;
+}
+hipError_t hipHostMalloc(void** p, size_t n, unsigned) { return hipMalloc(p, n); }
+hipError_t hipHostFree(void* p) { return hipFree(p); }
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind, hipStream_t) {
+    std::memcpy(dst, src, n);
+    return hipSuccess;
+}
 const char* hipGetErrorString(hipError_t e) {
     switch (e) {
         case hipSuccess: return "hipSuccess";
@@ -207,6 +222,30 @@ bool builtin_check(const char*, const void*, uint32_t, kl_dim3*, std::string* er
 }
 bool is_builtin_fn(const void*, const char**) { return false; }
 }  // namespace kl
+
+// The surrogate network's forward pass on the host (the double's "device"
+// memory is host memory): same parameter layout as the library's kernel.
+extern "C" kl_status kernelet_mlp_forward(const float* p, const float* x, uint32_t n, float* y,
+                                          void*) {
+    const int I = 16, H = 64;
+    const float *W1 = p, *b1 = W1 + I * H, *W2 = b1 + H, *b2 = W2 + H * H, *W3 = b2 + H,
+                *b3 = W3 + H;
+    for (uint32_t s = 0; s < n; ++s) {
+        float h1[64], out = b3[0];
+        for (int j = 0; j < H; ++j) {
+            float a = b1[j];
+            for (int i = 0; i < I; ++i) a += x[s * I + i] * W1[i * H + j];
+            h1[j] = a > 0 ? a : 0;
+        }
+        for (int j = 0; j < H; ++j) {
+            float a = b2[j];
+            for (int i = 0; i < H; ++i) a += h1[i] * W2[i * H + j];
+            out += (a > 0 ? a : 0) * W3[j];
+        }
+        y[s] = out;
+    }
+    return KL_OK;
+}
 
 extern "C" kl_status kernelet_builtin(const char*, kl_kernel_desc*) { return KL_ENOTFOUND; }
 extern "C" kl_status kernelet_builtin_grid(const char*, const void*, uint32_t, kl_dim3*) {

@@ -57,3 +57,12 @@ hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void* fn);
 hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void* fn, int block,
                                                         size_t dyn);
 const char* hipGetErrorString(hipError_t e);
+
+// memory: plain host memory; copies are synchronous
+typedef enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 } hipMemcpyKind;
+hipError_t hipMalloc(void** p, size_t n);
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t n, unsigned flags = 0);
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t n, hipMemcpyKind k,
+                          hipStream_t s);

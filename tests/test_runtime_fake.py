@@ -298,3 +298,26 @@ def test_submit_chain_is_atomic_and_holds_the_footprint(L):
     assert e.value.code == -2
     assert h.rt.stats()["jobs_submitted"] == before
     h.close()
+
+
+def test_surrogate_policy_ranks_pairs_and_runs_everything(L):
+    """SURROGATE: refused without weights; with weights, candidates of the
+    surviving pairs are scored in one batch and only the top pair goes to
+    the Markov model; every workgroup still runs once."""
+    h = Harness(L, surrogate_topk=1, use_prune=0)
+    d = _lib.KernelDesc(b"fake2", C.addressof(L._keys[0]), 256, C.sizeof(VisitArgs), 0, None)
+    h.kids.append(h.rt.register(d, dict(PROF[0], r_mem=0.05, pur=0.5, mur=0.3)))
+    jobs = [h.job(32, i, kind=i % 3, us=20) for i in range(9)]
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.schedule("surrogate")
+    assert e.value.code == -5
+    from paper_1303_5164_amd import surrogate as S
+    h.rt.set_surrogate(S.init_params(0))
+    _run_with_deadline(lambda: h.rt.schedule("surrogate", blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    st = h.rt.stats()
+    assert st["surrogate_pairs"] >= 3 and st["surrogate_candidates"] > 0
+    assert any(dd["j2"] >= 0 for dd in h.rt.decisions())
+    h.close()

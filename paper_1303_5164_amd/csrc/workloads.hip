@@ -411,6 +411,7 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
 template <int NACC, int LDSB>
 __device__ __forceinline__ void synthk_body(const kl_synthk_args& a, const kl_slice& s) {
     constexpr int NL = LDSB > 0 ? LDSB / 4 : 1;
+    static_assert(LDSB == 0 || NL >= KL_WG, "an LDS class holds a value per thread");
     __shared__ float lds[NL];
     const uint32_t t = kl_wg_linear(s) * KL_WG + threadIdx.x;
     const bool active = t < a.n_threads;
@@ -437,10 +438,10 @@ __device__ __forceinline__ void synthk_body(const kl_synthk_args& a, const kl_sl
             for (uint32_t j = 0; j < a.alu; ++j) x = __builtin_fmaf(x, v, 0.5f);
         }
     }
-    if (LDSB > 0) {
-        lds[threadIdx.x % NL] = x;
+    if (LDSB > 0) {   // every value read here was written by this workgroup
+        lds[threadIdx.x] = x;
         __syncthreads();
-        x += lds[(threadIdx.x + 1) % NL];
+        x += lds[(threadIdx.x + 1) % KL_WG];
     }
 #pragma unroll
     for (int k = 0; k < NACC; ++k) {

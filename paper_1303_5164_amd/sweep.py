@@ -45,6 +45,12 @@ def main():
                     help="exact: slices of b*n_cu WGs; min: max(b*n_cu, calibrated minimum "
                          "slice); none: whole launches")
     ap.add_argument("--lds-reserve", type=int, default=0)
+    ap.add_argument("--solo-occupancy", action="store_true",
+                    help="also time every kernel alone at each occupancy b (held by LDS "
+                         "reservation; needs --lds-reserve 2)")
+    ap.add_argument("--balance", action="store_true",
+                    help="re-run each co-run with work amounts set from the first run's "
+                         "rates so that both kernels finish together")
     a = ap.parse_args()
 
     import numpy as np
@@ -131,6 +137,21 @@ def main():
         solo[kind] = float(np.median(ts[1:]))
         print(f"# solo {kind}: {solo[kind]:.4f} ms", file=sys.stderr, flush=True)
 
+    solo_occ = {}
+    if a.solo_occupancy:
+        for kind in kinds:
+            p = prof[launch[kind][0]]
+            n = max(1, round(a.window_ms / solo[kind]))
+            solo_occ[kind] = {}
+            for b in range(1, p["max_wg_per_cu"] + 1):
+                ts = []
+                for _ in range(3):
+                    _, busy = run([(kind, n, 0, b)])
+                    ts.append(busy[kind][0] / n)
+                solo_occ[kind][b] = float(np.median(ts))
+            print(f"# occupancy {kind}: " + ", ".join(
+                f"{b}:{v:.4f}" for b, v in solo_occ[kind].items()), file=sys.stderr, flush=True)
+
     rows = []
     for ka, kb in itertools.combinations(kinds, 2):
         pa, pb = prof[launch[ka][0]], prof[launch[kb][0]]
@@ -154,10 +175,20 @@ def main():
                 return min(s, wg)
 
             wall, busy = run([(ka, na, sl(b1, wga, pa), b1), (kb, nb, sl(b2, wgb, pb), b2)])
+            na_r, nb_r = na, nb
+            if a.balance:
+                # kernel b's count scaled so that both take the same time at
+                # the rates just measured
+                ra = na / max(busy[ka][0], 1e-9)
+                rb = nb / max(busy[kb][0], 1e-9)
+                nb_r = max(1, round(rb * na / ra))
+                wall, busy = run([(ka, na, sl(b1, wga, pa), b1),
+                                  (kb, nb_r, sl(b2, wgb, pb), b2)])
             co_ms = wall * 1e3
-            S = seq_ms / co_ms
-            sa = (na * solo[ka]) / max(busy[ka][0], 1e-9)
-            sb = (nb * solo[kb]) / max(busy[kb][0], 1e-9)
+            seq = na_r * solo[ka] + nb_r * solo[kb]
+            S = seq / co_ms
+            sa = (na_r * solo[ka]) / max(busy[ka][0], 1e-9)
+            sb = (nb_r * solo[kb]) / max(busy[kb][0], 1e-9)
             try:
                 i1, i2, _ = K.predict(pa, pb, b1, b2)
                 s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0)[0]
@@ -166,7 +197,7 @@ def main():
                 pcp = 1.0 - 1.0 / (pr1 + pr2)
             except K.KerneletError:
                 pr1 = pr2 = pcp = float("nan")
-            row = dict(a=ka, b=kb, b1=b1, b2=b2, na=na, nb=nb, seq_ms=seq_ms, co_ms=co_ms,
+            row = dict(a=ka, b=kb, b1=b1, b2=b2, na=na_r, nb=nb_r, seq_ms=seq, co_ms=co_ms,
                        speedup=S, cp=1.0 - 1.0 / S, rel_a=sa, rel_b=sb,
                        pred_rel_a=pr1, pred_rel_b=pr2, pred_cp=pcp,
                        busy_a_ms=busy[ka][0], busy_b_ms=busy[kb][0])
@@ -176,8 +207,9 @@ def main():
                   file=sys.stderr, flush=True)
     rt.close()
     with open(a.out, "w") as f:
-        json.dump({"n_cu": n_cu, "solo_ms": solo, "window_ms": a.window_ms, "rows": rows},
-                  f, indent=1)
+        json.dump({"n_cu": n_cu, "solo_ms": solo, "window_ms": a.window_ms,
+                   "slicing": a.slicing, "lds_reserve": a.lds_reserve, "balance": a.balance,
+                   "solo_occupancy_ms": solo_occ, "rows": rows}, f, indent=1)
 
 
 if __name__ == "__main__":

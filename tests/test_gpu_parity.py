@@ -117,3 +117,31 @@ def test_lookup_single_key(rtk):
     h = dict(keys=np.array([7], np.uint32), q=np.array([0, 7, 8, 6], np.uint32))
     out = _both(rtk, _case("lookup", h), 1)
     assert list(out) == [0, 0, 1, 0]
+
+
+def test_polynomial_and_gather_four_slices_each_markov(rtk):
+    """The two-kernel case at full size: polynomial over 2^20 values (4096
+    workgroups) and gather of 2^22 from 2^24 (16384 workgroups), each cut
+    into 4 slices, co-scheduled by the Markov model: every output equals the
+    oracle's (same-order fp32 Horner for the polynomial; exact gather)."""
+    from paper_1303_5164_amd import profiles
+    rt, kids = rtk
+    prof = profiles.load()
+    for k in ("poly", "gather"):
+        rt.set_profile(kids[k], prof[k])
+    hp = synth.poly(0, n=1 << 20)
+    hg = synth.gather(0, n=1 << 22, table=1 << 24)
+    pa, ga = _case("poly", hp), _case("gather", hg)
+    insts = [pa, ga]
+    torch.cuda.synchronize()
+    jobs = [W.submit(rt, kids, i)[0] for i in insts]
+    assert rt.slice(jobs[0], 1024) == 4 and rt.slice(jobs[1], 4096) == 4
+    rt.schedule("markov", blocking=True, wait_done=True)
+    for j in jobs:
+        rt.wait(j, 60_000_000_000)
+    dec = rt.decisions()
+    rt.reap()
+    assert any(d["j2"] >= 0 for d in dec), "the two kernels were not co-scheduled"
+    assert all(d["slice1"] in (1024, 4096) for d in dec if d["j2"] >= 0)
+    assert np.array_equal(result(pa), oracle.poly_f32_horner(hp["x"], hp["coef"]))
+    assert np.array_equal(result(ga), oracle.gather(hg["idx"], hg["table"]))

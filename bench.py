@@ -36,7 +36,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--instances", type=int, default=8, help="instances per kernel type")
-    ap.add_argument("--policy", default="markov", choices=["markov", "fixed"])
+    ap.add_argument("--policy", default="markov", choices=["markov", "fixed", "surrogate"])
+    ap.add_argument("--topk", type=int, default=None,
+                    help="pairs the Markov model re-ranks under the surrogate policy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="fifo,kernelet")
     ap.add_argument("--seed", type=int, default=0)
@@ -140,6 +142,22 @@ def cpu_baseline(hosts):
             "seconds_per_instance": {k: round(v, 4) for k, v in t_inst.items()}}
 
 
+def _traffic(kernel):
+    """HBM bytes per full launch of `kernel` from the counter summary under
+    profiles/ (two rocprofv3 --pmc runs, see paper_1303_5164_amd/traffic.py),
+    or None when absent or taken from a different kernel source."""
+    from paper_1303_5164_amd import traffic
+    path = os.path.join(ROOT, "profiles", "traffic_mi355x.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha256") != traffic.source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return float(k["bytes"]) if k else None
+
+
 def nearest_rank(v, q):
     v = sorted(v)
     return v[max(1, math.ceil(q * len(v))) - 1]
@@ -194,7 +212,12 @@ def main():
         over["lds_reserve"] = args.lds_reserve
     if args.cp_min is not None:
         over["cp_min"] = args.cp_min
+    if args.topk is not None:
+        over["surrogate_topk"] = args.topk
     rt = K.Runtime(0, **over)
+    if args.policy == "surrogate":
+        from paper_1303_5164_amd import surrogate
+        rt.set_surrogate(np.load(surrogate.WEIGHTS))
     prof = profiles.load(prefer_measured=not args.estimates)
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     setup_s = time.perf_counter() - t_setup
@@ -326,6 +349,13 @@ def main():
     roof["achieved"] = round(roof["achieved"], 3)
     roof["frac"] = round(roof["frac"], 4)
     roof["traffic"] = None
+    tr = _traffic(dom)
+    if tr is not None:
+        # HBM bytes of one full launch, per workgroup, times the timed
+        # launches' average workgroups (slices move proportionally less)
+        roof["traffic"] = round(tr / wk["wgs"] * wg / max(n, 1), 1)
+        roof["traffic_unit"] = "bytes/launch"
+        roof["traffic_over_algorithmic"] = round(tr / wk["bytes"], 3) if wk["bytes"] else None
     roof["kernel"] = dom
     roof["launches"] = n
     roof["avg_launch_ms"] = round(ms / max(n, 1), 5)

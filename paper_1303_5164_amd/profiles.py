@@ -42,8 +42,13 @@ ESTIMATES = {
 }
 
 
+# dominant access pattern of each kernel (0 coalesced, 1 strided, 2 random),
+# read off the code: the gather, lookup and SpMV's x reads are random
+ACCESS = {"gather": 2, "lookup": 2, "spmv": 2}
+
+
 def load(prefer_measured: bool = True) -> dict:
-    table = {k: dict(v) for k, v in ESTIMATES.items()}
+    table = {k: dict(v, access=ACCESS.get(k, 0)) for k, v in ESTIMATES.items()}
     if prefer_measured and os.path.exists(MEASURED):
         with open(MEASURED) as f:
             meas = json.load(f).get("profiles", {})

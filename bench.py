@@ -53,9 +53,8 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic(kind, inst_args, n_below=None):
-    """(flops, bytes, compute peak) of one launch, from its argument block;
-    n_below: the lookup's queries at or below its largest key."""
+def algorithmic(kind, inst_args):
+    """(flops, bytes, compute peak) of one instance, from its argument block."""
     a = inst_args
     if kind == "poly":
         return 2.0 * a.n * (a.ncoef - 1), 8.0 * a.n + 4.0 * a.ncoef, PEAK_VALU_F32
@@ -72,17 +71,11 @@ def algorithmic(kind, inst_args, n_below=None):
         return 0.0, 20.0 * a.n, PEAK_VALU_F32
     if kind == "hist":
         return 0.0, 1.0 * a.n + 1024, PEAK_VALU_F32
-    if kind.startswith("lookup"):
-        nb = float(a.nq if n_below is None else n_below)
-        tiles = float(-(-a.nq // 4096)) * 256
-        by = {"lookup_index": 8.0 * float(_index_entries(a.nkeys)),
-              "lookup_count": 4.0 * a.nq + 4.0 * tiles,          # queries; tile counts
-              "lookup_total": 4.0 * tiles,
-              "lookup_offset": 8.0 * tiles,
-              "lookup_scatter": 8.0 * a.nq + 4.0 * nb,          # queries, positions, moved
-              "lookup": 8.0 * nb + 4.0 * a.nkeys,                # moved queries, results, keys
-              "lookup_gather": 8.0 * a.nq + 4.0 * nb}           # positions, out; results
-        return 0.0, by[kind], PEAK_VALU_F32
+    if kind == "lookup":
+        return 0.0, 8.0 * a.nq + 4.0 * a.nkeys, PEAK_VALU_F32
+    if kind == "lookup_index":
+        ent = float(_index_entries(a.nkeys))
+        return 0.0, 8.0 * ent, PEAK_VALU_F32
     raise KeyError(kind)
 
 
@@ -229,8 +222,6 @@ def main():
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     setup_s = time.perf_counter() - t_setup
 
-    # queries the lookup partitions (at or below its largest key)
-    n_below = int(np.count_nonzero(hosts["lookup"]["q"] <= hosts["lookup"]["keys"][-1]))
     # algorithmic work of each kernel per instance (all its launches) and its
     # workgroups
     work = {}
@@ -241,7 +232,7 @@ def main():
         seen.add(inst.kind)
         for ln in inst.launches:
             kname = ln.kernel or inst.kind
-            ff, bb, peak = algorithmic(kname, ln.args, n_below)
+            ff, bb, peak = algorithmic(kname, ln.args)
             w = work.setdefault(kname, dict(flops=0.0, bytes=0.0, peak=peak, wgs=0))
             w["flops"] += ff
             w["bytes"] += bb

@@ -104,44 +104,22 @@ typedef struct {
  * entry i is keys[min(16 i + 15, n - 1)] (the largest key of leaf line i),
  * level k + 1 entry i is level k entry min(16 i + 15, m_k - 1); level sizes
  * m_1 = ceil(n / 16), m_{k+1} = ceil(m_k / 16), stopping at the first level
- * with at most 1024 entries (the top, searched in LDS).  `index` holds the
- * levels back to back (level 1 first), kernelet_lookup_index_entries(n)
- * entries.
- *
- * The queries are first partitioned by key range so that the search reads
- * each region of keys while it is cache-resident, then the results are put
- * back in query order.  One instance is a chain of seven launches over the
- * same argument block (grids from kernelet_builtin_grid):
- *   lookup_index    writes the tree                    ceil(entries / 256)
- *   lookup_count    key-range bucket histogram of each  ceil(nq / 4096)
- *                   4096-query tile (256 buckets of top-level entries)
- *   lookup_total    bucket sums over slabs of tiles     64
- *   lookup_offset   start of every (tile, bucket) run   64
- *   lookup_scatter  queries below the largest key to    ceil(nq / 4096)
- *                   their bucket's run; position of each
- *   lookup          the search, over partitioned        ceil(nq / 1024)
- *                   queries, results in that order
- *   lookup_gather   out[t] from the partitioned results ceil(nq / 1024)
- * `work` holds kernelet_lookup_work_entries(nq) uint32 entries of
- * intermediate state owned by the instance.  nq a multiple of 4, nkeys >= 1;
- * keys, q, out, index, work 16-byte aligned. */
+ * with at most 1024 entries (searched in LDS).  `index` holds the levels
+ * back to back (level 1 first), kernelet_lookup_index_entries(n) entries;
+ * the "lookup_index" kernel writes it (grid = ceil(entries / 256)) and the
+ * "lookup" kernel reads it (four queries per thread, grid = ceil(nq / 1024)).
+ * nq a multiple of 4, nkeys >= 1; keys, q, out, index 16-byte aligned. */
 typedef struct {
     const uint32_t* keys;
     const uint32_t* q;
     int32_t* out;
     uint32_t* index;
-    uint32_t* work;
     uint32_t nkeys;
     uint32_t nq;
 } kl_lookup_args;
 
 /* Number of uint32 entries of the lookup tree index for n keys. */
 uint64_t kernelet_lookup_index_entries(uint32_t nkeys);
-
-/* Number of uint32 entries of the lookup's intermediate state for nq
- * queries: per-tile bucket counts and run offsets, slab sums, the
- * partitioned queries, each query's position and the partitioned results. */
-uint64_t kernelet_lookup_work_entries(uint32_t nq);
 
 /* probe (not a workload): workgroup w adds 1 to visits[w] and writes
  * info[3w] = (XCC_ID << 32) | HW_ID, info[3w+1] = start, info[3w+2] = end

@@ -108,13 +108,8 @@ class HistArgs(C.Structure):
 
 
 class LookupArgs(C.Structure):
-    _fields_ = [("keys", P), ("q", P), ("out", P), ("index", P), ("work", P),
-                ("nkeys", C.c_uint32), ("nq", C.c_uint32)]
-
-
-# the launches of one lookup instance, in order
-LOOKUP_CHAIN = ["lookup_index", "lookup_count", "lookup_total", "lookup_offset",
-                "lookup_scatter", "lookup", "lookup_gather"]
+    _fields_ = [("keys", P), ("q", P), ("out", P), ("index", P), ("nkeys", C.c_uint32),
+                ("nq", C.c_uint32)]
 
 
 class SynthkArgs(C.Structure):
@@ -134,7 +129,7 @@ class ProbeArgs(C.Structure):
 
 ARGS = {"probe": ProbeArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
         "stencil": StencilArgs, "bs": BsArgs, "hist": HistArgs, "lookup": LookupArgs,
-        **{k: LookupArgs for k in LOOKUP_CHAIN}, **{k: SynthkArgs for k in SYNTHK}}
+        "lookup_index": LookupArgs, **{k: SynthkArgs for k in SYNTHK}}
 
 # every symbol include/kernelet.h declares
 SYMBOLS = [
@@ -230,10 +225,9 @@ def configure(L):
         if hasattr(L, name):
             getattr(L, name).argtypes = args
             getattr(L, name).restype = res
-    for name in ("kernelet_lookup_index_entries", "kernelet_lookup_work_entries"):
-        if hasattr(L, name):
-            getattr(L, name).argtypes = [C.c_uint32]
-            getattr(L, name).restype = C.c_uint64
+    if hasattr(L, "kernelet_lookup_index_entries"):
+        L.kernelet_lookup_index_entries.argtypes = [C.c_uint32]
+        L.kernelet_lookup_index_entries.restype = C.c_uint64
     L.kernelet_last_error.argtypes = []
     L.kernelet_last_error.restype = C.c_char_p
     return L

@@ -291,7 +291,7 @@ def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict
         p["fetch_bytes_per_launch"] = fetch_b
         p["write_bytes_per_launch"] = write_b
         p["wgs_per_launch"] = t["wgs_per_launch"]
-        kind = "lookup" if name.startswith("lookup") else name
+        kind = "lookup" if name == "lookup_index" else name
         if kind in slices:
             # 0 = no slice size met the overhead bound: never slice
             p["min_slice_wgs"] = int(slices[kind]["min_slice_wgs"]) or 2147483647

@@ -346,40 +346,10 @@ __device__ __forceinline__ uint32_t lk_count16(const uint32_t* p, uint32_t q) {
     return c;
 }
 
-// Partitioned search.  Queries are bucketed by key range (LK_NB buckets of
-// top-level entries) in tiles of LK_TILE; work holds, in uint32 entries:
-//   counts  [ntile][LK_NB]  queries of each tile in each bucket
-//   offsets [ntile][LK_NB]  first position of each (tile, bucket) run
-//   slabs   [LK_SLABS][LK_NB] bucket sums over slabs of tiles
-//   meta    [4]             meta[0] = queries below the largest key
-//   qpart   [nq]            those queries, bucket-major
-//   pos     [nq]            each query's position in qpart (~0u: above all keys)
-//   res     [nq]            lower_bound of qpart[p]
-constexpr uint32_t LK_TILE = 4096;
-constexpr uint32_t LK_NB = 256;
-constexpr uint32_t LK_SLABS = 64;
-static_assert(LK_NB == KL_WG, "one thread per bucket");
-
-struct LkWork {
-    uint64_t counts, offsets, slabs, meta, qpart, pos, res, total;
-    uint32_t ntile;
-};
-
-__host__ __device__ inline void lk_work(uint32_t nq, LkWork* W) {
-    W->ntile = (uint32_t)(((uint64_t)nq + LK_TILE - 1) / LK_TILE);
-    W->counts = 0;
-    W->offsets = (uint64_t)W->ntile * LK_NB;
-    W->slabs = 2 * (uint64_t)W->ntile * LK_NB;
-    W->meta = W->slabs + (uint64_t)LK_SLABS * LK_NB;
-    W->qpart = W->meta + 4;
-    W->pos = W->qpart + nq;
-    W->res = W->pos + nq;
-    W->total = W->res + nq;
-}
-
-// The top level of the tree in LDS; returns its entry count.
-__device__ __forceinline__ uint32_t lk_load_top(const kl_lookup_args& a, const LkLevels& L,
-                                                uint32_t* top) {
+__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
+    __shared__ uint32_t top[1024];
+    LkLevels L;
+    lk_levels(a.nkeys, &L);
     const uint32_t T = L.nlev - 1;
     uint32_t mt = 0;
     uint64_t top_off = 0;
@@ -390,34 +360,19 @@ __device__ __forceinline__ uint32_t lk_load_top(const kl_lookup_args& a, const L
             top_off = L.off[j];
         }
     for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[top_off + i];
-    return mt;
-}
-
-// Number of top-level entries below q (mt: q above every key).
-__device__ __forceinline__ uint32_t lk_top_count(const uint32_t* top, uint32_t mt, uint32_t q) {
-    uint32_t c = 0;
+    __syncthreads();
+    const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
+    if (t0 >= a.nq) return;
+    const uint4 qv = *(const uint4*)(a.q + t0);
+    const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
+    uint32_t c[4] = {0, 0, 0, 0};
     for (uint32_t st = kl_highbit(mt); st; st >>= 1)
-        if (c + st <= mt && top[c + st - 1] < q) c += st;
-    return c;
-}
-
-__device__ __forceinline__ uint32_t lk_bucket(uint32_t c, uint32_t mt) {
-    return (uint32_t)(((uint64_t)c * LK_NB) / mt);
-}
-
-// lower_bound of four queries: LDS top level, then one 64-byte node per
-// level, then the leaf line of keys.
-__device__ __forceinline__ void lk_search4(const kl_lookup_args& a, const LkLevels& L,
-                                           const uint32_t* top, uint32_t mt, const uint32_t* q,
-                                           uint32_t* r) {
-    const uint32_t T = L.nlev - 1;
-    uint32_t c[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (c[i] + st <= mt && top[c[i] + st - 1] < q[i]) c[i] += st;
     bool past[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        c[i] = lk_top_count(top, mt, q[i]);
-        past[i] = c[i] >= mt;  // above every key
-    }
+    for (int i = 0; i < 4; ++i) past[i] = c[i] >= mt;  // above every key
     const uint32_t* __restrict__ idx = a.index;
 #pragma unroll
     for (int k = 6; k >= 0; --k) {
@@ -428,169 +383,26 @@ __device__ __forceinline__ void lk_search4(const kl_lookup_args& a, const LkLeve
     }
     const uint32_t n = a.nkeys;
     const uint32_t* __restrict__ keys = a.keys;
+    int4 o;
+    int* op = &o.x;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        r[i] = n;
+        uint32_t r = n;
         if (!past[i]) {
             const uint64_t base = 16 * (uint64_t)c[i];
             if (base + 16 <= n) {
-                r[i] = (uint32_t)base + lk_count16(keys + base, q[i]);
+                r = (uint32_t)base + lk_count16(keys + base, q[i]);
             } else {
                 uint32_t cnt = 0;
                 for (uint64_t j = base; j < n; ++j) cnt += keys[j] < q[i];
-                r[i] = (uint32_t)base + cnt;
+                r = (uint32_t)base + cnt;
             }
         }
+        op[i] = (int)r;
     }
-}
-
-__global__ __launch_bounds__(KL_WG) void kl_lookup_count(kl_lookup_args a, kl_slice s) {
-    __shared__ uint32_t top[1024];
-    __shared__ uint32_t hist[LK_NB];
-    LkLevels L;
-    lk_levels(a.nkeys, &L);
-    LkWork W;
-    lk_work(a.nq, &W);
-    const uint32_t mt = lk_load_top(a, L, top);
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t tile = kl_wg_linear(s);
-    const uint64_t base = (uint64_t)tile * LK_TILE;
-    for (uint32_t i = threadIdx.x * 4; i < LK_TILE; i += KL_WG * 4) {
-        const uint64_t t0 = base + i;
-        if (t0 >= a.nq) break;
-        const uint4 qv = *(const uint4*)(a.q + t0);
-        const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t c = lk_top_count(top, mt, q[j]);
-            if (c < mt) atomicAdd(&hist[lk_bucket(c, mt)], 1u);
-        }
-    }
-    __syncthreads();
-    a.work[W.counts + (uint64_t)tile * LK_NB + threadIdx.x] = hist[threadIdx.x];
-}
-
-// Slab s of the tiles: bucket sums over its tiles (thread = bucket).
-__global__ __launch_bounds__(KL_WG) void kl_lookup_total(kl_lookup_args a, kl_slice s) {
-    LkWork W;
-    lk_work(a.nq, &W);
-    const uint32_t slab = kl_wg_linear(s);
-    const uint32_t per = (W.ntile + LK_SLABS - 1) / LK_SLABS;
-    const uint32_t t0 = slab * per, t1 = min(W.ntile, t0 + per);
-    uint32_t sum = 0;
-    for (uint32_t t = t0; t < t1; ++t) sum += a.work[W.counts + (uint64_t)t * LK_NB + threadIdx.x];
-    a.work[W.slabs + (uint64_t)slab * LK_NB + threadIdx.x] = sum;
-}
-
-// Run offsets: bucket b starts after every query of buckets < b; within b,
-// tiles in order.  Slab 0 also stores the number of partitioned queries.
-__global__ __launch_bounds__(KL_WG) void kl_lookup_offset(kl_lookup_args a, kl_slice s) {
-    __shared__ uint32_t scan[LK_NB];
-    LkWork W;
-    lk_work(a.nq, &W);
-    const uint32_t slab = kl_wg_linear(s);
-    const uint32_t b = threadIdx.x;
-    uint32_t total = 0, before = 0;
-    for (uint32_t k = 0; k < LK_SLABS; ++k) {
-        const uint32_t v = a.work[W.slabs + (uint64_t)k * LK_NB + b];
-        total += v;
-        if (k < slab) before += v;
-    }
-    // exclusive scan of the bucket totals over b (Hillis-Steele in LDS)
-    scan[b] = total;
-    __syncthreads();
-    for (uint32_t d = 1; d < LK_NB; d <<= 1) {
-        const uint32_t v = b >= d ? scan[b - d] : 0u;
-        __syncthreads();
-        scan[b] += v;
-        __syncthreads();
-    }
-    uint32_t run = scan[b] - total + before;
-    if (slab == 0 && b == LK_NB - 1) a.work[W.meta] = scan[b];
-    const uint32_t per = (W.ntile + LK_SLABS - 1) / LK_SLABS;
-    const uint32_t t0 = slab * per, t1 = min(W.ntile, t0 + per);
-    for (uint32_t t = t0; t < t1; ++t) {
-        const uint64_t e = (uint64_t)t * LK_NB + b;
-        a.work[W.offsets + e] = run;
-        run += a.work[W.counts + e];
-    }
-}
-
-__global__ __launch_bounds__(KL_WG) void kl_lookup_scatter(kl_lookup_args a, kl_slice s) {
-    __shared__ uint32_t top[1024];
-    __shared__ uint32_t cursor[LK_NB];
-    LkLevels L;
-    lk_levels(a.nkeys, &L);
-    LkWork W;
-    lk_work(a.nq, &W);
-    const uint32_t mt = lk_load_top(a, L, top);
-    const uint32_t tile = kl_wg_linear(s);
-    cursor[threadIdx.x] = a.work[W.offsets + (uint64_t)tile * LK_NB + threadIdx.x];
-    __syncthreads();
-    const uint64_t base = (uint64_t)tile * LK_TILE;
-    uint32_t* __restrict__ qpart = a.work + W.qpart;
-    for (uint32_t i = threadIdx.x * 4; i < LK_TILE; i += KL_WG * 4) {
-        const uint64_t t0 = base + i;
-        if (t0 >= a.nq) break;
-        const uint4 qv = *(const uint4*)(a.q + t0);
-        const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
-        uint32_t p[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t c = lk_top_count(top, mt, q[j]);
-            p[j] = 0xffffffffu;
-            if (c < mt) {
-                p[j] = atomicAdd(&cursor[lk_bucket(c, mt)], 1u);
-                qpart[p[j]] = q[j];
-            }
-        }
-        *(uint4*)(a.work + W.pos + t0) = make_uint4(p[0], p[1], p[2], p[3]);
-    }
-}
-
-// The search over the partitioned queries.  Workgroups take consecutive
-// chunks of 1024 within each XCD (the dispatcher deals workgroups to the
-// eight XCDs in turn), so each XCD's L2 holds one region of keys.
-__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
-    __shared__ uint32_t top[1024];
-    LkLevels L;
-    lk_levels(a.nkeys, &L);
-    LkWork W;
-    lk_work(a.nq, &W);
-    const uint32_t mt = lk_load_top(a, L, top);
-    __syncthreads();
-    const uint32_t lin = kl_wg_linear(s);
-    const uint32_t G = s.gx;
-    const uint32_t chunk = (G % 8 == 0) ? (lin % 8) * (G / 8) + lin / 8 : lin;
-    const uint32_t n = a.work[W.meta];
-    const uint64_t t0 = ((uint64_t)chunk * KL_WG + threadIdx.x) * 4;
-    if (t0 >= n) return;
-    const uint32_t* __restrict__ qpart = a.work + W.qpart;
-    uint32_t q[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) q[j] = t0 + j < n ? qpart[t0 + j] : 0u;
-    uint32_t r[4];
-    lk_search4(a, L, top, mt, q, r);
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        if (t0 + j < n) a.work[W.res + t0 + j] = r[j];
-}
-
-__global__ __launch_bounds__(KL_WG) void kl_lookup_gather(kl_lookup_args a, kl_slice s) {
-    LkWork W;
-    lk_work(a.nq, &W);
-    const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
-    if (t0 >= a.nq) return;
-    const uint4 p = *(const uint4*)(a.work + W.pos + t0);
-    const uint32_t* __restrict__ res = a.work + W.res;
-    const uint32_t n = a.nkeys;
-    const int4 o = make_int4((int)(p.x == 0xffffffffu ? n : res[p.x]),
-                             (int)(p.y == 0xffffffffu ? n : res[p.y]),
-                             (int)(p.z == 0xffffffffu ? n : res[p.z]),
-                             (int)(p.w == 0xffffffffu ? n : res[p.w]));
     *(int4*)(a.out + t0) = o;
 }
+
 
 // ------------------------------------------------------ synthetic kernels
 // One load and a chain of dependent fmas per iteration; NACC values made
@@ -759,7 +571,7 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         if (!a.visits || !a.info || a.n_wg == 0) return "null pointer or n_wg == 0";
         if (a.spin > (1u << 24)) return "spin above 2^24";
         g->x = a.n_wg;
-    } else if (n.rfind("lookup", 0) == 0) {
+    } else if (n == "lookup" || n == "lookup_index") {
         KL_ARGS(kl_lookup_args);
         if (!a.keys || !a.index || a.nkeys == 0 || a.nkeys > 0x7fffffffu)
             return "null keys or index, or nkeys outside [1, 2^31 - 1]";
@@ -769,18 +581,10 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
             lk_levels(a.nkeys, &L);
             g->x = cdiv(L.total, KL_WG);
         } else {
-            if (!a.q || !a.out || !a.work || a.nq == 0 || a.nq % 4)
-                return "null q, out or work, or nq not a positive multiple of 4";
-            if (!aligned16(a.q) || !aligned16(a.out) || !aligned16(a.work))
-                return "q, out, work must be 16-byte aligned";
-            if (n == "lookup_count" || n == "lookup_scatter")
-                g->x = cdiv(a.nq, LK_TILE);
-            else if (n == "lookup_total" || n == "lookup_offset")
-                g->x = LK_SLABS;
-            else if (n == "lookup" || n == "lookup_gather")
-                g->x = cdiv(a.nq, 4 * KL_WG);
-            else
-                return "unknown built-in kernel";
+            if (!a.q || !a.out || a.nq == 0 || a.nq % 4)
+                return "null q or out, or nq not a positive multiple of 4";
+            if (!aligned16(a.q) || !aligned16(a.out)) return "q, out must be 16-byte aligned";
+            g->x = cdiv(a.nq, 4 * KL_WG);
         }
     } else {
         return "unknown built-in kernel";
@@ -804,14 +608,8 @@ const BuiltinEntry kBuiltins[] = {
     {"stencil", (const void*)kl_stencil, sizeof(kl_stencil_args), KL_KF_IDEMPOTENT},
     {"bs", (const void*)kl_bs, sizeof(kl_bs_args), KL_KF_IDEMPOTENT},
     {"hist", (const void*)kl_hist, sizeof(kl_hist_args), 0u},
-    {"lookup_index", (const void*)kl_lookup_index, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
-    {"lookup_count", (const void*)kl_lookup_count, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
-    {"lookup_total", (const void*)kl_lookup_total, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
-    {"lookup_offset", (const void*)kl_lookup_offset, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
-    // the scatter's run order depends on LDS atomics; positions are stored
-    {"lookup_scatter", (const void*)kl_lookup_scatter, sizeof(kl_lookup_args), 0u},
     {"lookup", (const void*)kl_lookup, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
-    {"lookup_gather", (const void*)kl_lookup_gather, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
+    {"lookup_index", (const void*)kl_lookup_index, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
     {"probe", (const void*)kl_probe, sizeof(kl_probe_args), 0u},
 #define KL_SYNTHK_ENTRY(V, L)                                                 \
     {"synthk_v" #V "_l" #L, (const void*)kl_synthk_v##V##_l##L, sizeof(kl_synthk_args), \
@@ -821,12 +619,6 @@ const BuiltinEntry kBuiltins[] = {
 };
 
 }  // namespace
-
-extern "C" uint64_t kernelet_lookup_work_entries(uint32_t nq) {
-    LkWork W;
-    lk_work(nq, &W);
-    return W.total;
-}
 
 extern "C" uint64_t kernelet_lookup_index_entries(uint32_t nkeys) {
     if (nkeys == 0) return 0;

@@ -37,16 +37,6 @@ ESTIMATES = {
                    lds_bytes=4096, pur=0.10, mur=0.30),
     "lookup_index": dict(_COMMON, r_mem=0.2, mem_req=64, instr_per_wave=40, max_wg_per_cu=8,
                          pur=0.1, mur=0.5),
-    "lookup_count": dict(_COMMON, r_mem=0.02, mem_req=4, instr_per_wave=800, max_wg_per_cu=8,
-                         lds_bytes=5120, pur=0.5, mur=0.3),
-    "lookup_total": dict(_COMMON, r_mem=0.3, mem_req=4, instr_per_wave=1200, max_wg_per_cu=8,
-                         pur=0.1, mur=0.1),
-    "lookup_offset": dict(_COMMON, r_mem=0.3, mem_req=4, instr_per_wave=2400,
-                          max_wg_per_cu=8, lds_bytes=1024, pur=0.1, mur=0.1),
-    "lookup_scatter": dict(_COMMON, r_mem=0.04, mem_req=16, instr_per_wave=900,
-                           max_wg_per_cu=8, lds_bytes=5120, pur=0.4, mur=0.5),
-    "lookup_gather": dict(_COMMON, r_mem=0.3, mem_req=16, instr_per_wave=20, max_wg_per_cu=8,
-                          pur=0.1, mur=0.6),
     "probe": dict(_COMMON, r_mem=0.001, mem_req=1, instr_per_wave=1000, max_wg_per_cu=8,
                   pur=0.5, mur=0.0),
 }

@@ -18,9 +18,8 @@ from . import _lib
 from .runtime import builtin_grid
 
 TYPES = ["poly", "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup"]
-# every built-in kernel the instances launch (the lookup is a chain: tree,
-# partition of the queries by key range, search, gather)
-KERNELS = TYPES + [k for k in _lib.LOOKUP_CHAIN if k != "lookup"]
+# every built-in kernel the instances launch (the lookup builds its tree first)
+KERNELS = TYPES + ["lookup_index"]
 
 
 @dataclass
@@ -128,13 +127,12 @@ def build(kind: str, dev_in: dict, params: dict, device) -> Instance:
         T["out"] = torch.empty(nq, dtype=torch.int32, device=device)
         ne = int(_lib.lib().kernelet_lookup_index_entries(nk))
         T["index"] = torch.empty(max(ne, 4), dtype=torch.int32, device=device)
-        nw = int(_lib.lib().kernelet_lookup_work_entries(nq))
-        T["work"] = torch.empty(nw, dtype=torch.int32, device=device)
         a = A(_ptr(dev_in["keys"]), _ptr(dev_in["q"]), _ptr(T["out"]), _ptr(T["index"]),
-              _ptr(T["work"]), nk, nq)
+              nk, nq)
         fp = sum(t.numel() * t.element_size() for t in T.values()) + sum(
             t.numel() * t.element_size() for t in dev_in.values())
-        launches = [Launch(a, builtin_grid(k, a), k) for k in _lib.LOOKUP_CHAIN]
+        launches = [Launch(a, builtin_grid("lookup_index", a), "lookup_index"),
+                    Launch(a, builtin_grid("lookup", a), "lookup")]
         return Instance(kind, launches, T, ["out"], fp, "out", dict(dev_in))
     else:
         raise KeyError(kind)

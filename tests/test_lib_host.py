@@ -145,25 +145,10 @@ def test_builtin_descriptors_and_grids():
     a = _lib.StencilArgs(16, 32, 10, 102, 0.5, 0.125)     # nx not a multiple of 4
     with pytest.raises(K.KerneletError):
         K.builtin_grid("stencil", a)
-    a = _lib.LookupArgs(16, 16, 16, 16, 16, 1 << 26, 1 << 26)
+    a = _lib.LookupArgs(16, 16, 16, 16, 1 << 26, 1 << 26)
     assert K.builtin_grid("lookup", a) == (1 << 16, 1, 1)
-    assert K.builtin_grid("lookup_gather", a) == (1 << 16, 1, 1)
-    assert K.builtin_grid("lookup_count", a) == (1 << 14, 1, 1)
-    assert K.builtin_grid("lookup_scatter", a) == (1 << 14, 1, 1)
-    assert K.builtin_grid("lookup_total", a) == (64, 1, 1)
-    assert K.builtin_grid("lookup_offset", a) == (64, 1, 1)
     assert K.builtin_grid("lookup_index", a) == (4473856 // 256, 1, 1)
     assert _lib.lib().kernelet_lookup_index_entries(1 << 26) == 4473856
-    # counts and offsets per 4096-query tile (256 each), 64 x 256 slab sums,
-    # 4 of meta, then partitioned queries, positions and results
-    tiles = (1 << 26) // 4096
-    assert _lib.lib().kernelet_lookup_work_entries(1 << 26) == \
-        2 * tiles * 256 + 64 * 256 + 4 + 3 * (1 << 26)
-    assert _lib.lib().kernelet_lookup_work_entries(4100) == 2 * 2 * 256 + 64 * 256 + 4 + 3 * 4100
-    b = _lib.LookupArgs(16, 16, 16, 16, 0, 100, 100)     # no work buffer
-    with pytest.raises(K.KerneletError):
-        K.builtin_grid("lookup", b)
-    assert K.builtin_grid("lookup_index", b) == (1, 1, 1)
     a = _lib.SgemmArgs(16, 16, 16, 100, 4096, 4096)
     with pytest.raises(K.KerneletError) as e:
         K.builtin_grid("sgemm", a)

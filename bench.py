@@ -38,7 +38,10 @@ def parse():
     ap.add_argument("--instances", type=int, default=8, help="instances per kernel type")
     ap.add_argument("--policy", default="markov", choices=["markov", "fixed", "surrogate"])
     ap.add_argument("--topk", type=int, default=None,
-                    help="pairs the Markov model re-ranks under the surrogate policy")
+                    help="pairs the Markov model re-ranks under the surrogate policy "
+                         "(0: the surrogate decides alone)")
+    ap.add_argument("--surrogate-weights", default=None,
+                    help="surrogate parameters (.npy); default: the packaged weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="fifo,kernelet")
     ap.add_argument("--seed", type=int, default=0)
@@ -217,7 +220,7 @@ def main():
     rt = K.Runtime(0, **over)
     if args.policy == "surrogate":
         from paper_1303_5164_amd import surrogate
-        rt.set_surrogate(np.load(surrogate.WEIGHTS))
+        rt.set_surrogate(np.load(args.surrogate_weights or surrogate.WEIGHTS))
     prof = profiles.load(prefer_measured=not args.estimates)
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     setup_s = time.perf_counter() - t_setup
@@ -315,7 +318,11 @@ def main():
                    "policy": args.policy, "parallelism": "single GPU, 2 co-execution lanes",
                    "inflight": rt.cfg.inflight, "lds_reserve": rt.cfg.lds_reserve,
                    "cp_min": rt.cfg.cp_min,
-                   "profiles": "estimates" if args.estimates else "measured"},
+                   "profiles": "estimates" if args.estimates else "measured",
+                   "surrogate": (None if args.policy != "surrogate" else
+                                 {"topk": rt.cfg.surrogate_topk,
+                                  "weights": os.path.basename(args.surrogate_weights or
+                                                              "surrogate_mi355x.npy")})},
     }
     if "fifo" in legs:
         out["fifo_kernels_per_s"] = round(n_inst / med["fifo"], 3)

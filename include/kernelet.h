@@ -138,7 +138,8 @@ typedef struct {
                               its partner fills the rest (b >= 2); default 2 */
     int32_t max_slices;    /* cap on slices per co-schedule of one kernel (0: none) */
     int64_t hbm_budget;    /* bytes of job footprint admitted at once (0: none) */
-    int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE) */
+    int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE);
+                              0: the surrogate's best pair and ratio as is */
     int32_t reserved[7];
 } kl_config;
 

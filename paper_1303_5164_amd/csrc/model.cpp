@@ -381,18 +381,32 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
         }
         if (!keep.empty()) pairs.swap(keep);
     }
-    if (score && k > 0 && (int)pairs.size() > k) {
+    if (score && (k == 0 || (int)pairs.size() > k)) {
         std::vector<std::pair<const kl_profile*, const kl_profile*>> pp;
         for (auto& pr : pairs)
             pp.emplace_back(&types_[order[pr.first].type], &types_[order[pr.second].type]);
         std::vector<double> sc;
-        if ((*score)(pp, &sc) && sc.size() == pairs.size()) {
+        std::vector<std::pair<int, int>> rat;
+        if ((*score)(pp, &sc, &rat) && sc.size() == pairs.size() && rat.size() == pairs.size()) {
             scored_pairs += (int64_t)pairs.size();
             std::vector<int> idx(pairs.size());
             for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
             // best scores first; ties keep submission order
             std::stable_sort(idx.begin(), idx.end(),
                              [&](int x, int y) { return sc[x] > sc[y]; });
+            if (k == 0) {
+                // the surrogate decides: its best pair at its best ratio
+                const int i = idx[0];
+                const double S = sc[i];
+                if (rat[i].first < 1 || !(S > 0) || 1.0 - 1.0 / S <= cfg_.cp_min) return solo_d;
+                Decision d;
+                d.j1 = order[pairs[i].first].id;
+                d.j2 = order[pairs[i].second].id;
+                d.b1 = rat[i].first;
+                d.b2 = rat[i].second;
+                d.value = 1.0 - 1.0 / S;
+                return d;
+            }
             std::vector<std::pair<int, int>> top;
             for (int i = 0; i < k; ++i) top.push_back(pairs[idx[i]]);
             pairs.swap(top);

@@ -92,13 +92,16 @@ class Planner {
     // restricts the search to the listed type pairs.
     Decision find(const std::vector<PendingJob>& pending,
                   const std::vector<std::pair<int, int>>* only_pairs = nullptr);
-    // Scores candidate pairs given their two profiles (higher = better);
+    // Scores candidate pairs given their two profiles: the predicted
+    // weighted speedup of each pair at its best slice ratio, and that ratio;
     // false if it could not (then every pair is evaluated).
     using Scorer = std::function<bool(
         const std::vector<std::pair<const kl_profile*, const kl_profile*>>&,
-        std::vector<double>*)>;
+        std::vector<double>*, std::vector<std::pair<int, int>>*)>;
     // FindCoSchedule in which the pairs surviving pruning are ranked by
-    // `score` and only the best `k` are evaluated by the Markov model.
+    // `score` and only the best `k` are evaluated by the Markov model; with
+    // k == 0 the best-scored pair and ratio are taken as they are (a pair is
+    // kept when its CP = 1 - 1/S exceeds cp_min).
     Decision find_ranked(const std::vector<PendingJob>& pending, int k, const Scorer& score);
     int64_t scored_pairs = 0;
     const kl_profile& prof(int t) const { return types_[t]; }

@@ -212,7 +212,8 @@ static kl_status check_cfg(const kl_config& c) {
     if (c.wmax < 1 || c.wmax > 64 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
         c.beta < 0 || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
-        c.lds_reserve < 0 || c.lds_reserve > 2) {
+        c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
+        c.hbm_budget < 0) {
         set_error("invalid kl_config field");
         return KL_EINVAL;
     }
@@ -493,10 +494,11 @@ static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
 // Markov model) on a device error.
 static bool surrogate_scores(
     kl_runtime* rt, const std::vector<std::pair<const kl_profile*, const kl_profile*>>& pp,
-    std::vector<double>* scores) {
+    std::vector<double>* scores, std::vector<std::pair<int, int>>* ratios) {
     auto t0 = std::chrono::steady_clock::now();
     const kl_config& c = rt->cfg;
     std::vector<int> owner;  // candidate -> pair
+    std::vector<std::pair<int, int>> cand;  // candidate -> (b1, b2)
     std::vector<float> feat;
     for (size_t i = 0; i < pp.size(); ++i) {
         const kl_profile& a = *pp[i].first;
@@ -509,10 +511,12 @@ static bool surrogate_scores(
                 surrogate_features(b, b2, c.wmax, f + 8);
                 feat.insert(feat.end(), f, f + 16);
                 owner.push_back((int)i);
+                cand.emplace_back(b1, b2);
             }
     }
     const uint32_t n = (uint32_t)owner.size();
     scores->assign(pp.size(), -1e30);
+    ratios->assign(pp.size(), std::make_pair(0, 0));
     if (n == 0) return true;
     if (n > rt->sur_cap) {
         uint32_t cap = 1024;
@@ -541,7 +545,10 @@ static bool surrogate_scores(
         hipStreamSynchronize(rt->sur_stream) != hipSuccess)
         return false;
     for (uint32_t k = 0; k < n; ++k)
-        (*scores)[owner[k]] = std::max((*scores)[owner[k]], (double)rt->sur_hy[k]);
+        if ((double)rt->sur_hy[k] > (*scores)[owner[k]]) {
+            (*scores)[owner[k]] = (double)rt->sur_hy[k];
+            (*ratios)[owner[k]] = cand[k];
+        }
     rt->stats.surrogate_us_total +=
         std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
     rt->stats.surrogate_candidates += n;
@@ -583,9 +590,11 @@ static void decide(kl_runtime* rt, kl_policy policy) {
             }
     } else if (policy == KL_POLICY_SURROGATE) {
         d = rt->planner->find_ranked(
-            pend, std::max(1, rt->cfg.surrogate_topk),
+            pend, std::max(0, rt->cfg.surrogate_topk),
             [rt](const std::vector<std::pair<const kl_profile*, const kl_profile*>>& pp,
-                 std::vector<double>* sc) { return surrogate_scores(rt, pp, sc); });
+                 std::vector<double>* sc, std::vector<std::pair<int, int>>* rat) {
+                return surrogate_scores(rt, pp, sc, rat);
+            });
     } else {
         d = rt->planner->find(pend);
     }

@@ -156,6 +156,26 @@ def dataset(seed: int, n_kernels: int, n_samples: int, lo: int, hi: int, cfg=Non
     return X[:i], T[:i], P[:i]
 
 
+def measured_samples(sweep_path: str, prof=None, kinds=None):
+    """Samples from a balanced co-run sweep of the built-in kernels: for
+    each measured (a at b1, b at b2) the features of both orders, labelled
+    with the measured weighted speedup S; returns X, T and each sample's
+    unordered pair name."""
+    from . import profiles
+    prof = prof or profiles.load()
+    rows = json.load(open(sweep_path))["rows"]
+    X, T, G = [], [], []
+    for r in rows:
+        if kinds and (r["a"] not in kinds or r["b"] not in kinds):
+            continue
+        pa, pb = prof[r["a"]], prof[r["b"]]
+        for (p1, p2, c1, c2) in ((pa, pb, r["b1"], r["b2"]), (pb, pa, r["b2"], r["b1"])):
+            X.append(pair_features(p1, p2, c1, c2))
+            T.append(r["speedup"])
+            G.append("+".join(sorted((r["a"], r["b"]))))
+    return np.array(X, np.float32), np.array(T, np.float32), G
+
+
 def mape(pred, ref) -> float:
     pred, ref = np.asarray(pred, np.float64), np.asarray(ref, np.float64)
     return float(np.mean(np.abs(pred - ref) / np.abs(ref)))
@@ -246,6 +266,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--measured", default=None,
+                    help="balanced co-run sweep JSON of the built-in kernels: its measured "
+                         "speedups join the training set")
+    ap.add_argument("--measured-weight", type=int, default=40,
+                    help="times each measured sample is repeated in the training set")
     a = ap.parse_args()
 
     def log(s):
@@ -257,6 +282,24 @@ def main():
     Xtr, Ttr, _ = dataset(a.seed, a.kernels, a.train_samples, 0, n_train)
     Xte, Tte, _ = dataset(a.seed, a.kernels, a.test_samples, n_train, a.kernels)
     log(f"dataset: {len(Ttr)} train / {len(Tte)} test samples, {time.time() - t0:.1f} s")
+    rep_m = {}
+    if a.measured:
+        Xm, Tm, Gm = measured_samples(a.measured)
+        groups = sorted(set(Gm))
+        # leave one pair out: train without it, predict it
+        pred = np.zeros_like(Tm)
+        for g in groups:
+            hold = np.array([x == g for x in Gm])
+            Xa = np.concatenate([Xtr] + [Xm[~hold]] * a.measured_weight)
+            Ta = np.concatenate([Ttr] + [Tm[~hold]] * a.measured_weight)
+            net = train(Xa, Ta, a.seed, a.epochs)
+            pred[hold] = net.forward(torch.from_numpy(Xm[hold]).to(net.dev)).cpu().numpy()
+        rep_m = {"measured_samples": int(len(Tm)), "measured_pairs": len(groups),
+                 "measured_weight": a.measured_weight,
+                 "leave_one_pair_out_mape": mape(pred, Tm)}
+        log(json.dumps(rep_m))
+        Xtr = np.concatenate([Xtr] + [Xm] * a.measured_weight)
+        Ttr = np.concatenate([Ttr] + [Tm] * a.measured_weight)
     t0 = time.time()
     net = train(Xtr, Ttr, a.seed, a.epochs, log=log)
     t_train = time.time() - t0
@@ -265,7 +308,11 @@ def main():
     rep = {"kernels": a.kernels, "train_kernels": n_train, "train_samples": int(len(Ttr)),
            "test_samples": int(len(Tte)), "epochs": a.epochs, "train_s": round(t_train, 2),
            "train_mape": mape(ytr, Ttr), "test_mape": mape(yte, Tte),
-           "label": "Markov-model weighted speedup (analytic profiles)"}
+           "label": "Markov-model weighted speedup (analytic profiles)" +
+                    (" and measured co-run speedups" if a.measured else ""), **rep_m}
+    if a.measured:
+        rep["measured_train_mape"] = mape(
+            net.forward(torch.from_numpy(Xm).to(net.dev)).cpu().numpy(), Tm)
     log(json.dumps(rep))
     np.save(a.out, net.params())
     if a.report:

@@ -10,7 +10,7 @@ KINDS = ["poly", "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup"]
 
 def runtime(**over):
     rt = K.Runtime(0, **over)
-    kids = {k: rt.register_builtin(k) for k in KINDS + ["lookup_index", "probe"]}
+    kids = {k: rt.register_builtin(k) for k in W.KERNELS + ["probe"]}
     return rt, kids
 
 

@@ -113,6 +113,28 @@ def test_lookup(rtk):
     assert np.array_equal(out, oracle.lower_bound(h["keys"], h["q"]))
 
 
+@pytest.mark.parametrize("nkeys,nq,slice_wgs", [(300007, 3 * 4096 + 12, 7),
+                                                (1 << 20, 1 << 18, 64),
+                                                (5000, 4100, 1)])
+def test_lookup_queries_within_the_keys(rtk, nkeys, nq, slice_wgs):
+    """Queries drawn inside the key range (nearly all are partitioned), a
+    ragged last tile of 4096 queries, and every launch of the chain sliced."""
+    h = synth.lookup(1, nkeys=nkeys, nq=nq)
+    k = h["keys"]
+    u = synth.below_u32(2, synth.STREAM["lookup_q"], nq, int(k[-1]) + 2)
+    h["q"] = u.astype(np.uint32)
+    h["q"][:4] = np.array([0, k[-1], k[-1] + 1, k[0]], dtype=np.uint32)
+    out = _both(rtk, _case("lookup", h), slice_wgs)
+    assert np.array_equal(out, oracle.lower_bound(h["keys"], h["q"]))
+
+
+def test_lookup_all_queries_above_the_keys(rtk):
+    keys = np.arange(1, 1001, dtype=np.uint32) * 3
+    h = dict(keys=keys, q=np.full(8192, 10_000, np.uint32))
+    out = _both(rtk, _case("lookup", h), 5)
+    assert np.all(out == 1000)
+
+
 def test_lookup_single_key(rtk):
     h = dict(keys=np.array([7], np.uint32), q=np.array([0, 7, 8, 6], np.uint32))
     out = _both(rtk, _case("lookup", h), 1)

@@ -321,3 +321,26 @@ def test_surrogate_policy_ranks_pairs_and_runs_everything(L):
     assert st["surrogate_pairs"] >= 3 and st["surrogate_candidates"] > 0
     assert any(dd["j2"] >= 0 for dd in h.rt.decisions())
     h.close()
+
+
+def test_surrogate_alone_decides_pair_and_ratio(L):
+    """surrogate_topk = 0: the best-scored pair runs at the surrogate's best
+    ratio without a Markov evaluation (no model time is spent)."""
+    h = Harness(L, surrogate_topk=0, use_prune=0)
+    from paper_1303_5164_amd import surrogate as S
+    p = S.init_params(0)
+    p[-1] = 5.0            # output bias: every candidate predicts S well above 1
+    h.rt.set_surrogate(p)
+    jobs = [h.job(64, i, kind=i % 2, us=20) for i in range(6)]
+    _run_with_deadline(lambda: h.rt.schedule("surrogate", blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    dec = [d for d in h.rt.decisions() if d["j2"] >= 0]
+    assert dec and all(d["value"] > 0.5 and d["b1"] >= 1 and d["b2"] >= 1 for d in dec)
+    # no Markov evaluation of the pair: its predicted co-run IPCs stay unset
+    assert all(d["cipc1"] == 0.0 and d["cipc2"] == 0.0 for d in dec)
+    assert h.rt.stats()["surrogate_pairs"] > 0
+    h.close()
+    with pytest.raises(K.KerneletError):
+        K.Runtime(0, lib_handle=L, n_cu=4, surrogate_topk=-1)

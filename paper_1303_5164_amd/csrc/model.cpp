@@ -293,6 +293,7 @@ void Planner::set_types(const std::vector<kl_profile>& t) {
     types_ = t;
     solo_.clear();
     pair_.clear();
+    scored_.clear();
 }
 
 void Planner::set_type(int idx, const kl_profile& p) {
@@ -301,6 +302,12 @@ void Planner::set_type(int idx, const kl_profile& p) {
     types_[idx] = p;
     solo_.clear();
     pair_.clear();
+    scored_.clear();
+}
+
+void Planner::clear_scores() {
+    std::lock_guard<std::mutex> g(mu_);
+    scored_.clear();
 }
 
 double Planner::solo(int t) {
@@ -382,13 +389,41 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
         if (!keep.empty()) pairs.swap(keep);
     }
     if (score && (k == 0 || (int)pairs.size() > k)) {
+        // scores depend on the two types only: score the pairs not seen yet
         std::vector<std::pair<const kl_profile*, const kl_profile*>> pp;
-        for (auto& pr : pairs)
-            pp.emplace_back(&types_[order[pr.first].type], &types_[order[pr.second].type]);
-        std::vector<double> sc;
-        std::vector<std::pair<int, int>> rat;
-        if ((*score)(pp, &sc, &rat) && sc.size() == pairs.size() && rat.size() == pairs.size()) {
-            scored_pairs += (int64_t)pairs.size();
+        std::vector<size_t> todo;
+        for (size_t i = 0; i < pairs.size(); ++i) {
+            const int ta = order[pairs[i].first].type, tb = order[pairs[i].second].type;
+            if (scored_.count({ta, tb})) continue;
+            todo.push_back(i);
+            pp.emplace_back(&types_[ta], &types_[tb]);
+        }
+        std::vector<double> sc_new;
+        std::vector<std::pair<int, int>> rat_new;
+        bool ok = true;
+        if (!pp.empty()) {
+            ok = (*score)(pp, &sc_new, &rat_new) && sc_new.size() == pp.size() &&
+                 rat_new.size() == pp.size();
+            if (ok) {
+                scored_pairs += (int64_t)pp.size();
+                for (size_t j = 0; j < todo.size(); ++j) {
+                    const auto& pr = pairs[todo[j]];
+                    scored_[{order[pr.first].type, order[pr.second].type}] = {sc_new[j],
+                                                                              rat_new[j]};
+                }
+            }
+        } else {
+            ++cache_hits;
+        }
+        std::vector<double> sc(pairs.size());
+        std::vector<std::pair<int, int>> rat(pairs.size());
+        if (ok)
+            for (size_t i = 0; i < pairs.size(); ++i) {
+                const auto& e = scored_.at({order[pairs[i].first].type, order[pairs[i].second].type});
+                sc[i] = e.first;
+                rat[i] = e.second;
+            }
+        if (ok) {
             std::vector<int> idx(pairs.size());
             for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
             // best scores first; ties keep submission order

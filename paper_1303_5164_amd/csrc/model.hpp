@@ -103,6 +103,8 @@ class Planner {
     // k == 0 the best-scored pair and ratio are taken as they are (a pair is
     // kept when its CP = 1 - 1/S exceeds cp_min).
     Decision find_ranked(const std::vector<PendingJob>& pending, int k, const Scorer& score);
+    // Forget cached surrogate scores (new network parameters).
+    void clear_scores();
     int64_t scored_pairs = 0;
     const kl_profile& prof(int t) const { return types_[t]; }
     int ntypes() const { return (int)types_.size(); }
@@ -117,6 +119,8 @@ class Planner {
     std::vector<kl_profile> types_;
     std::map<int, double> solo_;
     std::map<std::pair<int, int>, Ratio> pair_;
+    // surrogate score and best ratio per ordered type pair
+    std::map<std::pair<int, int>, std::pair<double, std::pair<int, int>>> scored_;
     std::mutex mu_;
 };
 

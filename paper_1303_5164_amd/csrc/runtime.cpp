@@ -1385,6 +1385,7 @@ kl_status kernelet_set_surrogate(kl_runtime* rt, const float* params, uint32_t n
     KL_HIP(hipMemcpyAsync(rt->sur_params, params, KL_MLP_PARAMS * sizeof(float),
                           hipMemcpyHostToDevice, rt->sur_stream));
     KL_HIP(hipStreamSynchronize(rt->sur_stream));
+    rt->planner->clear_scores();
     return KL_OK;
 }
 

@@ -318,7 +318,8 @@ def test_surrogate_policy_ranks_pairs_and_runs_everything(L):
         h.rt.wait(j[0], 5_000_000_000)
         assert np.all(j[1] == 1)
     st = h.rt.stats()
-    assert st["surrogate_pairs"] >= 3 and st["surrogate_candidates"] > 0
+    # three types: three ordered pairs scored once, then served from the cache
+    assert 3 <= st["surrogate_pairs"] <= 6 and st["surrogate_candidates"] > 0
     assert any(dd["j2"] >= 0 for dd in h.rt.decisions())
     h.close()
 

@@ -43,7 +43,9 @@ def parse():
     ap.add_argument("--surrogate-weights", default=None,
                     help="surrogate parameters (.npy); default: the packaged weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fifo,kernelet")
+    ap.add_argument("--legs", default="fifo,kernelet,surrogate",
+                    help="fifo: one in-order stream; kernelet: --policy; surrogate: the "
+                         "surrogate network deciding (weights trained with measured co-runs)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
     ap.add_argument("--lds-reserve", type=int, default=None)
@@ -215,12 +217,17 @@ def main():
         over["lds_reserve"] = args.lds_reserve
     if args.cp_min is not None:
         over["cp_min"] = args.cp_min
-    if args.topk is not None:
-        over["surrogate_topk"] = args.topk
+    legs = [l for l in args.legs.split(",") if l]
+    main_leg = "kernelet" if "kernelet" in legs else legs[0]
+    over["surrogate_topk"] = args.topk if args.topk is not None else 0
     rt = K.Runtime(0, **over)
-    if args.policy == "surrogate":
+    sur_weights = None
+    if args.policy == "surrogate" or "surrogate" in legs:
         from paper_1303_5164_amd import surrogate
-        rt.set_surrogate(np.load(args.surrogate_weights or surrogate.WEIGHTS))
+        sur_weights = args.surrogate_weights or (
+            surrogate.WEIGHTS_MEASURED if os.path.exists(surrogate.WEIGHTS_MEASURED)
+            else surrogate.WEIGHTS)
+        rt.set_surrogate(np.load(sur_weights))
     prof = profiles.load(prefer_measured=not args.estimates)
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     setup_s = time.perf_counter() - t_setup
@@ -248,7 +255,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    legs = [l for l in args.legs.split(",") if l]
     times = {l: [] for l in legs}
     turn = {l: [] for l in legs}
     ktime = {k: [0.0, 0, 0] for k in W.KERNELS}
@@ -265,8 +271,8 @@ def main():
             jobs = [W.submit(rt, kids, inst) for inst in insts]
             torch.cuda.synchronize()
             t0 = time.monotonic_ns()
-            rt.schedule("fifo" if leg == "fifo" else args.policy, blocking=True,
-                        wait_done=True)
+            pol = {"fifo": "fifo", "surrogate": "surrogate"}.get(leg, args.policy)
+            rt.schedule(pol, blocking=True, wait_done=True)
             torch.cuda.synchronize()
             t1 = time.monotonic_ns()
             if timed_step:
@@ -284,18 +290,18 @@ def main():
                 kind_of = {j: (inst.launches[i].kernel or inst.kind)
                            for inst, js in zip(insts, jobs) for i, j in enumerate(js)}
                 for d in rt.decisions():
-                    decisions += 1
+                    decisions += leg == main_leg
                     if timed_step:
                         key = kind_of.get(d["j1"], "?") + (
                             "+" + kind_of.get(d["j2"], "?") if d["j2"] >= 0 else "")
-                        pairs[key] = pairs.get(key, 0) + 1
+                        pl = pairs.setdefault(leg, {})
+                        pl[key] = pl.get(key, 0) + 1
             rt.reap()
             print(f"# step {step} {leg}: {(t1 - t0) / 1e6:.2f} ms", file=sys.stderr,
                   flush=True)
 
     n_inst = len(insts)
     med = {l: float(np.median(times[l])) for l in legs}
-    main_leg = "kernelet" if "kernelet" in legs else legs[0]
     value = n_inst / med[main_leg]
     out = {
         "metric": METRIC,
@@ -319,10 +325,9 @@ def main():
                    "inflight": rt.cfg.inflight, "lds_reserve": rt.cfg.lds_reserve,
                    "cp_min": rt.cfg.cp_min,
                    "profiles": "estimates" if args.estimates else "measured",
-                   "surrogate": (None if args.policy != "surrogate" else
+                   "surrogate": (None if sur_weights is None else
                                  {"topk": rt.cfg.surrogate_topk,
-                                  "weights": os.path.basename(args.surrogate_weights or
-                                                              "surrogate_mi355x.npy")})},
+                                  "weights": os.path.basename(sur_weights)})},
     }
     if "fifo" in legs:
         out["fifo_kernels_per_s"] = round(n_inst / med["fifo"], 3)
@@ -333,7 +338,13 @@ def main():
         out[f"{l}_p50_turnaround_ms"] = round(nearest_rank(turn[l], 0.5), 3)
         out[f"{l}_p99_turnaround_ms"] = round(nearest_rank(turn[l], 0.99), 3)
     out["decisions_per_step"] = decisions / max(1, args.warmup + args.steps)
-    out["coschedules"] = dict(sorted(pairs.items(), key=lambda kv: -kv[1]))
+    for l, pl in pairs.items():
+        name = "coschedules" if l == main_leg else f"{l}_coschedules"
+        out[name] = dict(sorted(pl.items(), key=lambda kv: -kv[1]))
+    if "surrogate" in legs and main_leg != "surrogate":
+        out["surrogate_kernels_per_s"] = round(n_inst / med["surrogate"], 3)
+        if "fifo" in legs:
+            out["gain_surrogate_vs_fifo"] = round(med["fifo"] / med["surrogate"], 4)
 
     # roofline of the dominant kernel: all its launches in the timed region
     dom = max(W.KERNELS, key=lambda k: ktime[k][0])

@@ -83,6 +83,11 @@ typedef struct {
     int32_t min_slice_wgs; /* calibrated minimum slice (0: unknown)        */
     int32_t access;        /* dominant access pattern: 0 coalesced,
                               1 strided, 2 random (a surrogate feature)    */
+    int32_t comp_pool;     /* 0: the compute stall has the fixed latency
+                              lat_comp; 1: it waits on the CU's LDS, latency
+                              lat_comp + beta_lds * (waves of all resident
+                              kernels stalled on LDS)                      */
+    int32_t reserved;
 } kl_profile;
 
 #define KL_KF_IDEMPOTENT 1u /* re-running a slice gives the same result */
@@ -141,6 +146,11 @@ typedef struct {
     int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE);
                               0: the surrogate's best pair and ratio as is */
     int32_t reserved[7];
+    double beta_lds;       /* latency added per wave stalled on LDS, slots
+                              (0: LDS stalls have fixed latencies)         */
+    double min_pair_slots; /* a job predicted to finish alone within this
+                              many issue slots is never co-scheduled
+                              (0: every job may be)                        */
 } kl_config;
 
 typedef struct {

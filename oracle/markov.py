@@ -32,7 +32,11 @@ Readings where the paper is silent or garbled (each is listed in the design doc):
     load, contradicting the sentence before it); beta = 0 gives constant L;
   * "sum of the probabilities of all possible transitions" = independent
     warps, i.e. a convolution of binomial / multinomial counts;
-  * in Eqs. (5)-(6) the undefined R_(i,j) is the joint round length D.
+  * in Eqs. (5)-(6) the undefined R_(i,j) is the joint round length D;
+  * (extension for GPUs whose kernels are bound by different shared
+    resources) each contended class belongs to a pool, the HBM (pool 0) or
+    the CU's LDS (pool 1), and its latency grows with the requests held in
+    its own pool only: L = base + beta_pool * n_pool.
 """
 from __future__ import annotations
 
@@ -46,8 +50,9 @@ import numpy as np
 @dataclass(frozen=True)
 class StallClass:
     r: float          # prob. that an issued instruction stalls the wave here
-    base: float       # latency with an idle memory system (issue slots)
-    req: float = 0.0  # outstanding memory requests held while stalled (0: not memory)
+    base: float       # latency with the shared resource idle (issue slots)
+    req: float = 0.0  # requests held in the pool while stalled (0: fixed latency)
+    pool: int = 0     # 0: HBM, 1: the CU's LDS
 
 
 @dataclass(frozen=True)
@@ -89,7 +94,8 @@ def kernel_states(w: int, nclass: int):
 class Chain:
     kernels: list          # list[Kernel]
     waves: list            # list[int]
-    beta: float = 0.0      # latency per outstanding request
+    beta: float = 0.0      # latency per outstanding HBM request
+    beta_lds: float = 0.0  # latency per wave stalled on LDS
     states: list = field(default_factory=list)
     P: np.ndarray = None
 
@@ -107,13 +113,14 @@ class Chain:
     def round_len(self, s):
         return max(sum(self.ready(s, k) for k in range(len(self.kernels))), 1)
 
-    def outstanding(self, s):
+    def outstanding(self, s, pool=0):
         return sum(n * c.req for sk, kern in zip(s, self.kernels)
-                   for n, c in zip(sk, kern.classes))
+                   for n, c in zip(sk, kern.classes) if c.pool == pool)
 
     def latency(self, s, c: StallClass):
         if c.req > 0:
-            return c.base + self.beta * self.outstanding(s)
+            b = self.beta if c.pool == 0 else self.beta_lds
+            return c.base + b * self.outstanding(s, c.pool)
         return c.base
 
     def ret_prob(self, s, c: StallClass):
@@ -184,21 +191,23 @@ class Chain:
 
 
 # ------------------------------------------------------------ convenience
-def ipc_homogeneous(kernel: Kernel, w: int, beta: float = 0.0) -> float:
+def ipc_homogeneous(kernel: Kernel, w: int, beta: float = 0.0,
+                    beta_lds: float = 0.0) -> float:
     if w == 0:
         return 0.0
-    return Chain([kernel], [w], beta).ipc()[0]
+    return Chain([kernel], [w], beta, beta_lds).ipc()[0]
 
 
-def ipc_pair(k1: Kernel, w1: int, k2: Kernel, w2: int, beta: float = 0.0):
+def ipc_pair(k1: Kernel, w1: int, k2: Kernel, w2: int, beta: float = 0.0,
+             beta_lds: float = 0.0):
     """Per-kernel IPCs of two co-resident kernels (Eqs. 5-7)."""
     if w1 == 0 and w2 == 0:
         return 0.0, 0.0
     if w2 == 0:
-        return ipc_homogeneous(k1, w1, beta), 0.0
+        return ipc_homogeneous(k1, w1, beta, beta_lds), 0.0
     if w1 == 0:
-        return 0.0, ipc_homogeneous(k2, w2, beta)
-    return tuple(Chain([k1, k2], [w1, w2], beta).ipc())
+        return 0.0, ipc_homogeneous(k2, w2, beta, beta_lds)
+    return tuple(Chain([k1, k2], [w1, w2], beta, beta_lds).ipc())
 
 
 def cp(cipc, ipc_solo) -> float:
@@ -240,7 +249,7 @@ def feasible_ratios(p1: KProfile, p2: KProfile, wmax=8, vgpr_file=512,
     return out
 
 
-def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", **kw):
+def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", beta_lds=0.0, **kw):
     """Search the feasible (b1, b2) of a pair.
 
     mode "balanced": maximise CP_eff = 1 - max(T1, T2) / (T1s + T2s) with
@@ -253,12 +262,12 @@ def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", **kw):
     Returns (b1, b2, cp_value, cipc1, cipc2); first maximum in (b1, b2)
     lexicographic order wins ties.
     """
-    s1 = ipc_homogeneous(p1.kernel, p1.max_wg_per_cu * p1.wave_per_wg, beta)
-    s2 = ipc_homogeneous(p2.kernel, p2.max_wg_per_cu * p2.wave_per_wg, beta)
+    s1 = ipc_homogeneous(p1.kernel, p1.max_wg_per_cu * p1.wave_per_wg, beta, beta_lds)
+    s2 = ipc_homogeneous(p2.kernel, p2.max_wg_per_cu * p2.wave_per_wg, beta, beta_lds)
     best = None
     for b1, b2 in feasible_ratios(p1, p2, **kw):
         c1, c2 = ipc_pair(p1.kernel, b1 * p1.wave_per_wg,
-                          p2.kernel, b2 * p2.wave_per_wg, beta)
+                          p2.kernel, b2 * p2.wave_per_wg, beta, beta_lds)
         cpv = cp((c1, c2), (s1, s2))
         # instructions one SIMD executes for a slice: b workgroups, each
         # with wave_per_wg waves of I_K instructions

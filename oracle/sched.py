@@ -59,6 +59,8 @@ class Config:
     alpha_m: float = 0.1
     use_prune: bool = True
     beta: float = 0.0
+    beta_lds: float = 0.0
+    min_pair_slots: float = 0.0
     mode: str = "cp"
     cp_min: float = 0.0
     wmax: int = 8
@@ -89,7 +91,8 @@ class Model:
         if t not in self._solo:
             p = self.types[t].prof
             self._solo[t] = markov.ipc_homogeneous(
-                p.kernel, p.max_wg_per_cu * p.wave_per_wg, self.cfg.beta)
+                p.kernel, p.max_wg_per_cu * p.wave_per_wg, self.cfg.beta,
+                self.cfg.beta_lds)
         return self._solo[t]
 
     def pair(self, t1, t2):
@@ -98,7 +101,7 @@ class Model:
             c = self.cfg
             self._pair[key] = markov.best_ratio(
                 self.types[t1].prof, self.types[t2].prof, c.beta, c.mode,
-                wmax=c.wmax, vgpr_file=c.vgpr_file, lds_cu=c.lds_cu)
+                beta_lds=c.beta_lds, wmax=c.wmax, vgpr_file=c.vgpr_file, lds_cu=c.lds_cu)
         return self._pair[key]
 
     def rate(self, t, ipc):
@@ -115,6 +118,10 @@ def find_coschedule(pending, model: Model) -> Decision:
     first = order[0]
     solo = Decision(first.id, -1, model.types[first.type].prof.max_wg_per_cu,
                     0, 0.0, model.solo_ipc(first.type), 0.0)
+    if cfg.min_pair_slots > 0:
+        # a job that would finish alone within min_pair_slots is never paired
+        order = [j for j in order
+                 if not (j.rem / model.rate(j.type, model.solo_ipc(j.type)) < cfg.min_pair_slots)]
     if len(order) < 2:
         return solo
     pairs = [(a, b) for ia, a in enumerate(order) for b in order[ia + 1:]]

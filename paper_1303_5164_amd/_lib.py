@@ -33,7 +33,8 @@ class Profile(C.Structure):
                 ("pur", C.c_double), ("mur", C.c_double), ("solo_ipc", C.c_double),
                 ("max_wg_per_cu", C.c_int32), ("waves_per_simd", C.c_int32),
                 ("vgpr", C.c_int32), ("lds_bytes", C.c_int32),
-                ("min_slice_wgs", C.c_int32), ("access", C.c_int32)]
+                ("min_slice_wgs", C.c_int32), ("access", C.c_int32),
+                ("comp_pool", C.c_int32), ("reserved", C.c_int32)]
 
 
 class KernelDesc(C.Structure):
@@ -50,7 +51,8 @@ class Config(C.Structure):
                 ("beta", C.c_double), ("lanes", C.c_int32), ("inflight", C.c_int32),
                 ("lds_reserve", C.c_int32), ("max_slices", C.c_int32),
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("reserved", C.c_int32 * 7), ("beta_lds", C.c_double),
+                ("min_pair_slots", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -12,9 +12,9 @@ namespace kl {
 KernelModel kernel_model(const kl_profile& p, const kl_config& cfg) {
     KernelModel m;
     m.nclass = 1;
-    m.cls[0] = {p.r_mem, p.lat_mem > 0 ? p.lat_mem : cfg.mem_latency, p.mem_req};
+    m.cls[0] = {p.r_mem, p.lat_mem > 0 ? p.lat_mem : cfg.mem_latency, p.mem_req, 0};
     if (p.r_comp > 0) {
-        m.cls[1] = {p.r_comp, p.lat_comp, 0.0};
+        m.cls[1] = {p.r_comp, p.lat_comp, p.comp_pool == 1 ? 1.0 : 0.0, 1};
         m.nclass = 2;
     }
     return m;
@@ -101,8 +101,9 @@ void stationary(const std::vector<double>& P, int N, std::vector<double>& pi) {
 
 }  // namespace
 
-void chain_ipc(const KernelModel* km, const int* w, int nk, double beta,
-               double* ipc_out) {
+void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
+               double beta_lds, double* ipc_out) {
+    const double beta[2] = {beta_hbm, beta_lds};
     KStates ks[2] = {enumerate(w[0], km[0].nclass),
                      enumerate(nk > 1 ? w[1] : 0, nk > 1 ? km[1].nclass : 1)};
     const int S1 = ks[0].size(), S2 = nk > 1 ? ks[1].size() : 1;
@@ -114,12 +115,13 @@ void chain_ipc(const KernelModel* km, const int* w, int nk, double beta,
             int nst[2][2] = {{ks[0].n0[i1], ks[0].n1[i1]},
                              {nk > 1 ? ks[1].n0[i2] : 0, nk > 1 ? ks[1].n1[i2] : 0}};
             int ready[2];
-            double outst = 0.0;
+            double outst[2] = {0.0, 0.0};  // requests held in each pool
             int rtot = 0;
             for (int k = 0; k < nk; ++k) {
                 ready[k] = w[k] - nst[k][0] - nst[k][1];
                 rtot += ready[k];
-                for (int c = 0; c < km[k].nclass; ++c) outst += nst[k][c] * km[k].cls[c].req;
+                for (int c = 0; c < km[k].nclass; ++c)
+                    outst[km[k].cls[c].pool] += nst[k][c] * km[k].cls[c].req;
             }
             double D = std::max(rtot, 1);
             for (int k = 0; k < nk; ++k) {
@@ -127,7 +129,7 @@ void chain_ipc(const KernelModel* km, const int* w, int nk, double beta,
                 double q[2] = {0, 0};
                 for (int c = 0; c < m.nclass; ++c) {
                     const StallClass& sc = m.cls[c];
-                    double lat = sc.req > 0 ? sc.base + beta * outst : sc.base;
+                    double lat = sc.req > 0 ? sc.base + beta[sc.pool] * outst[sc.pool] : sc.base;
                     q[c] = std::min(1.0, D / lat);
                 }
                 std::vector<double>& out = mv[k];
@@ -205,7 +207,7 @@ double solo_ipc(const kl_profile& p, const kl_config& cfg) {
     if (w <= 0) return 0.0;
     KernelModel km = kernel_model(p, cfg);
     double ipc;
-    chain_ipc(&km, &w, 1, cfg.beta, &ipc);
+    chain_ipc(&km, &w, 1, cfg.beta, cfg.beta_lds, &ipc);
     return ipc;
 }
 
@@ -241,7 +243,7 @@ static Ratio best_ratio_with(const kl_profile& p1, const kl_profile& p2,
             if (!ratio_feasible(p1, p2, cfg, b1, b2)) continue;
             int w[2] = {b1 * p1.waves_per_simd, b2 * p2.waves_per_simd};
             double c[2];
-            chain_ipc(km, w, 2, cfg.beta, c);
+            chain_ipc(km, w, 2, cfg.beta, cfg.beta_lds, c);
             double solo[2] = {s1, s2};
             double cpv = cp_value(c, solo, 2);
             double n1 = (double)w[0] * p1.instr_per_wave;
@@ -362,11 +364,21 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
         for (const auto& o : order) seen |= o.type == j.type;
         if (!seen) order.push_back(j);
     }
-    const PendingJob& first = order[0];
+    const PendingJob first = order[0];
     solo_d.j1 = first.id;
     solo_d.j2 = -1;
     solo_d.b1 = types_[first.type].max_wg_per_cu;
     solo_d.cipc1 = solo(first.type);
+    if (cfg_.min_pair_slots > 0) {
+        // a job that would finish alone within min_pair_slots issue slots is
+        // not worth a co-schedule: it only runs alone
+        std::vector<PendingJob> keep;
+        for (const auto& j : order) {
+            const double t = j.wgs / wg_rate(types_[j.type], solo(j.type), cfg_.n_cu);
+            if (!(t < cfg_.min_pair_slots)) keep.push_back(j);
+        }
+        order.swap(keep);
+    }
     if (order.size() < 2) return solo_d;
 
     const int n = (int)order.size();

@@ -24,8 +24,9 @@ namespace kl {
 
 struct StallClass {
     double r;     // probability per issued instruction
-    double base;  // latency with an idle memory system (issue slots)
-    double req;   // outstanding requests held while stalled (0: compute)
+    double base;  // latency with the shared resource idle (issue slots)
+    double req;   // requests held in its pool while stalled (0: fixed latency)
+    int pool;     // contended resource: 0 HBM, 1 the CU's LDS
 };
 
 struct KernelModel {
@@ -38,8 +39,8 @@ struct KernelModel {
 KernelModel kernel_model(const kl_profile& p, const kl_config& cfg);
 
 // Per-kernel IPCs of up to two co-resident kernels with w[k] waves each.
-void chain_ipc(const KernelModel* km, const int* w, int nk, double beta,
-               double* ipc_out);
+void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
+               double beta_lds, double* ipc_out);
 
 double cp_value(const double* cipc, const double* solo, int n);
 
@@ -69,8 +70,9 @@ void surrogate_features(const kl_profile& p, int b, int wmax, float* out8);
 
 // One pending job as seen by FindCoSchedule.
 struct PendingJob {
-    int64_t id;    // submission order key (smaller = earlier)
-    int type;      // kernel type index
+    int64_t id;        // submission order key (smaller = earlier)
+    int type;          // kernel type index
+    double wgs = 0.0;  // workgroups still to run
 };
 
 struct Decision {

@@ -211,7 +211,7 @@ static kl_config defaults() {
 static kl_status check_cfg(const kl_config& c) {
     if (c.wmax < 1 || c.wmax > 64 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
-        c.beta < 0 || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
+        c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
         c.hbm_budget < 0) {
         set_error("invalid kl_config field");
@@ -224,7 +224,7 @@ static kl_status check_profile(const kl_profile& p) {
     if (!(p.r_mem >= 0 && p.r_comp >= 0 && p.r_mem + p.r_comp <= 1.0) || p.mem_req < 0 ||
         p.lat_mem < 0 || (p.r_comp > 0 && !(p.lat_comp >= 1.0)) || !(p.instr_per_wave > 0) ||
         p.max_wg_per_cu < 1 || p.waves_per_simd < 1 || p.vgpr < 0 || p.lds_bytes < 0 ||
-        p.access < 0 || p.access > 2) {
+        p.access < 0 || p.access > 2 || p.comp_pool < 0 || p.comp_pool > 1) {
         set_error("invalid kl_profile field");
         return KL_EINVAL;
     }
@@ -560,7 +560,7 @@ static void decide(kl_runtime* rt, kl_policy policy) {
     std::vector<PendingJob> pend;
     for (kl_job id : rt->live) {
         const Job& j = rt->jobs.at(id);
-        if (runnable(j)) pend.push_back({id, j.type});
+        if (runnable(j)) pend.push_back({id, j.type, (double)(j.total - j.next)});
     }
     rt->cs_active = false;
     rt->cs_job[0] = rt->cs_job[1] = KL_NO_JOB;
@@ -1439,12 +1439,12 @@ kl_status kernelet_predict(const kl_config* cfg, const kl_profile* p1, const kl_
         int w = w1 ? w1 : w2;
         KernelModel km = kernel_model(p, c);
         double v;
-        chain_ipc(&km, &w, 1, c.beta, &v);
+        chain_ipc(&km, &w, 1, c.beta, c.beta_lds, &v);
         out[w1 ? 0 : 1] = v;
     } else {
         KernelModel km[2] = {kernel_model(*p1, c), kernel_model(*p2, c)};
         int w[2] = {w1, w2};
-        chain_ipc(km, w, 2, c.beta, out);
+        chain_ipc(km, w, 2, c.beta, c.beta_lds, out);
     }
     if (ipc1) *ipc1 = out[0];
     if (ipc2) *ipc2 = out[1];
@@ -1528,7 +1528,7 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
     while (ndone < n_jobs) {
         std::vector<PendingJob> pend;
         for (int i = 0; i < n_jobs; ++i)
-            if (!fin[i] && arrival(i) <= t) pend.push_back({i, job_profile[i]});
+            if (!fin[i] && arrival(i) <= t) pend.push_back({i, job_profile[i], rem[i]});
         if (pend.empty()) {
             double nt = 1e300;
             for (int i = 0; i < n_jobs; ++i)

@@ -26,9 +26,11 @@ def test_exports_every_declared_symbol():
 
 
 def oracle_kernel(p, mem_latency=400.0):
-    cl = [M.StallClass(p["r_mem"], p.get("lat_mem") or mem_latency, p.get("mem_req", 1.0))]
+    cl = [M.StallClass(p["r_mem"], p.get("lat_mem") or mem_latency, p.get("mem_req", 1.0), 0)]
     if p.get("r_comp", 0) > 0:
-        cl.append(M.StallClass(p["r_comp"], p["lat_comp"], 0.0))
+        # a compute stall on the CU's LDS holds one request in the LDS pool
+        lds = p.get("comp_pool", 0) == 1
+        cl.append(M.StallClass(p["r_comp"], p["lat_comp"], 1.0 if lds else 0.0, 1))
     return M.Kernel(tuple(cl))
 
 
@@ -44,21 +46,23 @@ def rand_profile(rng, two_class):
              vgpr=int(rng.choice([16, 32, 64, 128])), lds_bytes=int(rng.choice([0, 4096, 32768])),
              pur=float(rng.uniform(0, 1)), mur=float(rng.uniform(0, 1)))
     if two_class:
-        p.update(r_comp=float(rng.uniform(0.01, 0.3)), lat_comp=float(rng.uniform(2, 40)))
+        p.update(r_comp=float(rng.uniform(0.01, 0.3)), lat_comp=float(rng.uniform(2, 40)),
+                 comp_pool=int(rng.integers(0, 2)))
     return p
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(10))
 def test_predict_matches_oracle(seed):
     rng = np.random.default_rng(seed)
     p1, p2 = rand_profile(rng, seed % 2 == 0), rand_profile(rng, seed % 3 == 0)
     beta = [0.0, 0.5, 2.0][seed % 3]
-    cfg = K.default_config(beta=beta)
+    beta_lds = [0.0, 3.0, 12.0][seed % 3 if seed < 6 else (seed + 1) % 3]
+    cfg = K.default_config(beta=beta, beta_lds=beta_lds)
     w1, w2 = int(rng.integers(1, 5)), int(rng.integers(1, 5))
     i1, i2, cp = K.predict(p1, p2, w1, w2, cfg)
-    o = M.ipc_pair(oracle_kernel(p1), w1, oracle_kernel(p2), w2, beta)
-    s = (M.ipc_homogeneous(oracle_kernel(p1), p1["max_wg_per_cu"], beta),
-         M.ipc_homogeneous(oracle_kernel(p2), p2["max_wg_per_cu"], beta))
+    o = M.ipc_pair(oracle_kernel(p1), w1, oracle_kernel(p2), w2, beta, beta_lds)
+    s = (M.ipc_homogeneous(oracle_kernel(p1), p1["max_wg_per_cu"], beta, beta_lds),
+         M.ipc_homogeneous(oracle_kernel(p2), p2["max_wg_per_cu"], beta, beta_lds))
     assert abs(i1 - o[0]) <= 1e-9 * abs(o[0]) and abs(i2 - o[1]) <= 1e-9 * abs(o[1])
     assert abs(cp - M.cp(o, s)) <= 1e-9 * max(1.0, abs(cp))
 
@@ -73,14 +77,15 @@ def test_one_wave_closed_form_through_abi():
 @pytest.mark.parametrize("mode", ["cp", "balanced", "literal"])
 def test_best_ratio_matches_oracle(mode):
     rng = np.random.default_rng(11)
-    for _ in range(4):
+    for i in range(4):
         p1, p2 = rand_profile(rng, False), rand_profile(rng, True)
-        cfg = K.default_config(ratio_mode=mode)
+        bl = 0.0 if i % 2 == 0 else 6.0
+        cfg = K.default_config(ratio_mode=mode, beta_lds=bl)
         try:
             got = K.best_ratio(p1, p2, cfg)
         except K.KerneletError:
             got = None
-        ref = M.best_ratio(oracle_kprof(p1), oracle_kprof(p2), 0.0, mode)
+        ref = M.best_ratio(oracle_kprof(p1), oracle_kprof(p2), 0.0, mode, beta_lds=bl)
         if ref is None:
             assert got is None
             continue
@@ -97,13 +102,19 @@ def _types_and_jobs(seed, n_types=5, n_jobs=30, arrivals=True):
     return profs, jp, jw, ja
 
 
-@pytest.mark.parametrize("seed,prune", [(1, True), (2, False), (3, True)])
-def test_simulate_matches_oracle(seed, prune):
+@pytest.mark.parametrize("seed,prune,betas,short", [(1, True, (0.0, 0.0), 0.0),
+                                                    (2, False, (0.0, 0.0), 0.0),
+                                                    (3, True, (0.0, 0.0), 0.0),
+                                                    (4, True, (1.0, 8.0), 0.0),
+                                                    (5, False, (0.0, 0.0), 3000.0)])
+def test_simulate_matches_oracle(seed, prune, betas, short):
     profs, jp, jw, ja = _types_and_jobs(seed)
-    cfg = K.default_config(use_prune=int(prune), n_cu=256)
+    cfg = K.default_config(use_prune=int(prune), n_cu=256, beta=betas[0], beta_lds=betas[1],
+                           min_pair_slots=short)
     decs, span, done = K.simulate(profs, jp, jw, ja, "markov", cfg)
     types = {i: S.TypeInfo(oracle_kprof(p), p["pur"], p["mur"]) for i, p in enumerate(profs)}
-    ocfg = S.Config(use_prune=prune, mode="cp", n_cu=256)
+    ocfg = S.Config(use_prune=prune, mode="cp", n_cu=256, beta=betas[0], beta_lds=betas[1],
+                    min_pair_slots=short)
     jobs = [S.Job(i, jp[i], jw[i], ja[i]) for i in range(len(jp))]
     log, ospan, odone = S.simulate_kernelet(jobs, types, ocfg)
     assert len(decs) == len(log)

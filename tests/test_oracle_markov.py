@@ -12,7 +12,7 @@ from oracle import markov as M
 
 
 # ------------------------------------------------------------ brute force
-def brute_chain(kernels, waves, beta=0.0):
+def brute_chain(kernels, waves, beta=0.0, beta_lds=0.0):
     """Per-wave chain: each wave of kernel k is 0 (ready) or c+1 (stalled in
     class c).  Transitions: every ready wave independently picks a class
     with its probability (or stays ready); every stalled wave independently
@@ -25,7 +25,11 @@ def brute_chain(kernels, waves, beta=0.0):
     for s in states:
         ready = sum(1 for v in s if v == 0)
         D = max(ready, 1)
-        outst = sum(kernels[k].classes[v - 1].req for k, v in zip(owners, s) if v)
+        # requests held in each pool by the stalled waves
+        held = {0: 0.0, 1: 0.0}
+        for k, v in zip(owners, s):
+            if v:
+                held[kernels[k].classes[v - 1].pool] += kernels[k].classes[v - 1].req
         per_wave = []
         for k, v in zip(owners, s):
             cl = kernels[k].classes
@@ -34,7 +38,8 @@ def brute_chain(kernels, waves, beta=0.0):
                     (c + 1, cl[c].r) for c in range(len(cl))]
             else:
                 c = cl[v - 1]
-                lat = c.base + (beta * outst if c.req > 0 else 0.0)
+                slope = beta if c.pool == 0 else beta_lds
+                lat = c.base + (slope * held[c.pool] if c.req > 0 else 0.0)
                 q = min(1.0, D / lat)
                 opts = [(0, q), (v, 1.0 - q)]
             per_wave.append(opts)
@@ -44,8 +49,8 @@ def brute_chain(kernels, waves, beta=0.0):
     return states, owners, P
 
 
-def brute_ipc(kernels, waves, beta=0.0):
-    states, owners, P = brute_chain(kernels, waves, beta)
+def brute_ipc(kernels, waves, beta=0.0, beta_lds=0.0):
+    states, owners, P = brute_chain(kernels, waves, beta, beta_lds)
     N = len(states)
     A = P.T - np.eye(N)
     A[-1, :] = 1
@@ -190,3 +195,51 @@ def test_best_ratio_is_brute_force_argmax():
     T1s, T2s = rb[0] * 1000.0 / sa, rb[1] * 200.0 / sb
     assert abs(rb[2] - (1 - max(T1, T2) / (T1s + T2s))) < 1e-12
     assert rb[2] <= M.cp((c1, c2), (sa, sb)) + 1e-12
+
+
+# ------------------------------------------------------ contention pools
+def _pooled(rm, lm, rq, rc, lc, pool_c, req_c=1.0):
+    return M.Kernel((M.StallClass(rm, lm, rq, 0), M.StallClass(rc, lc, req_c, pool_c)))
+
+
+@pytest.mark.parametrize("beta,beta_lds", [(0.0, 3.0), (1.5, 0.0), (0.8, 5.0)])
+def test_pools_match_brute_force(beta, beta_lds):
+    a = _pooled(0.1, 40.0, 2.0, 0.2, 6.0, 1)
+    b = _pooled(0.05, 90.0, 4.0, 0.15, 3.0, 1)
+    got = M.ipc_pair(a, 2, b, 2, beta, beta_lds)
+    ref = brute_ipc([a, b], [2, 2], beta, beta_lds)
+    assert np.allclose(got, ref, rtol=0, atol=1e-12)
+    assert abs(M.ipc_homogeneous(a, 3, beta, beta_lds) - brute_ipc([a], [3], beta, beta_lds)[0]) < 1e-12
+
+
+def test_one_wave_closed_form_with_lds_pool():
+    """One wave stalled on LDS holds one request: its latency is base +
+    beta_lds, so IPC = 1 / (1 + r_m L_m + r_c (L_c + beta_lds))."""
+    k = _pooled(0.1, 50.0, 2.0, 0.2, 5.0, 1)
+    for bl in (0.0, 4.0, 30.0):
+        want = 1.0 / (1.0 + 0.1 * 50.0 + 0.2 * (5.0 + bl))
+        assert abs(M.ipc_homogeneous(k, 1, 0.0, bl) - want) < 1e-12
+
+
+def test_pools_are_separate():
+    """An LDS-bound kernel's latency does not see the HBM load: beside a
+    memory-bound partner its IPC does not depend on beta (HBM), and the
+    partner's does not depend on beta_lds; with the partner's class moved to
+    the LDS pool both see both."""
+    lds_k = M.Kernel((M.StallClass(0.2, 8.0, 1.0, 1),))
+    mem_k = M.Kernel((M.StallClass(0.2, 60.0, 4.0, 0),))
+    a = M.ipc_pair(lds_k, 3, mem_k, 3, 0.0, 2.0)
+    b = M.ipc_pair(lds_k, 3, mem_k, 3, 5.0, 2.0)
+    c = M.ipc_pair(lds_k, 3, mem_k, 3, 5.0, 0.0)
+    # HBM slope changes only the memory kernel's latency ...
+    assert b[1] < a[1]
+    # ... and the LDS slope only the LDS kernel's
+    assert c[0] > b[0]
+    # fixed latency (req 0) in the LDS pool ignores beta_lds
+    fixed = M.Kernel((M.StallClass(0.2, 8.0, 0.0, 1),))
+    assert M.ipc_homogeneous(fixed, 4, 0.0, 9.0) == M.ipc_homogeneous(fixed, 4, 0.0, 0.0)
+    # all classes in one pool, that pool's slope equal to the other: the
+    # labels do not matter
+    both0 = M.Kernel((M.StallClass(0.1, 40.0, 2.0, 0), M.StallClass(0.2, 6.0, 1.0, 0)))
+    both1 = M.Kernel((M.StallClass(0.1, 40.0, 2.0, 1), M.StallClass(0.2, 6.0, 1.0, 1)))
+    assert abs(M.ipc_homogeneous(both0, 4, 2.0, 0.0) - M.ipc_homogeneous(both1, 4, 0.0, 2.0)) < 1e-12

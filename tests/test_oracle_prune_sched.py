@@ -192,3 +192,30 @@ def test_nearest_rank_percentiles():
     assert stats.percentile(list(range(1, 101)), 0.99) == 99
     with pytest.raises(ValueError):
         stats.percentile([], 0.5)
+
+
+def test_short_jobs_are_never_paired():
+    """With a pairing threshold above every job's solo duration, every
+    decision runs one kernel alone and the makespan is FIFO's (all jobs
+    present at time 0); with a threshold that only one type's jobs fall
+    under, that type never appears in a pair."""
+    types = _types()
+    # type 3's jobs are small, the others' large
+    jobs = [sched.Job(i, i % 4, (40 + i) if i % 4 == 3 else 20000 + 700 * i) for i in range(12)]
+    cfg = sched.Config(use_prune=False, mode="cp", min_pair_slots=1e18)
+    log, span, _ = sched.simulate_kernelet(jobs, types, cfg)
+    assert all(d.j2 < 0 for d in log)
+    fspan, _ = sched.simulate_fifo(jobs, types, cfg)
+    assert abs(span - fspan) <= 1e-9 * fspan
+    model = sched.Model(types, sched.Config(use_prune=False))
+    dur = {j.id: j.wgs / model.rate(j.type, model.solo_ipc(j.type)) for j in jobs}
+    # a threshold between type 3's longest job and the shortest job of the others
+    t3 = max(d for i, d in dur.items() if jobs[i].type == 3)
+    rest = min(d for i, d in dur.items() if jobs[i].type != 3)
+    assert t3 < rest
+    cfg = sched.Config(use_prune=False, mode="cp", min_pair_slots=(t3 + rest) / 2)
+    log, _, done = sched.simulate_kernelet(jobs, types, cfg)
+    assert len(done) == len(jobs)
+    ty = {j.id: j.type for j in jobs}
+    assert all(ty[d.j1] != 3 and ty[d.j2] != 3 for d in log if d.j2 >= 0)
+    assert any(d.j2 >= 0 for d in log)

@@ -220,6 +220,9 @@ def main():
     legs = [l for l in args.legs.split(",") if l]
     main_leg = "kernelet" if "kernelet" in legs else legs[0]
     over["surrogate_topk"] = args.topk if args.topk is not None else 0
+    # contention slopes and pairing threshold the profile table was fitted with
+    for k, v in profiles.model_config(prefer_measured=not args.estimates).items():
+        over.setdefault(k, v)
     rt = K.Runtime(0, **over)
     sur_weights = None
     if args.policy == "surrogate" or "surrogate" in legs:
@@ -323,7 +326,8 @@ def main():
                    "instances_per_type": args.instances, "instances": n_inst,
                    "policy": args.policy, "parallelism": "single GPU, 2 co-execution lanes",
                    "inflight": rt.cfg.inflight, "lds_reserve": rt.cfg.lds_reserve,
-                   "cp_min": rt.cfg.cp_min,
+                   "cp_min": rt.cfg.cp_min, "beta": rt.cfg.beta, "beta_lds": rt.cfg.beta_lds,
+                   "min_pair_slots": rt.cfg.min_pair_slots,
                    "profiles": "estimates" if args.estimates else "measured",
                    "surrogate": (None if sur_weights is None else
                                  {"topk": rt.cfg.surrogate_topk,

@@ -306,6 +306,124 @@ def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict
     return prof
 
 
+def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str,
+              slices_path=None, betas=(0.0, 2.0, 4.0, 8.0), betas_lds=(0.0, 4.0, 16.0, 64.0),
+              min_pair_us: float = 50.0) -> dict:
+    """Profiles for the model with contention pools.
+
+    Instructions are counted by the issue slots they hold (an FP32 32x32x2
+    matrix instruction 16, a transcendental 4, others 1); memory
+    instructions stall in the HBM pool (requests = DRAM lines per
+    instruction), LDS instructions in the CU's LDS pool (one request per
+    stalled wave).  Each kernel's two base latencies are fitted so that the
+    model's IPC follows the kernel's measured IPC at every enforceable
+    occupancy b (solo time per launch at b from a `sweep --solo-occupancy`
+    run: IPC(b) = PUR * T(b_max) / T(b)); the global slopes (beta for HBM,
+    beta_lds for LDS) are the grid point with the least total squared log
+    error over all kernels.  Jobs predicted to finish alone within
+    min_pair_us are never paired."""
+    import math
+
+    import numpy as np
+
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import profiles
+
+    times = json.load(open(times_path))
+    occ = json.load(open(occupancy_path)).get("solo_occupancy_ms", {})
+    slices = json.load(open(slices_path))["kernels"] if slices_path else {}
+    n_cu = times["n_cu"]
+    cnt = read_counters(counter_paths)
+    cp = cnt.get("_copy", {})
+    cb = float(times.get("copy_bytes", 0))
+    f_fetch = cb / (1024.0 * cp["FETCH_SIZE"]) if cp.get("FETCH_SIZE") else 1.0
+    f_write = cb / (1024.0 * cp["WRITE_SIZE"]) if cp.get("WRITE_SIZE") else 1.0
+    est = profiles.ESTIMATES
+    base = {}
+    for name, t in times["kernels"].items():
+        c = cnt.get(name)
+        if not c or "SQ_WAVES" not in c:
+            continue
+        waves = c["SQ_WAVES"]
+        tot = sum(c.get(k, 0.0) for k in ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM",
+                                           "SQ_INSTS_SMEM", "SQ_INSTS_LDS", "SQ_INSTS_BRANCH"])
+        mf = c.get("SQ_INSTS_MFMA", 0.0)
+        tr = c.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
+        slots = tot - mf - tr + MFMA_SLOTS * mf + 4.0 * tr
+        I = slots / waves
+        T = t["avg_launch_ms"] / 1e3
+        pur = waves * I / (T * FREQ * n_cu)
+        vm = c.get("SQ_INSTS_VMEM", 0.0)
+        lds = c.get("SQ_INSTS_LDS", 0.0)
+        dram = 1024.0 * (c.get("FETCH_SIZE", 0.0) * f_fetch + c.get("WRITE_SIZE", 0.0) * f_write)
+        r_lds = lds / slots
+        p = dict(est.get(name, {}))
+        p.update(r_mem=vm / slots, mem_req=max(1.0, dram / 64.0 / vm) if vm else 1.0,
+                 r_comp=r_lds if r_lds > 1e-4 else 0.0, comp_pool=1 if r_lds > 1e-4 else 0,
+                 lat_comp=1.0, instr_per_wave=I, pur=min(pur, 1.0), mur=dram / T / PEAK_HBM,
+                 solo_ipc=pur, max_wg_per_cu=min(max(1, int(t["max_wg_per_cu"])), 8),
+                 waves_per_simd=1, vgpr=int(t["vgpr"]), lds_bytes=int(t["lds_bytes"]),
+                 solo_ms=t["avg_launch_ms"], fetch_bytes_per_launch=dram - 1024.0 *
+                 c.get("WRITE_SIZE", 0.0) * f_write,
+                 write_bytes_per_launch=1024.0 * c.get("WRITE_SIZE", 0.0) * f_write,
+                 wgs_per_launch=t["wgs_per_launch"])
+        kind = "lookup" if name.startswith("lookup") else name
+        if kind in slices:
+            p["min_slice_wgs"] = int(slices[kind]["min_slice_wgs"]) or 2147483647
+        # measured IPC at each enforceable occupancy (LDS reservation holds b
+        # only where a workgroup's reservation fits in 64 KiB)
+        curve = {p["max_wg_per_cu"]: min(pur, 0.999)}
+        o = {int(b): v for b, v in occ.get(name, {}).items()}
+        if o:
+            if p["lds_bytes"] < 16384:
+                o.pop(1, None)
+            bm = max(o)
+            curve = {b: min(pur, 0.999) * o[bm] / o[b] for b in o}
+        base[name] = (p, curve)
+
+    def fit_one(p, curve, cfg):
+        best = None
+        lm_grid = np.logspace(0, 4.3, 28)
+        lc_grid = np.logspace(0, 3.3, 16) if p["r_comp"] > 0 else [1.0]
+        for lm in lm_grid:
+            for lc in lc_grid:
+                q = dict(p, lat_mem=float(lm), lat_comp=float(lc))
+                try:
+                    e = sum((math.log(K.predict(q, None, b, 0, cfg)[0]) - math.log(v)) ** 2
+                            for b, v in curve.items())
+                except K.KerneletError:
+                    continue
+                if best is None or e < best[0]:
+                    best = (e, q)
+        return best
+
+    results = []
+    for bh in betas:
+        for bl in betas_lds:
+            cfg = K.default_config(beta=bh, beta_lds=bl)
+            fitted, err = {}, 0.0
+            for name, (p, curve) in base.items():
+                e, q = fit_one(p, curve, cfg)
+                q["model_solo_ipc"] = K.predict(q, None, q["max_wg_per_cu"], 0, cfg)[0]
+                fitted[name] = q
+                err += e
+            print(f"# beta {bh} beta_lds {bl}: occupancy fit error {err:.4f}", file=sys.stderr,
+                  flush=True)
+            results.append((err, bh, bl, fitted))
+    err, bh, bl, prof = min(results, key=lambda r: r[0])
+    meta = {"source": "calibrate.py fit_pools over solo runs at every occupancy on MI355X",
+            "times": os.path.basename(times_path), "occupancy": os.path.basename(occupancy_path),
+            "counters": [os.path.basename(x) for x in counter_paths], "freq_hz": FREQ,
+            "n_cu": n_cu, "copy_scale_fetch": f_fetch, "copy_scale_write": f_write,
+            "model": {"beta": bh, "beta_lds": bl,
+                      "min_pair_slots": min_pair_us * 1e-6 * FREQ / 4.0,
+                      "occupancy_fit_error": err,
+                      "grid": [[r[1], r[2], r[0]] for r in results]}}
+    with open(out_path, "w") as f:
+        json.dump({"meta": meta, "profiles": prof}, f, indent=1, sort_keys=True)
+    return prof
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -320,6 +438,9 @@ def main():
     f.add_argument("--counters", nargs="+", required=True)
     f.add_argument("--slices", default=None)
     f.add_argument("--out", default=os.path.join(HERE, "profiles_mi355x.json"))
+    f.add_argument("--occupancy", default=None,
+                   help="sweep JSON with solo_occupancy_ms: fit the model with contention "
+                        "pools to every kernel's IPC-vs-occupancy curve")
     a = ap.parse_args()
     if a.cmd == "run":
         t0 = time.time()
@@ -328,7 +449,10 @@ def main():
     elif a.cmd == "slices":
         run_slices(a.out, a.reps)
     else:
-        prof = fit(a.times, a.counters, a.out, a.slices)
+        if a.occupancy:
+            prof = fit_pools(a.times, a.counters, a.occupancy, a.out, a.slices)
+        else:
+            prof = fit(a.times, a.counters, a.out, a.slices)
         for k, v in prof.items():
             print(f"{k:13s} I={v['instr_per_wave']:9.1f} r_mem={v['r_mem']:.4f} "
                   f"r_comp={v['r_comp']:.4f} pur={v['pur']:.3f} mur={v['mur']:.3f} "

@@ -55,3 +55,13 @@ def load(prefer_measured: bool = True) -> dict:
         for k, v in meas.items():
             table.setdefault(k, dict(_COMMON)).update(v)
     return table
+
+
+def model_config(prefer_measured: bool = True) -> dict:
+    """Runtime configuration fields the measured table was fitted with
+    (contention slopes, pairing threshold); empty for the estimates."""
+    if prefer_measured and os.path.exists(MEASURED):
+        with open(MEASURED) as f:
+            m = json.load(f).get("meta", {}).get("model", {})
+        return {k: float(m[k]) for k in ("beta", "beta_lds", "min_pair_slots") if k in m}
+    return {}

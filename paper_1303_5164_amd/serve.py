@@ -168,7 +168,10 @@ class Server:
         return inst
 
     def runtime(self, **cfg):
+        from . import profiles
         from . import runtime as R
+        for k, v in profiles.model_config().items():
+            cfg.setdefault(k, v)
         rt = R.Runtime(self.device, **cfg)
         kids = {k: rt.register_builtin(k, self.prof[k]) for k in self.W.KERNELS}
         return rt, kids

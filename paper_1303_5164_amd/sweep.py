@@ -79,7 +79,9 @@ def main():
     params = {"stencil": dict(iters=1, c0=F["stencil"]["c0"], c1=F["stencil"]["c1"]),
               "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
     prof = profiles.load()
-    rt = K.Runtime(0, lds_reserve=a.lds_reserve)
+    mcfg = profiles.model_config()
+    rt = K.Runtime(0, lds_reserve=a.lds_reserve, **mcfg)
+    pcfg = K.default_config(**mcfg)
     n_cu = rt.cfg.n_cu
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
     launch = {}   # kind -> (kernel name, args, grid): the one launch a job makes
@@ -190,9 +192,9 @@ def main():
             sa = (na_r * solo[ka]) / max(busy[ka][0], 1e-9)
             sb = (nb_r * solo[kb]) / max(busy[kb][0], 1e-9)
             try:
-                i1, i2, _ = K.predict(pa, pb, b1, b2)
-                s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0)[0]
-                s2 = K.predict(pb, None, pb["max_wg_per_cu"], 0)[0]
+                i1, i2, _ = K.predict(pa, pb, b1, b2, pcfg)
+                s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0, pcfg)[0]
+                s2 = K.predict(pb, None, pb["max_wg_per_cu"], 0, pcfg)[0]
                 pr1, pr2 = i1 / s1, i2 / s2
                 pcp = 1.0 - 1.0 / (pr1 + pr2)
             except K.KerneletError:

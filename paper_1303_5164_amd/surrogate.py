@@ -31,6 +31,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS = os.path.join(HERE, "surrogate_mi355x.npy")
 # trained on Markov labels and on measured co-run speedups of the built-in kernels
 WEIGHTS_MEASURED = os.path.join(HERE, "surrogate_measured_mi355x.npy")
+# measured co-run speedups of the built-in kernels (a balanced sweep)
+CORUNS = os.path.join(HERE, "coruns_mi355x.json")
 
 N_IN, N_H = 16, 64
 SHAPES = [(N_IN, N_H), (N_H,), (N_H, N_H), (N_H,), (N_H, 1), (1,)]

@@ -148,9 +148,10 @@ def cpu_baseline(hosts):
 
 
 def _traffic(kernel):
-    """HBM bytes per full launch of `kernel` from the counter summary under
-    profiles/ (two rocprofv3 --pmc runs, see paper_1303_5164_amd/traffic.py),
-    or None when absent or taken from a different kernel source."""
+    """(HBM bytes, workgroups) of one full launch of `kernel` from the
+    counter summary under profiles/ (two rocprofv3 --pmc runs, see
+    paper_1303_5164_amd/traffic.py), or None when absent or taken from a
+    different kernel source."""
     from paper_1303_5164_amd import traffic
     path = os.path.join(ROOT, "profiles", "traffic_mi355x.json")
     if not os.path.exists(path):
@@ -160,7 +161,8 @@ def _traffic(kernel):
     if t.get("source_sha256") != traffic.source_hash():
         return None
     k = t.get("kernels", {}).get(kernel)
-    return float(k["bytes"]) if k else None
+    # (bytes of one counted launch, its workgroups)
+    return (float(k["bytes"]), float(k["grid_threads"]) / 256.0) if k else None
 
 
 def nearest_rank(v, q):
@@ -373,11 +375,14 @@ def main():
     roof["traffic"] = None
     tr = _traffic(dom)
     if tr is not None:
-        # HBM bytes of one full launch, per workgroup, times the timed
-        # launches' average workgroups (slices move proportionally less)
-        roof["traffic"] = round(tr / wk["wgs"] * wg / max(n, 1), 1)
+        # HBM bytes of the counted (full) launch per workgroup, times the
+        # timed launches' average workgroups (slices move proportionally less)
+        t_bytes, t_wgs = tr
+        roof["traffic"] = round(t_bytes / t_wgs * wg / max(n, 1), 1)
         roof["traffic_unit"] = "bytes/launch"
-        roof["traffic_over_algorithmic"] = round(tr / wk["bytes"], 3) if wk["bytes"] else None
+        alg = (per_wg_f if dom in ("sgemm", "poly") else per_wg_b) * wg / max(n, 1)
+        roof["traffic_over_algorithmic"] = (round(roof["traffic"] / alg, 3)
+                                            if dom not in ("sgemm", "poly") and alg else None)
     roof["kernel"] = dom
     roof["launches"] = n
     roof["avg_launch_ms"] = round(ms / max(n, 1), 5)

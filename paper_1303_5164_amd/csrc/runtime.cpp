@@ -664,6 +664,16 @@ static void decide(kl_runtime* rt, kl_policy policy) {
     log_decision(rt, d, sl[0], sl[1], us);
 }
 
+// Whether job j would finish alone within the pairing threshold (such a
+// job runs alone only because it is too short to pair, and need not hold
+// the other lanes back).
+static bool too_short_to_pair(kl_runtime* rt, const Job& j) {
+    const KernelType& kt = rt->kernels[j.type];
+    if (rt->cfg.min_pair_slots <= 0 || !kt.has_prof) return false;
+    const double rate = wg_rate(kt.prof, rt->planner->solo(j.type), rt->cfg.n_cu);
+    return rate > 0 && (double)(j.total - j.next) / rate < rt->cfg.min_pair_slots;
+}
+
 // One step of Algorithm 1: decide if needed, then fill the lanes' queues.
 static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed) {
     bool ended = !rt->cs_active;
@@ -685,11 +695,12 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
         Lane& ln = rt->lanes[li];
         if (ln.job == KL_NO_JOB) continue;
         Job& j = rt->jobs.at(ln.job);
+        const bool hold_others = solo && !(j.next == 0 && too_short_to_pair(rt, j));
         while ((int)ln.inflight.size() < rt->cfg.inflight && j.next < j.total) {
             kl_status s = launch_slice(rt, li, j.id, ln.slice);
             if (s) return s;
             *progressed = true;
-            if (solo && j.next >= j.total) {
+            if (hold_others && j.next >= j.total) {
                 // later launches on the other lanes start after this run
                 for (int o = 0; o < (int)rt->lanes.size(); ++o) {
                     if (o == li) continue;

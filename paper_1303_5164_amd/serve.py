@@ -300,6 +300,8 @@ def main():
     ap.add_argument("--base-scale", type=float, default=1.0)
     ap.add_argument("--verify-every", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--min-pair-us", type=float, default=None,
+                    help="pairing threshold (default: the profile table's)")
     a = ap.parse_args()
 
     def log(s):
@@ -315,8 +317,11 @@ def main():
            "rate_per_s": rate, "mean_service_ms": es, "base_scale": a.base_scale,
            "solo_ms": {f"{k}:{c}": v for (k, c), v in srv.solo_ms.items()}, "runs": []}
     for pol in a.policies.split(","):
+        over = {}
+        if a.min_pair_us is not None:
+            over["min_pair_slots"] = a.min_pair_us * 1e-6 * 2.4e9 / 4.0
         _, summ = srv.serve(reqs, pol, budget=a.budget_gb * (1 << 30),
-                            verify_every=a.verify_every)
+                            verify_every=a.verify_every, **over)
         log(json.dumps(summ))
         out["runs"].append(summ)
     with open(a.out, "w") as f:

@@ -345,3 +345,23 @@ def test_surrogate_alone_decides_pair_and_ratio(L):
     h.close()
     with pytest.raises(K.KerneletError):
         K.Runtime(0, lib_handle=L, n_cu=4, surrogate_topk=-1)
+
+
+def test_jobs_too_short_to_pair_run_alone_without_holding_lanes(L):
+    """With a pairing threshold above every job, each decision runs one job
+    alone; such jobs do not make the other lane wait, and every workgroup
+    still runs once, chains in order."""
+    h = Harness(L, min_pair_slots=1e12)
+    jobs = [h.job(16 + 3 * i, i, kind=i % 2, us=30) for i in range(8)]
+    c1 = h.job(24, 100, kind=0, us=30)
+    c2 = h.job(24, 101, kind=1, us=30, after=c1[0])
+    _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+    for j in jobs + [c1, c2]:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    dec = h.rt.decisions()
+    assert dec and all(d["j2"] < 0 for d in dec)
+    end = lambda j: j[2][: j[3][0], 4].max()
+    start = lambda j: j[2][: j[3][0], 3].min()
+    assert start(c2) >= end(c1)
+    h.close()

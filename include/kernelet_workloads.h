@@ -67,8 +67,8 @@ typedef struct {
 
 /* stencil: one Jacobi sweep of the 5-point stencil on an ny x nx grid:
  * interior out = c0 in + c1 ((N + S) + (W + E)), boundary cells copied.
- * nx a multiple of 4, in/out 16-byte aligned.  Tiles of 256 x 32 cells;
- * grid = (ceil(nx/256), ceil(ny/32), 1). */
+ * nx a multiple of 4, in/out 16-byte aligned.  Tiles of 1024 x 32 cells;
+ * grid = (ceil(nx/1024), ceil(ny/32), 1). */
 typedef struct {
     const float* in;
     float* out;

@@ -161,24 +161,29 @@ __global__ __launch_bounds__(KL_WG) void kl_spmv(kl_spmv_args a, kl_slice s) {
 }
 
 // --------------------------------------------------------------- stencil
-// 256 x 32 cells per workgroup.  Each wave covers 256 consecutive cells of a
-// row (four per lane, one 16-byte access) and walks 8 rows, keeping the rows
-// above and below in registers; the west / east neighbours of a lane's four
-// cells come from the adjacent lanes by shuffles, and from memory at the
-// two ends of the wave.  Original grid: (ceil(nx/256), ceil(ny/32), 1).
+// 1024 x 32 cells per workgroup.  Each wave covers 256 consecutive cells of
+// a row (four per lane, one 16-byte access) and walks the 32 rows, keeping
+// the rows above and below in registers; the west / east neighbours of a
+// lane's four cells come from the adjacent lanes by shuffles, and from
+// memory at the two ends of the wave.  Original grid: (ceil(nx/1024),
+// ceil(ny/32), 1).
 __device__ __forceinline__ float st_cell(float c0, float c1, float mid, float n, float s,
                                          float w, float e) {
     return __builtin_fmaf(c1, (n + s) + (w + e), c0 * mid);
 }
 
+// A workgroup owns 1024 x 32 cells: its four waves sit side by side, each
+// 256 columns wide (four per lane), and roll down the 32 rows, so a row's
+// west / east halo lines are fetched once per 1024 columns and its north /
+// south halo rows once per 32 rows.
 __global__ __launch_bounds__(KL_WG) void kl_stencil(kl_stencil_args a, kl_slice s) {
     const uint32_t lin = kl_wg_linear(s);
     const uint32_t bx = lin % s.gx, by = lin / s.gx;
     const int lane = threadIdx.x & 63;
     const uint32_t nx = a.nx, ny = a.ny;
-    const uint32_t x0 = bx * 256 + lane * 4;
-    const uint32_t y0 = by * 32 + (threadIdx.x >> 6) * 8;
-    if (y0 >= ny) return;                   // uniform over the wave
+    const uint32_t x0 = bx * 1024 + (threadIdx.x >> 6) * 256 + lane * 4;
+    const uint32_t y0 = by * 32;
+    if (y0 >= ny) return;                   // uniform over the workgroup
     const bool act = x0 < nx;               // nx % 4 == 0: all four cells or none
     const uint32_t xc = act ? x0 : nx - 4;  // in-range column for idle lanes' loads
     const float* __restrict__ in = a.in;
@@ -188,7 +193,7 @@ __global__ __launch_bounds__(KL_WG) void kl_stencil(kl_stencil_args a, kl_slice 
     float4 up = zero;
     if (y0 > 0) up = *(const float4*)(in + (size_t)(y0 - 1) * nx + xc);
     float4 mid = *(const float4*)(in + (size_t)y0 * nx + xc);
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < 32; ++r) {
         const uint32_t y = y0 + r;
         if (y >= ny) break;                 // uniform over the wave
         const size_t row = (size_t)y * nx;
@@ -542,7 +547,7 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         if (a.in == a.out) return "stencil in and out must differ";
         if (a.nx % 4) return "stencil nx must be a multiple of 4";
         if (!aligned16(a.in) || !aligned16(a.out)) return "stencil in, out must be 16-byte aligned";
-        g->x = cdiv(a.nx, 256);
+        g->x = cdiv(a.nx, 1024);
         g->y = cdiv(a.ny, 32);
     } else if (n == "bs") {
         KL_ARGS(kl_bs_args);

@@ -152,7 +152,7 @@ def test_builtin_descriptors_and_grids():
     a = _lib.SgemmArgs(16, 16, 16, 4096, 4096, 4096)
     assert K.builtin_grid("sgemm", a) == (1024, 1, 1)
     a = _lib.StencilArgs(16, 32, 8192, 8192, 0.5, 0.125)
-    assert K.builtin_grid("stencil", a) == (32, 256, 1)
+    assert K.builtin_grid("stencil", a) == (8, 256, 1)
     a = _lib.StencilArgs(16, 32, 10, 102, 0.5, 0.125)     # nx not a multiple of 4
     with pytest.raises(K.KerneletError):
         K.builtin_grid("stencil", a)

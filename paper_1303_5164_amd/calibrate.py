@@ -85,12 +85,23 @@ def run(out_path: str, reps: int = 3, scale: int = 1) -> dict:
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+    # its duration gives the read + write bandwidth a plain streaming kernel
+    # reaches, the practical ceiling of the HBM-bound kernels
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(5):
+        dst.copy_(src)
+    ev[1].record()
     torch.cuda.synchronize()
+    copy_ms = ev[0].elapsed_time(ev[1]) / 5
     del src, dst
     torch.cuda.empty_cache()
     rt = K.Runtime(0)
     kids = {k: rt.register_builtin(k) for k in W.KERNELS}
-    out = {"n_cu": rt.cfg.n_cu, "copy_bytes": copy_bytes, "kernels": {}}
+    out = {"n_cu": rt.cfg.n_cu, "copy_bytes": copy_bytes, "copy_ms": copy_ms,
+           "copy_gbps": 2 * copy_bytes / copy_ms / 1e6, "kernels": {}}
+    print(f"# 1 GiB copy {copy_ms:.4f} ms, {out['copy_gbps']:.0f} GB/s read + write",
+          file=sys.stderr, flush=True)
     for kind in W.TYPES:
         d_in = W.device_inputs(kind, hosts[kind], dev)
         inst = W.build(kind, d_in, params.get(kind, {}), dev)

@@ -340,6 +340,10 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup_index(kl_lookup_args a, kl_sl
     a.index[e] = v;
 }
 
+// The queries and results stream through once: nontemporal accesses keep
+// them from displacing the tree's upper levels in the caches.
+typedef uint32_t kl_u32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ uint32_t lk_count16(const uint32_t* p, uint32_t q) {
     const uint4* v = (const uint4*)p;
     uint32_t c = 0;
@@ -368,7 +372,7 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
     __syncthreads();
     const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
     if (t0 >= a.nq) return;
-    const uint4 qv = *(const uint4*)(a.q + t0);
+    const kl_u32x4 qv = __builtin_nontemporal_load((const kl_u32x4*)(a.q + t0));
     const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
     uint32_t c[4] = {0, 0, 0, 0};
     for (uint32_t st = kl_highbit(mt); st; st >>= 1)
@@ -388,8 +392,7 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
     }
     const uint32_t n = a.nkeys;
     const uint32_t* __restrict__ keys = a.keys;
-    int4 o;
-    int* op = &o.x;
+    kl_u32x4 o;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         uint32_t r = n;
@@ -403,9 +406,9 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
                 r = (uint32_t)base + cnt;
             }
         }
-        op[i] = (int)r;
+        o[i] = r;
     }
-    *(int4*)(a.out + t0) = o;
+    __builtin_nontemporal_store(o, (kl_u32x4*)(a.out + t0));
 }
 
 

@@ -17,6 +17,7 @@ The stencil runs single sweeps and the lookup its query kernel over an index
 built beforehand, so every job is one launch.
 
 Usage: python -m paper_1303_5164_amd.sweep --out gpurun_out/sweep.json
+       python -m paper_1303_5164_amd.sweep report gpurun_out/sweep.json [--occupancy OCC.json]
 """
 from __future__ import annotations
 
@@ -35,7 +36,75 @@ if ROOT not in sys.path:
 RATIOS = [(1, 7), (2, 6), (3, 5), (4, 4), (5, 3), (6, 2), (7, 1)]
 
 
+def report(sweep_path: str, occupancy_path: str | None = None) -> str:
+    """Markdown summary of a balanced sweep: the model's error over every
+    (pair, ratio) point (predicted S = sum of the predicted per-kernel
+    slowdowns), with and without the polynomial's pairs; the rank
+    correlation of the pairs' best S; per pair the measured best, the
+    model's best and the measured S at the model's choice; and the solo
+    occupancy curves of `occupancy_path` if given."""
+    import numpy as np
+    from scipy import stats as st
+
+    d = json.load(open(sweep_path))
+    rows = [r for r in d["rows"] if r["pred_rel_a"] == r["pred_rel_a"]]
+    meas = np.array([r["speedup"] for r in rows])
+    pred = np.array([r["pred_rel_a"] + r["pred_rel_b"] for r in rows])
+    nopoly = np.array(["poly" not in (r["a"], r["b"]) for r in rows])
+
+    def err(m, p):
+        return float(np.mean(np.abs(p - m) / m)), float(np.corrcoef(p, m)[0, 1])
+
+    best = {}
+    for r, pv in zip(rows, pred):
+        k = (r["a"], r["b"])
+        b = best.setdefault(k, dict(meas=None, model=None))
+        if b["meas"] is None or r["speedup"] > b["meas"]["speedup"]:
+            b["meas"] = r
+        if b["model"] is None or pv > b["model"][1]:
+            b["model"] = (r, pv)
+    keys = sorted(best, key=lambda k: -best[k]["meas"]["speedup"])
+    mb = np.array([best[k]["meas"]["speedup"] for k in keys])
+    pb = np.array([best[k]["model"][1] for k in keys])
+    npk = np.array(["poly" not in k for k in keys])
+    a_all, a_np = err(meas, pred), err(meas[nopoly], pred[nopoly])
+    out = [f"- {len(rows)} (pair, ratio) points: MAPE {a_all[0]:.3f}, Pearson r {a_all[1]:.2f}; "
+           f"without the polynomial's pairs MAPE {a_np[0]:.3f}, r {a_np[1]:.2f}.",
+           f"- Ranking of the {len(keys)} pairs by best S: Spearman "
+           f"{st.spearmanr(mb, pb)[0]:.2f} ({st.spearmanr(mb[npk], pb[npk])[0]:.2f} without "
+           "the polynomial).",
+           f"- Greedy on measured S at the model's choice: mean S "
+           f"{np.mean([best[k]['model'][0]['speedup'] for k in keys]):.3f} over the pairs "
+           f"against {np.mean(mb):.3f} at the measured best.", "",
+           "| Pair | measured best S (b1,b2) | model best S (b1,b2) | measured S at model's "
+           "choice |", "|---|---:|---:|---:|"]
+    for k in keys:
+        m, (r, pv) = best[k]["meas"], best[k]["model"]
+        out.append(f"| {k[0]} + {k[1]} | {m['speedup']:.3f} ({m['b1']}, {m['b2']}) | "
+                   f"{pv:.3f} ({r['b1']}, {r['b2']}) | {r['speedup']:.3f} |")
+    if occupancy_path:
+        occ = json.load(open(occupancy_path)).get("solo_occupancy_ms", {})
+        bs = sorted({int(b) for v in occ.values() for b in v})
+        out += ["", "Solo time per launch (ms) at occupancy b workgroups per CU, held by LDS "
+                "reservation (b = 1 is not enforceable for kernels with little static LDS: a "
+                "workgroup may reserve at most 64 KiB):", "",
+                "| Kernel | " + " | ".join(f"b={b}" for b in bs) + " |",
+                "|---|" + "---:|" * len(bs)]
+        for k, v in occ.items():
+            out.append(f"| {k} | " + " | ".join(
+                f"{v[str(b)]:.4f}" if str(b) in v else "" for b in bs) + " |")
+    return "\n".join(out)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "report":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("cmd")
+        ap.add_argument("sweep")
+        ap.add_argument("--occupancy", default=None)
+        a = ap.parse_args()
+        print(report(a.sweep, a.occupancy))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
     ap.add_argument("--window-ms", type=float, default=4.0)
@@ -51,6 +120,10 @@ def main():
     ap.add_argument("--balance", action="store_true",
                     help="re-run each co-run with work amounts set from the first run's "
                          "rates so that both kernels finish together")
+    ap.add_argument("--compact", default=None,
+                    help="also write the measured rows alone (pair, ratio, counts, S and "
+                         "per-kernel slowdowns) to this path: the co-run table the surrogate "
+                         "trains on and the OPT policy schedules with")
     a = ap.parse_args()
 
     import numpy as np
@@ -212,6 +285,13 @@ def main():
         json.dump({"n_cu": n_cu, "solo_ms": solo, "window_ms": a.window_ms,
                    "slicing": a.slicing, "lds_reserve": a.lds_reserve, "balance": a.balance,
                    "solo_occupancy_ms": solo_occ, "rows": rows}, f, indent=1)
+    if a.compact:
+        keys = ("a", "b", "b1", "b2", "na", "nb", "speedup", "rel_a", "rel_b")
+        with open(a.compact, "w") as f:
+            json.dump({"source": "python -m paper_1303_5164_amd.sweep " + " ".join(sys.argv[1:])
+                       + " (MI355X)", "n_cu": n_cu, "solo_ms": solo,
+                       "rows": [{k: (round(r[k], 5) if isinstance(r[k], float) else r[k])
+                                 for k in keys} for r in rows]}, f, indent=1)
 
 
 if __name__ == "__main__":

@@ -43,9 +43,11 @@ def parse():
     ap.add_argument("--surrogate-weights", default=None,
                     help="surrogate parameters (.npy); default: the packaged weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fifo,kernelet,surrogate",
+    ap.add_argument("--legs", default="fifo,kernelet,surrogate,opt",
                     help="fifo: one in-order stream; kernelet: --policy; surrogate: the "
-                         "surrogate network deciding (weights trained with measured co-runs)")
+                         "surrogate network deciding (weights trained with measured co-runs); "
+                         "opt: the greedy algorithm on measured co-run profits (the paper's "
+                         "OPT baseline)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
     ap.add_argument("--lds-reserve", type=int, default=None)
@@ -182,34 +184,14 @@ def main():
     import numpy as np
     import torch
 
-    import synth
     import paper_1303_5164_amd as K
     from paper_1303_5164_amd import profiles
     from paper_1303_5164_amd import workloads as W
 
     dev = torch.device("cuda:0")
     t_setup = time.perf_counter()
-    F = synth.FULL
-    hosts = {
-        "poly": synth.poly(args.seed, **F["poly"]),
-        "gather": synth.gather(args.seed, **F["gather"]),
-        "sgemm": synth.sgemm(args.seed, **F["sgemm"]),
-        "spmv": synth.spmv(args.seed, **F["spmv"]),
-        "stencil": synth.stencil(args.seed, F["stencil"]["ny"], F["stencil"]["nx"]),
-        "bs": synth.bs(args.seed, F["bs"]["n"]),
-        "hist": synth.hist(args.seed, F["hist"]["n"]),
-        "lookup": synth.lookup(args.seed, **F["lookup"]),
-    }
-    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
-                              c1=F["stencil"]["c1"]),
-              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
-    dev_in = {k: W.device_inputs(k, h, dev) for k, h in hosts.items()}
-    insts = []
-    for i in range(args.instances):
-        for k in W.TYPES:
-            insts.append(W.build(k, dev_in[k], params.get(k, {}), dev))
-    order = np.random.default_rng(args.seed).permutation(len(insts))
-    insts = [insts[i] for i in order]
+    hosts, params = W.full_hosts(args.seed)
+    insts = W.mix(hosts, params, args.instances, args.seed, dev)
     torch.cuda.synchronize()
 
     over = {}
@@ -235,6 +217,12 @@ def main():
         rt.set_surrogate(np.load(sur_weights))
     prof = profiles.load(prefer_measured=not args.estimates)
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
+    opt_rows = None
+    if "opt" in legs:
+        from paper_1303_5164_amd import surrogate
+        with open(surrogate.CORUNS) as f:
+            opt_rows = json.load(f)["rows"]
+        rt.set_pair_measures(opt_rows, kids)
     setup_s = time.perf_counter() - t_setup
 
     # algorithmic work of each kernel per instance (all its launches) and its
@@ -276,7 +264,7 @@ def main():
             jobs = [W.submit(rt, kids, inst) for inst in insts]
             torch.cuda.synchronize()
             t0 = time.monotonic_ns()
-            pol = {"fifo": "fifo", "surrogate": "surrogate"}.get(leg, args.policy)
+            pol = {"fifo": "fifo", "surrogate": "surrogate", "opt": "opt"}.get(leg, args.policy)
             rt.schedule(pol, blocking=True, wait_done=True)
             torch.cuda.synchronize()
             t1 = time.monotonic_ns()
@@ -333,7 +321,9 @@ def main():
                    "profiles": "estimates" if args.estimates else "measured",
                    "surrogate": (None if sur_weights is None else
                                  {"topk": rt.cfg.surrogate_topk,
-                                  "weights": os.path.basename(sur_weights)})},
+                                  "weights": os.path.basename(sur_weights)}),
+                   "opt_measures": (None if opt_rows is None else
+                                    {"table": "coruns_mi355x.json", "rows": len(opt_rows)})},
     }
     if "fifo" in legs:
         out["fifo_kernels_per_s"] = round(n_inst / med["fifo"], 3)
@@ -347,10 +337,11 @@ def main():
     for l, pl in pairs.items():
         name = "coschedules" if l == main_leg else f"{l}_coschedules"
         out[name] = dict(sorted(pl.items(), key=lambda kv: -kv[1]))
-    if "surrogate" in legs and main_leg != "surrogate":
-        out["surrogate_kernels_per_s"] = round(n_inst / med["surrogate"], 3)
-        if "fifo" in legs:
-            out["gain_surrogate_vs_fifo"] = round(med["fifo"] / med["surrogate"], 4)
+    for l in ("surrogate", "opt"):
+        if l in legs and main_leg != l:
+            out[f"{l}_kernels_per_s"] = round(n_inst / med[l], 3)
+            if "fifo" in legs:
+                out[f"gain_{l}_vs_fifo"] = round(med["fifo"] / med[l], 4)
 
     # roofline of the dominant kernel: all its launches in the timed region
     dom = max(W.KERNELS, key=lambda k: ktime[k][0])

@@ -106,7 +106,15 @@ typedef enum {
     KL_POLICY_MARKOV = 1,  /* Algorithm 1 driven by the Markov model */
     KL_POLICY_SURROGATE = 2, /* Algorithm 1, pairs ranked by the surrogate
                                 network, the Markov model evaluating its top k */
-    KL_POLICY_FIXED = 3    /* Algorithm 1 with explicit slice plans only */
+    KL_POLICY_FIXED = 3,   /* Algorithm 1 with explicit slice plans only */
+    KL_POLICY_OPT = 4,     /* Algorithm 1 with every pair and slice ratio
+                              measured beforehand (the paper's OPT baseline,
+                              Section 5): the pair and ratio of highest
+                              measured CP; needs kernelet_set_pair_measures */
+    KL_POLICY_RANDOM = 5   /* Algorithm 1 with the pair and slice ratio drawn
+                              at random: one sample of the paper's Monte
+                              Carlo baseline MC(s) (Section 5); draws from
+                              SplitMix64 seeded by cfg.random_seed */
 } kl_policy;
 
 #define KL_BLOCKING 1u           /* return when every pending job is launched */
@@ -145,7 +153,12 @@ typedef struct {
     int64_t hbm_budget;    /* bytes of job footprint admitted at once (0: none) */
     int32_t surrogate_topk;/* pairs the Markov model re-ranks (SURROGATE);
                               0: the surrogate's best pair and ratio as is */
-    int32_t reserved[7];
+    uint32_t random_seed;  /* KL_POLICY_RANDOM: its k-th decision (k = 0,
+                              1, ... since kernelet_init, or since the start
+                              of kernelet_simulate) takes outputs 2k and
+                              2k + 1 of the SplitMix64 stream whose state
+                              starts at this seed (0)                      */
+    int32_t reserved[6];
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this
@@ -165,6 +178,18 @@ typedef struct {
     int64_t surrogate_candidates; /* (pair, ratio) candidates scored */
     int64_t surrogate_pairs;    /* pairs ranked by the surrogate */
 } kl_stats;
+
+/* One measured co-run (KL_POLICY_OPT): kernel a at b1 workgroups per CU
+ * beside kernel b at b2, and each kernel's rate in the co-run relative to
+ * its rate alone (cIPC / IPC, Eq. 1), so that the measured weighted speedup
+ * is rel_a + rel_b and CP = 1 - 1 / (rel_a + rel_b).  a and b are kl_kernel
+ * handles (kernelet_set_pair_measures) or profile indices
+ * (kernelet_simulate). */
+typedef struct {
+    int32_t a, b;
+    int32_t b1, b2;
+    double rel_a, rel_b;
+} kl_pair_measure;
 
 /* One scheduling decision, as logged (Algorithm 1, one co-schedule). */
 typedef struct {
@@ -320,12 +345,17 @@ kl_status kernelet_best_ratio(const kl_config* cfg, const kl_profile* p1,
  * Algorithm 1 (or FIFO if policy == KL_POLICY_FIFO) over n jobs given by
  * kernel profile index, workgroup count and arrival time; writes up to
  * max_dec decisions (j1/j2 are job indices), their count, the makespan and
- * each job's completion time (host arrays of n).  Used to test the
- * scheduler against the oracle and to predict a plan's gain. */
+ * each job's completion time (host arrays of n).  KL_POLICY_OPT takes its
+ * pairs, ratios and co-run rates from `measures` (n_measures rows whose a
+ * and b are profile indices; may be NULL otherwise); every other policy
+ * takes co-run rates from the model.  Used to test the scheduler against
+ * the oracle and to predict a plan's gain.  KL_EINVAL for a policy other
+ * than FIFO, MARKOV, OPT and RANDOM or a measure naming no profile. */
 kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
                             int32_t n_profiles, const int32_t* job_profile,
                             const uint64_t* job_wgs, const double* job_arrival,
                             int32_t n_jobs, kl_policy policy,
+                            const kl_pair_measure* measures, uint32_t n_measures,
                             kl_decision* decisions, int32_t max_dec,
                             int32_t* n_dec, double* makespan, double* done);
 
@@ -347,6 +377,16 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
  * 4.3 with the model of Section 4.4 as the judge).  Errors: KL_EINVAL,
  * KL_EHIP. */
 kl_status kernelet_set_surrogate(kl_runtime* rt, const float* params, uint32_t n_params);
+
+/* Load measured co-runs (host array of n rows, copied; a and b are kl_kernel
+ * handles of this runtime) for KL_POLICY_OPT, replacing earlier ones.  A row
+ * for (a at b1, b at b2) also serves the pair in the other order.  Under
+ * OPT each decision takes, over the pairs of pending kernel types with
+ * rows, the ratio of highest measured CP = 1 - 1 / (rel_a + rel_b), and the
+ * pair of highest such CP if it exceeds cfg.cp_min (else the earliest job
+ * alone).  Errors: KL_EINVAL (unknown kernel, a == b, b1 or b2 outside
+ * 1..8, a rate not positive). */
+kl_status kernelet_set_pair_measures(kl_runtime* rt, const kl_pair_measure* rows, uint32_t n);
 
 /* The 16 input features of a candidate (kernel a at b1, kernel b at b2
  * workgroups per CU; host arrays): per kernel the memory-instruction ratio

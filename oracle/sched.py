@@ -1,7 +1,10 @@
 """CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
 
 Greedy co-scheduling (Kernelet, Section 4.2 "Scheduling", Algorithm 1 and
-procedure FindCoSchedule) and the FIFO baseline, on a virtual clock.
+procedure FindCoSchedule) and the FIFO baseline, on a virtual clock; and
+the two baselines of the evaluation (Section 5) that share the greedy
+algorithm: OPT (profits measured, not predicted) and one sample of the
+Monte Carlo method MC(s) (pair and slice ratio drawn at random).
 
 FindCoSchedule(R):
   1. candidate space: pairs of pending kernels (one representative per
@@ -63,6 +66,7 @@ class Config:
     min_pair_slots: float = 0.0
     mode: str = "cp"
     cp_min: float = 0.0
+    random_seed: int = 0
     wmax: int = 8
     vgpr_file: int = 512
     lds_cu: int = 160 * 1024
@@ -109,7 +113,10 @@ class Model:
         return self.cfg.n_cu * ipc / (p.wave_per_wg * p.instr_per_wave)
 
 
-def find_coschedule(pending, model: Model) -> Decision:
+def _candidates(pending, model: Model):
+    """Step 1 of FindCoSchedule: the earliest pending job of each type (by
+    submission), less the jobs too short to pair; and the decision to run
+    the earliest pending job alone."""
     cfg = model.cfg
     reps = {}
     for j in sorted(pending, key=lambda j: j.id):
@@ -122,6 +129,12 @@ def find_coschedule(pending, model: Model) -> Decision:
         # a job that would finish alone within min_pair_slots is never paired
         order = [j for j in order
                  if not (j.rem / model.rate(j.type, model.solo_ipc(j.type)) < cfg.min_pair_slots)]
+    return order, solo
+
+
+def find_coschedule(pending, model: Model) -> Decision:
+    cfg = model.cfg
+    order, solo = _candidates(pending, model)
     if len(order) < 2:
         return solo
     pairs = [(a, b) for ia, a in enumerate(order) for b in order[ia + 1:]]
@@ -143,13 +156,101 @@ def find_coschedule(pending, model: Model) -> Decision:
     return best
 
 
+@dataclass(frozen=True)
+class Measure:
+    """A measured co-run: type a at b1 workgroups per CU beside type b at
+    b2, and each one's co-run rate over its rate alone (cIPC / IPC)."""
+    a: int
+    b: int
+    b1: int
+    b2: int
+    rel_a: float
+    rel_b: float
+
+
+def find_opt(pending, model: Model, measures) -> Decision:
+    """The OPT baseline of the evaluation (Section 5): the greedy algorithm
+    with the profit of every pair and slice ratio measured beforehand
+    instead of predicted.  Over the candidate pairs (submission order) and,
+    for each, the measured rows in the order given (a row for (b, a) read
+    with its roles swapped), the largest CP = 1 - 1 / (rel_a + rel_b) (Eq. 1
+    with measured rates); the first maximum wins.  No pruning: nothing is
+    left to save.  Co-run IPCs: measured rate times the model's solo IPC."""
+    order, solo = _candidates(pending, model)
+    if len(order) < 2:
+        return solo
+    best = None
+    for ia, a in enumerate(order):
+        for b in order[ia + 1:]:
+            for r in measures:
+                if (r.a, r.b) == (a.type, b.type):
+                    b1, b2, ra, rb = r.b1, r.b2, r.rel_a, r.rel_b
+                elif (r.a, r.b) == (b.type, a.type):
+                    b1, b2, ra, rb = r.b2, r.b1, r.rel_b, r.rel_a
+                else:
+                    continue
+                v = 1.0 - 1.0 / (ra + rb)
+                if best is None or v > best.value:
+                    best = Decision(a.id, b.id, b1, b2, v, ra * model.solo_ipc(a.type),
+                                    rb * model.solo_ipc(b.type))
+    if best is None or best.value <= model.cfg.cp_min:
+        return solo
+    return best
+
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(seed: int, i: int) -> int:
+    """Output i (from 0) of SplitMix64 (Steele, Lea and Flood, "Fast
+    splittable pseudorandom number generators", OOPSLA 2014) whose state
+    starts at `seed`: the state grows by the odd 64-bit constant nearest
+    2^64 / golden ratio before each output, and the output is that state
+    after two xor-shift-multiply rounds and a last xor-shift."""
+    z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def find_random(pending, model: Model, r_pair: int, r_ratio: int) -> Decision:
+    """One sample of the Monte Carlo baseline MC(s) of the evaluation
+    (Section 5): a random kernel pair at a random slice ratio.  Candidates
+    as in FindCoSchedule; among the pairs (submission order) that have a
+    feasible ratio, pair r_pair mod their count; among its feasible ratios
+    (b1 major, ascending), ratio r_ratio mod their count.  IPCs and CP from
+    the model.  Alone only when no pair has a feasible ratio."""
+    cfg = model.cfg
+    order, solo = _candidates(pending, model)
+    if len(order) < 2:
+        return solo
+    kw = dict(wmax=cfg.wmax, vgpr_file=cfg.vgpr_file, lds_cu=cfg.lds_cu)
+    prof = lambda j: model.types[j.type].prof
+    pairs = [(a, b) for ia, a in enumerate(order) for b in order[ia + 1:]
+             if markov.feasible_ratios(prof(a), prof(b), **kw)]
+    if not pairs:
+        return solo
+    a, b = pairs[r_pair % len(pairs)]
+    pa, pb = prof(a), prof(b)
+    rats = markov.feasible_ratios(pa, pb, **kw)
+    b1, b2 = rats[r_ratio % len(rats)]
+    c1, c2 = markov.ipc_pair(pa.kernel, b1 * pa.wave_per_wg, pb.kernel, b2 * pb.wave_per_wg,
+                             cfg.beta, cfg.beta_lds)
+    v = markov.cp((c1, c2), (model.solo_ipc(a.type), model.solo_ipc(b.type)))
+    return Decision(a.id, b.id, b1, b2, v, c1, c2)
+
+
 EPS_WG = 1e-6   # residual workgroups below this count as finished
 
 
-def simulate_kernelet(jobs, types, cfg: Config):
+def simulate_kernelet(jobs, types, cfg: Config, policy="markov", measures=()):
     """Algorithm 1 on the virtual clock.  Returns (decision log, makespan,
-    completion time per job id)."""
+    completion time per job id).  policy "markov": FindCoSchedule; "opt":
+    find_opt over `measures`; "random": find_random, the k-th decision
+    taking SplitMix64 outputs 2k and 2k + 1 of the stream seeded by
+    cfg.random_seed."""
     model = Model(types, cfg)
+    draws = 0
     jobs = [Job(j.id, j.type, j.wgs, j.arrival) for j in jobs]
     byid = {j.id: j for j in jobs}
     t, log, done = 0.0, [], {}
@@ -158,7 +259,14 @@ def simulate_kernelet(jobs, types, cfg: Config):
         if not pend:
             t = min(j.arrival for j in jobs if j.id not in done)
             continue
-        d = find_coschedule(pend, model)
+        if policy == "opt":
+            d = find_opt(pend, model, measures)
+        elif policy == "random":
+            d = find_random(pend, model, splitmix64(cfg.random_seed, 2 * draws),
+                            splitmix64(cfg.random_seed, 2 * draws + 1))
+            draws += 1
+        else:
+            d = find_coschedule(pend, model)
         log.append(d)
         j1 = byid[d.j1]
         if d.j2 < 0:

@@ -14,7 +14,7 @@ ERRORS = {-1: "KL_EINVAL", -2: "KL_ENOMEM", -3: "KL_EEXIST", -4: "KL_ENOTFOUND",
           -9: "KL_EINTERNAL"}
 KL_NO_JOB = -1
 
-POLICY = {"fifo": 0, "markov": 1, "surrogate": 2, "fixed": 3}
+POLICY = {"fifo": 0, "markov": 1, "surrogate": 2, "fixed": 3, "opt": 4, "random": 5}
 KL_BLOCKING = 1
 KL_REPLAN_ON_ARRIVAL = 2
 KL_WAIT_DONE = 4
@@ -51,7 +51,8 @@ class Config(C.Structure):
                 ("beta", C.c_double), ("lanes", C.c_int32), ("inflight", C.c_int32),
                 ("lds_reserve", C.c_int32), ("max_slices", C.c_int32),
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
-                ("reserved", C.c_int32 * 7), ("beta_lds", C.c_double),
+                ("random_seed", C.c_uint32), ("reserved", C.c_int32 * 6),
+                ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 
 
@@ -62,6 +63,11 @@ class Stats(C.Structure):
                 ("cache_hits", C.c_int64), ("resident_bytes", C.c_int64),
                 ("resident_peak", C.c_int64), ("surrogate_us_total", C.c_double),
                 ("surrogate_candidates", C.c_int64), ("surrogate_pairs", C.c_int64)]
+
+
+class PairMeasure(C.Structure):
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("b1", C.c_int32), ("b2", C.c_int32),
+                ("rel_a", C.c_double), ("rel_b", C.c_double)]
 
 
 class Decision(C.Structure):
@@ -145,6 +151,7 @@ SYMBOLS = [
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
     "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
+    "kernelet_set_pair_measures",
 ]
 
 _lib = None
@@ -202,6 +209,7 @@ def configure(L):
                                 C.POINTER(i32), C.POINTER(i32), PD, PD, PD],
         "kernelet_simulate": [C.POINTER(Config), C.POINTER(Profile), i32,
                               C.POINTER(i32), C.POINTER(u64), PD, i32, C.c_int,
+                              C.POINTER(PairMeasure), u32,
                               C.POINTER(Decision), i32, C.POINTER(i32), PD, PD],
         "kernelet_stats": [C.c_void_p, C.POINTER(Stats)],
         "kernelet_decisions": [C.c_void_p, C.POINTER(Decision), i32, C.POINTER(i32)],
@@ -210,6 +218,7 @@ def configure(L):
                                  C.POINTER(i32)],
         "kernelet_kernel_time": [C.c_void_p, i32, PD, C.POINTER(i64), C.POINTER(i64)],
         "kernelet_set_surrogate": [C.c_void_p, C.c_void_p, u32],
+        "kernelet_set_pair_measures": [C.c_void_p, C.POINTER(PairMeasure), u32],
         "kernelet_surrogate_features": [C.POINTER(Config), C.POINTER(Profile),
                                         C.POINTER(Profile), i32, i32, C.c_void_p],
     }

@@ -349,26 +349,23 @@ Decision Planner::find_ranked(const std::vector<PendingJob>& pending, int k,
     return search(pending, nullptr, k, &score);
 }
 
-Decision Planner::search(const std::vector<PendingJob>& pending,
-                         const std::vector<std::pair<int, int>>* only_pairs, int k,
-                         const Scorer* score) {
-    std::lock_guard<std::mutex> g(mu_);
-    Decision solo_d;
-    if (pending.empty()) return solo_d;
+bool Planner::candidates(const std::vector<PendingJob>& pending, std::vector<PendingJob>* out,
+                         Decision* solo_d) {
     std::vector<PendingJob> v(pending);
     std::sort(v.begin(), v.end(),
               [](const PendingJob& a, const PendingJob& b) { return a.id < b.id; });
-    std::vector<PendingJob> order;  // earliest job of each type, by id
+    std::vector<PendingJob>& order = *out;  // earliest job of each type, by id
+    order.clear();
     for (const auto& j : v) {
         bool seen = false;
         for (const auto& o : order) seen |= o.type == j.type;
         if (!seen) order.push_back(j);
     }
     const PendingJob first = order[0];
-    solo_d.j1 = first.id;
-    solo_d.j2 = -1;
-    solo_d.b1 = types_[first.type].max_wg_per_cu;
-    solo_d.cipc1 = solo(first.type);
+    solo_d->j1 = first.id;
+    solo_d->j2 = -1;
+    solo_d->b1 = types_[first.type].max_wg_per_cu;
+    solo_d->cipc1 = solo(first.type);
     if (cfg_.min_pair_slots > 0) {
         // a job that would finish alone within min_pair_slots issue slots is
         // not worth a co-schedule: it only runs alone
@@ -379,7 +376,97 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
         }
         order.swap(keep);
     }
-    if (order.size() < 2) return solo_d;
+    return order.size() >= 2;
+}
+
+void Planner::set_measures(const std::map<std::pair<int, int>, std::vector<Measure>>& m) {
+    std::lock_guard<std::mutex> g(mu_);
+    meas_ = m;
+}
+
+Decision Planner::find_opt(const std::vector<PendingJob>& pending) {
+    std::lock_guard<std::mutex> g(mu_);
+    Decision solo_d;
+    if (pending.empty()) return solo_d;
+    std::vector<PendingJob> order;
+    if (!candidates(pending, &order, &solo_d)) return solo_d;
+    Decision best;
+    bool have = false;
+    for (size_t x = 0; x < order.size(); ++x)
+        for (size_t y = x + 1; y < order.size(); ++y) {
+            auto it = meas_.find({order[x].type, order[y].type});
+            if (it == meas_.end()) continue;
+            for (const Measure& m : it->second) {
+                const double cp = 1.0 - 1.0 / (m.rel1 + m.rel2);
+                if (have && !(cp > best.value)) continue;
+                have = true;
+                best.j1 = order[x].id;
+                best.j2 = order[y].id;
+                best.b1 = m.b1;
+                best.b2 = m.b2;
+                best.value = cp;
+                best.cipc1 = m.rel1 * solo(order[x].type);
+                best.cipc2 = m.rel2 * solo(order[y].type);
+            }
+        }
+    if (!have || best.value <= cfg_.cp_min) return solo_d;
+    return best;
+}
+
+Decision Planner::find_random(const std::vector<PendingJob>& pending, uint64_t r_pair,
+                              uint64_t r_ratio) {
+    std::lock_guard<std::mutex> g(mu_);
+    Decision solo_d;
+    if (pending.empty()) return solo_d;
+    std::vector<PendingJob> order;
+    if (!candidates(pending, &order, &solo_d)) return solo_d;
+    auto ratios = [&](const kl_profile& p1, const kl_profile& p2) {
+        std::vector<std::pair<int, int>> r;
+        for (int b1 = 1; b1 <= p1.max_wg_per_cu; ++b1)
+            for (int b2 = 1; b2 <= p2.max_wg_per_cu; ++b2)
+                if (ratio_feasible(p1, p2, cfg_, b1, b2)) r.emplace_back(b1, b2);
+        return r;
+    };
+    std::vector<std::pair<size_t, size_t>> pairs;
+    for (size_t x = 0; x < order.size(); ++x)
+        for (size_t y = x + 1; y < order.size(); ++y)
+            if (!ratios(types_[order[x].type], types_[order[y].type]).empty())
+                pairs.emplace_back(x, y);
+    if (pairs.empty()) return solo_d;
+    const auto pr = pairs[r_pair % pairs.size()];
+    const PendingJob& a = order[pr.first];
+    const PendingJob& b = order[pr.second];
+    const kl_profile& p1 = types_[a.type];
+    const kl_profile& p2 = types_[b.type];
+    const auto rat = ratios(p1, p2);
+    const auto br = rat[r_ratio % rat.size()];
+    auto t0 = std::chrono::steady_clock::now();
+    KernelModel km[2] = {kernel_model(p1, cfg_), kernel_model(p2, cfg_)};
+    int w[2] = {br.first * p1.waves_per_simd, br.second * p2.waves_per_simd};
+    double c[2];
+    chain_ipc(km, w, 2, cfg_.beta, cfg_.beta_lds, c);
+    model_us += std::chrono::duration<double, std::micro>(
+                    std::chrono::steady_clock::now() - t0).count();
+    double s[2] = {solo(a.type), solo(b.type)};
+    Decision d;
+    d.j1 = a.id;
+    d.j2 = b.id;
+    d.b1 = br.first;
+    d.b2 = br.second;
+    d.value = cp_value(c, s, 2);
+    d.cipc1 = c[0];
+    d.cipc2 = c[1];
+    return d;
+}
+
+Decision Planner::search(const std::vector<PendingJob>& pending,
+                         const std::vector<std::pair<int, int>>* only_pairs, int k,
+                         const Scorer* score) {
+    std::lock_guard<std::mutex> g(mu_);
+    Decision solo_d;
+    if (pending.empty()) return solo_d;
+    std::vector<PendingJob> order;
+    if (!candidates(pending, &order, &solo_d)) return solo_d;
 
     const int n = (int)order.size();
     std::vector<std::pair<int, int>> pairs;

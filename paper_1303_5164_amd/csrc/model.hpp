@@ -75,6 +75,13 @@ struct PendingJob {
     double wgs = 0.0;  // workgroups still to run
 };
 
+// A measured co-run of two kernel types: the first at b1 workgroups per CU
+// beside the second at b2, and each one's co-run rate over its rate alone.
+struct Measure {
+    int b1 = 0, b2 = 0;
+    double rel1 = 0, rel2 = 0;
+};
+
 struct Decision {
     int64_t j1 = -1, j2 = -1;  // j2 = -1: solo
     int b1 = 0, b2 = 0;
@@ -107,6 +114,22 @@ class Planner {
     Decision find_ranked(const std::vector<PendingJob>& pending, int k, const Scorer& score);
     // Forget cached surrogate scores (new network parameters).
     void clear_scores();
+    // Measured co-runs per ordered type pair (every row kept in both orders,
+    // in the order given), for find_opt.
+    void set_measures(const std::map<std::pair<int, int>, std::vector<Measure>>& m);
+    // FindCoSchedule on measured CP (the paper's OPT baseline): over the
+    // pairs of the candidates with measurements, the pair and ratio of
+    // highest CP = 1 - 1/(rel1 + rel2) (first found on ties, pairs in
+    // submission order); kept when CP exceeds cp_min.  Co-run IPCs are the
+    // measured rates times the model's solo IPCs.  No pruning.
+    Decision find_opt(const std::vector<PendingJob>& pending);
+    // One random co-schedule (a sample of the paper's Monte Carlo baseline):
+    // among the candidate pairs with a feasible ratio (in submission order),
+    // pair r_pair mod their number; among its feasible ratios (b1 major,
+    // ascending), ratio r_ratio mod their number; co-run IPCs and CP from
+    // the model.  Alone only when no pair has a feasible ratio.
+    Decision find_random(const std::vector<PendingJob>& pending, uint64_t r_pair,
+                         uint64_t r_ratio);
     int64_t scored_pairs = 0;
     const kl_profile& prof(int t) const { return types_[t]; }
     int ntypes() const { return (int)types_.size(); }
@@ -114,6 +137,11 @@ class Planner {
     int64_t cache_hits = 0;
 
   private:
+    // The earliest pending job of each type (submission order) that is not
+    // too short to pair, and the decision to run the earliest job alone;
+    // false when fewer than two such types are pending.
+    bool candidates(const std::vector<PendingJob>& pending, std::vector<PendingJob>* order,
+                    Decision* solo_d);
     Decision search(const std::vector<PendingJob>& pending,
                     const std::vector<std::pair<int, int>>* only_pairs, int k,
                     const Scorer* score);
@@ -123,6 +151,7 @@ class Planner {
     std::map<std::pair<int, int>, Ratio> pair_;
     // surrogate score and best ratio per ordered type pair
     std::map<std::pair<int, int>, std::pair<double, std::pair<int, int>>> scored_;
+    std::map<std::pair<int, int>, std::vector<Measure>> meas_;
     std::mutex mu_;
 };
 

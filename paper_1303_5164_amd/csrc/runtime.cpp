@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <set>
 #include <cstring>
@@ -182,6 +183,9 @@ struct kl_runtime {
     float* sur_hy = nullptr;
     uint32_t sur_cap = 0;
     hipStream_t sur_stream = nullptr;
+    // OPT: measured co-runs were loaded; RANDOM: decisions drawn so far
+    bool have_measures = false;
+    uint64_t random_draws = 0;
 };
 
 namespace kl {
@@ -556,6 +560,16 @@ static bool surrogate_scores(
 }
 
 // Choose the next co-schedule (FindCoSchedule) and bind it to lanes.
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): output i of the stream whose state starts at
+// `seed` mixes the state after i + 1 steps of the golden-ratio increment.
+static uint64_t splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 static void decide(kl_runtime* rt, kl_policy policy) {
     std::vector<PendingJob> pend;
     for (kl_job id : rt->live) {
@@ -595,6 +609,12 @@ static void decide(kl_runtime* rt, kl_policy policy) {
                  std::vector<double>* sc, std::vector<std::pair<int, int>>* rat) {
                 return surrogate_scores(rt, pp, sc, rat);
             });
+    } else if (policy == KL_POLICY_OPT) {
+        d = rt->planner->find_opt(pend);
+    } else if (policy == KL_POLICY_RANDOM) {
+        const uint64_t k = rt->random_draws++;
+        d = rt->planner->find_random(pend, splitmix64(rt->cfg.random_seed, 2 * k),
+                                     splitmix64(rt->cfg.random_seed, 2 * k + 1));
     } else {
         d = rt->planner->find(pend);
     }
@@ -1140,7 +1160,7 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
         set_error("null runtime");
         return KL_EINVAL;
     }
-    if (policy < KL_POLICY_FIFO || policy > KL_POLICY_FIXED) {
+    if (policy < KL_POLICY_FIFO || policy > KL_POLICY_RANDOM) {
         set_error("kernelet_schedule: unknown policy");
         return KL_EINVAL;
     }
@@ -1152,6 +1172,10 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
         }
         if (policy == KL_POLICY_SURROGATE && !rt->sur_params) {
             set_error("kernelet_schedule: the surrogate policy needs kernelet_set_surrogate");
+            return KL_ESTATE;
+        }
+        if (policy == KL_POLICY_OPT && !rt->have_measures) {
+            set_error("kernelet_schedule: the OPT policy needs kernelet_set_pair_measures");
             return KL_ESTATE;
         }
         if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED) {
@@ -1400,6 +1424,40 @@ kl_status kernelet_set_surrogate(kl_runtime* rt, const float* params, uint32_t n
     return KL_OK;
 }
 
+// Measured co-runs by ordered type pair, each row in both orders; false
+// (with the error set) for a row naming no type, one type twice, a ratio
+// outside 1..8 or a rate that is not positive.
+static bool measure_map(const kl_pair_measure* rows, uint32_t n, int ntypes, const char* who,
+                        std::map<std::pair<int, int>, std::vector<Measure>>* out) {
+    out->clear();
+    for (uint32_t i = 0; i < n; ++i) {
+        const kl_pair_measure& r = rows[i];
+        if (r.a < 0 || r.b < 0 || r.a >= ntypes || r.b >= ntypes || r.a == r.b ||
+            r.b1 < 1 || r.b1 > 8 || r.b2 < 1 || r.b2 > 8 || !(r.rel_a > 0) || !(r.rel_b > 0) ||
+            !std::isfinite(r.rel_a) || !std::isfinite(r.rel_b)) {
+            set_error(std::string(who) + ": bad measure row " + std::to_string(i));
+            return false;
+        }
+        (*out)[{r.a, r.b}].push_back({r.b1, r.b2, r.rel_a, r.rel_b});
+        (*out)[{r.b, r.a}].push_back({r.b2, r.b1, r.rel_b, r.rel_a});
+    }
+    return true;
+}
+
+kl_status kernelet_set_pair_measures(kl_runtime* rt, const kl_pair_measure* rows, uint32_t n) {
+    if (!rt || (n > 0 && !rows)) {
+        set_error("kernelet_set_pair_measures: null argument");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    std::map<std::pair<int, int>, std::vector<Measure>> m;
+    if (!measure_map(rows, n, (int)rt->kernels.size(), "kernelet_set_pair_measures", &m))
+        return KL_EINVAL;
+    rt->planner->set_measures(m);
+    rt->have_measures = true;
+    return KL_OK;
+}
+
 kl_status kernelet_surrogate_features(const kl_config* cfg, const kl_profile* a,
                                       const kl_profile* b, int32_t b1, int32_t b2,
                                       float* out16) {
@@ -1497,11 +1555,18 @@ kl_status kernelet_best_ratio(const kl_config* cfg, const kl_profile* p1, const 
 kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
                             int32_t n_profiles, const int32_t* job_profile,
                             const uint64_t* job_wgs, const double* job_arrival,
-                            int32_t n_jobs, kl_policy policy, kl_decision* dec,
-                            int32_t max_dec, int32_t* n_dec, double* makespan, double* done) {
+                            int32_t n_jobs, kl_policy policy,
+                            const kl_pair_measure* measures, uint32_t n_measures,
+                            kl_decision* dec, int32_t max_dec, int32_t* n_dec,
+                            double* makespan, double* done) {
     if (!profiles || n_profiles < 1 || !job_profile || !job_wgs || n_jobs < 0 ||
-        (n_jobs > 0 && !done) || !makespan) {
+        (n_jobs > 0 && !done) || !makespan || (n_measures > 0 && !measures)) {
         set_error("kernelet_simulate: null argument");
+        return KL_EINVAL;
+    }
+    if (policy != KL_POLICY_FIFO && policy != KL_POLICY_MARKOV && policy != KL_POLICY_OPT &&
+        policy != KL_POLICY_RANDOM) {
+        set_error("kernelet_simulate: policy must be FIFO, MARKOV, OPT or RANDOM");
         return KL_EINVAL;
     }
     kl_config c = cfg ? *cfg : defaults();
@@ -1517,6 +1582,13 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
         }
     Planner pl(c);
     pl.set_types(types);
+    if (policy == KL_POLICY_OPT) {
+        std::map<std::pair<int, int>, std::vector<Measure>> m;
+        if (!measure_map(measures, n_measures, n_profiles, "kernelet_simulate", &m))
+            return KL_EINVAL;
+        pl.set_measures(m);
+    }
+    uint64_t draws = 0;
     auto arrival = [&](int i) { return job_arrival ? job_arrival[i] : 0.0; };
     int nd = 0;
     double t = 0.0;
@@ -1547,7 +1619,16 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
             t = nt;
             continue;
         }
-        Decision d = pl.find(pend);
+        Decision d;
+        if (policy == KL_POLICY_OPT) {
+            d = pl.find_opt(pend);
+        } else if (policy == KL_POLICY_RANDOM) {
+            d = pl.find_random(pend, splitmix64(c.random_seed, 2 * draws),
+                               splitmix64(c.random_seed, 2 * draws + 1));
+            ++draws;
+        } else {
+            d = pl.find(pend);
+        }
         if (dec && nd < max_dec) {
             kl_decision& x = dec[nd];
             x = kl_decision{};

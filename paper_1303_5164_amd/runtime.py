@@ -6,7 +6,8 @@ from __future__ import annotations
 import ctypes as C
 
 from . import _lib
-from ._lib import (Config, Decision, Dim3, KernelDesc, Profile, Stats, call, lib)
+from ._lib import (Config, Decision, Dim3, KernelDesc, PairMeasure, Profile, Stats, call,
+                   lib)
 
 PROFILE_FIELDS = [f for f, _ in Profile._fields_ if f != "reserved"]
 CONFIG_FIELDS = [f for f, _ in Config._fields_ if f != "reserved"]
@@ -69,9 +70,21 @@ def best_ratio(p1, p2, cfg: Config | None = None):
     return b1.value, b2.value, v.value, c1.value, c2.value
 
 
+def pair_measures(rows, index=None):
+    """ctypes array of kl_pair_measure from dicts with a, b, b1, b2, rel_a,
+    rel_b; `index` maps a and b to kernel handles or profile indices (if
+    they are names)."""
+    arr = (PairMeasure * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        a, b = (index[r["a"]], index[r["b"]]) if index is not None else (r["a"], r["b"])
+        arr[i] = PairMeasure(a, b, r["b1"], r["b2"], r["rel_a"], r["rel_b"])
+    return arr
+
+
 def simulate(profiles, job_profile, job_wgs, job_arrival=None, policy="markov",
-             cfg: Config | None = None, max_dec=100000):
-    """Algorithm 1 (or FIFO) on the model's virtual clock; no GPU needed."""
+             cfg: Config | None = None, max_dec=100000, measures=None):
+    """Algorithm 1 (or FIFO) on the model's virtual clock; no GPU needed.
+    `measures` (policy "opt"): rows with a, b as profile indices."""
     n = len(job_profile)
     P = (Profile * len(profiles))(*[make_profile(p) for p in profiles])
     jp = (C.c_int32 * n)(*job_profile)
@@ -81,8 +94,11 @@ def simulate(profiles, job_profile, job_wgs, job_arrival=None, policy="markov",
     nd = C.c_int32()
     span = C.c_double()
     done = (C.c_double * max(n, 1))()
+    rows = list(measures or [])
+    m = pair_measures(rows) if rows else None
     call("kernelet_simulate", C.byref(cfg) if cfg else None, P, len(profiles), jp, jw, ja,
-         n, _lib.POLICY[policy], dec, max_dec, C.byref(nd), C.byref(span), done)
+         n, _lib.POLICY[policy], m, len(rows), dec, max_dec, C.byref(nd), C.byref(span),
+         done)
     decs = [_dec_dict(dec[i]) for i in range(min(nd.value, max_dec))]
     return decs, span.value, list(done)[:n]
 
@@ -150,6 +166,12 @@ class Runtime:
         import numpy as np
         p = np.ascontiguousarray(params, dtype=np.float32)
         self._c("kernelet_set_surrogate", self.h, p.ctypes.data, p.size)
+
+    def set_pair_measures(self, rows, kids=None) -> None:
+        """Load measured co-runs for the OPT policy: dicts with a, b (kernel
+        handles, or names looked up in `kids`), b1, b2, rel_a, rel_b."""
+        arr = pair_measures(rows, kids)
+        self._c("kernelet_set_pair_measures", self.h, arr, len(rows))
 
     # ----------------------------------------------------------------- jobs
     def submit(self, k: int, grid, args, after: int = -1, client: int = 0,

@@ -147,3 +147,37 @@ def submit(rt, kernel_ids: dict, inst: Instance, client: int = 0, after: int = -
     return rt.submit_chain([(kernel_ids[ln.kernel or inst.kind], ln.grid, ln.args)
                             for ln in inst.launches], after=after, client=client,
                            footprint=inst.footprint)
+
+
+def full_hosts(seed: int = 0) -> tuple:
+    """Seeded host inputs of the eight kernels at their full sizes and the
+    per-kind parameters (stencil sweeps and coefficients, Black-Scholes rate
+    and volatility)."""
+    import synth
+    F = synth.FULL
+    hosts = {
+        "poly": synth.poly(seed, **F["poly"]),
+        "gather": synth.gather(seed, **F["gather"]),
+        "sgemm": synth.sgemm(seed, **F["sgemm"]),
+        "spmv": synth.spmv(seed, **F["spmv"]),
+        "stencil": synth.stencil(seed, F["stencil"]["ny"], F["stencil"]["nx"]),
+        "bs": synth.bs(seed, F["bs"]["n"]),
+        "hist": synth.hist(seed, F["hist"]["n"]),
+        "lookup": synth.lookup(seed, **F["lookup"]),
+    }
+    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
+                              c1=F["stencil"]["c1"]),
+              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    return hosts, params
+
+
+def mix(hosts: dict, params: dict, per_type: int, seed: int, device) -> list:
+    """The eight-kernel mix: `per_type` instances of every kind over shared
+    device inputs (each instance has its own outputs and scratch), in a
+    seeded random submission order."""
+    import numpy as np
+    dev_in = {k: device_inputs(k, h, device) for k, h in hosts.items()}
+    insts = [build(k, dev_in[k], params.get(k, {}), device)
+             for _ in range(per_type) for k in TYPES]
+    order = np.random.default_rng(seed).permutation(len(insts))
+    return [insts[i] for i in order]

@@ -41,3 +41,21 @@ def assert_close_scaled(got, ref, scale, tol, what):
     bad = np.nonzero(err > bound)[0]
     assert bad.size == 0, (f"{what}: {bad.size} elements out of tolerance, first "
                            f"{bad[:5]} err {err[bad[:5]]} bound {bound[bad[:5]]}")
+
+
+def small_mix(dev):
+    """Two instances of each of the eight kernels at small sizes (several
+    tiles each, seconds of oracle time), built on `dev`."""
+    import synth
+    hosts = {
+        "poly": (synth.poly(0, n=1 << 16), {}),
+        "gather": (synth.gather(0, n=1 << 18, table=1 << 20), {}),
+        "sgemm": (synth.sgemm(0, 512, 512, 512), {}),
+        "spmv": (synth.spmv(0, rows=1 << 16, cols=1 << 16), {}),
+        "stencil": (synth.stencil(0, 512, 512), dict(iters=10, c0=0.5, c1=0.125)),
+        "bs": (synth.bs(0, n=1 << 18), dict(r=0.02, sigma=0.3)),
+        "hist": (synth.hist(0, n=1 << 22), {}),
+        "lookup": (synth.lookup(0, nkeys=1 << 18, nq=1 << 18), {}),
+    }
+    return [W.build(k, W.device_inputs(k, *hosts[k][:1], dev), hosts[k][1], dev)
+            for rep in range(2) for k in KINDS]

@@ -12,7 +12,7 @@ from paper_1303_5164_amd import surrogate as S
 from paper_1303_5164_amd import workloads as W
 import synth
 
-from gpu_util import KINDS, result
+from gpu_util import result, small_mix
 
 pytestmark = pytest.mark.gpu
 
@@ -71,25 +71,10 @@ def test_trained_surrogate_generalises_to_unseen_kernels():
     assert err < 0.10
 
 
-def _mix(dev):
-    hosts = {
-        "poly": (synth.poly(0, n=1 << 16), {}),
-        "gather": (synth.gather(0, n=1 << 18, table=1 << 20), {}),
-        "sgemm": (synth.sgemm(0, 512, 512, 512), {}),
-        "spmv": (synth.spmv(0, rows=1 << 16, cols=1 << 16), {}),
-        "stencil": (synth.stencil(0, 512, 512), dict(iters=10, c0=0.5, c1=0.125)),
-        "bs": (synth.bs(0, n=1 << 18), dict(r=0.02, sigma=0.3)),
-        "hist": (synth.hist(0, n=1 << 22), {}),
-        "lookup": (synth.lookup(0, nkeys=1 << 18, nq=1 << 18), {}),
-    }
-    return [W.build(k, W.device_inputs(k, *hosts[k][:1], dev), hosts[k][1], dev)
-            for rep in range(2) for k in KINDS]
-
-
 def test_surrogate_policy_same_bits_as_fifo():
     dev = torch.device("cuda:0")
     prof = profiles.load()
-    insts = _mix(dev)
+    insts = small_mix(dev)
     with K.Runtime(0, surrogate_topk=2) as rt:
         kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
         j = rt.submit(kids["poly"], insts[0].launches[0].grid, insts[0].launches[0].args)

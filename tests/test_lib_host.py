@@ -127,6 +127,64 @@ def test_simulate_matches_oracle(seed, prune, betas, short):
     assert abs(span_f - fspan) <= 1e-9 * fspan
 
 
+def _rand_measures(rng, n_types):
+    rows = []
+    for a in range(n_types):
+        for b in range(a + 1, n_types):
+            if rng.uniform() < 0.3:
+                continue
+            for _ in range(int(rng.integers(1, 4))):
+                x, y = (a, b) if rng.uniform() < 0.5 else (b, a)
+                rows.append(dict(a=x, b=y, b1=int(rng.integers(1, 8)), b2=int(rng.integers(1, 8)),
+                                 rel_a=float(rng.uniform(0.3, 1.0)),
+                                 rel_b=float(rng.uniform(0.3, 1.0))))
+    return rows
+
+
+@pytest.mark.parametrize("seed,policy,short", [(11, "opt", 0.0), (12, "opt", 3000.0),
+                                               (13, "random", 0.0), (14, "random", 3000.0),
+                                               (15, "random", 0.0)])
+def test_simulate_baselines_match_oracle(seed, policy, short):
+    """OPT (measured co-runs) and Monte Carlo samples (SplitMix64 draws) on
+    the virtual clock: the library's decisions, makespan and completion
+    times equal the oracle's."""
+    profs, jp, jw, ja = _types_and_jobs(seed)
+    rng = np.random.default_rng(100 + seed)
+    rows = _rand_measures(rng, len(profs)) if policy == "opt" else []
+    cfg = K.default_config(n_cu=256, min_pair_slots=short, random_seed=1000 + seed)
+    decs, span, done = K.simulate(profs, jp, jw, ja, policy, cfg, measures=rows)
+    types = {i: S.TypeInfo(oracle_kprof(p), p["pur"], p["mur"]) for i, p in enumerate(profs)}
+    ocfg = S.Config(n_cu=256, min_pair_slots=short, random_seed=1000 + seed)
+    jobs = [S.Job(i, jp[i], jw[i], ja[i]) for i in range(len(jp))]
+    log, ospan, odone = S.simulate_kernelet(jobs, types, ocfg, policy=policy,
+                                            measures=[S.Measure(**r) for r in rows])
+    assert len(decs) == len(log)
+    paired = 0
+    for d, o in zip(decs, log):
+        assert (d["j1"], d["j2"], d["b1"], d["b2"]) == (o.j1, o.j2, o.b1, o.b2)
+        assert abs(d["value"] - o.value) <= 1e-12 * max(1.0, abs(o.value))
+        paired += o.j2 >= 0
+    assert paired > 0
+    assert abs(span - ospan) <= 1e-9 * ospan
+    assert np.allclose(done, [odone[i] for i in range(len(jp))], rtol=1e-9)
+
+
+def test_simulate_rejects_bad_measures_and_policies():
+    profs, jp, jw, ja = _types_and_jobs(1)
+    bad = [dict(a=0, b=0, b1=1, b2=1, rel_a=0.5, rel_b=0.5)]
+    with pytest.raises(K.KerneletError):
+        K.simulate(profs, jp, jw, ja, "opt", measures=bad)
+    bad = [dict(a=0, b=9, b1=1, b2=1, rel_a=0.5, rel_b=0.5)]
+    with pytest.raises(K.KerneletError):
+        K.simulate(profs, jp, jw, ja, "opt", measures=bad)
+    bad = [dict(a=0, b=1, b1=1, b2=1, rel_a=0.0, rel_b=0.5)]
+    with pytest.raises(K.KerneletError):
+        K.simulate(profs, jp, jw, ja, "opt", measures=bad)
+    for pol in ("surrogate", "fixed"):
+        with pytest.raises(K.KerneletError):
+            K.simulate(profs, jp, jw, ja, pol)
+
+
 def test_host_errors():
     good = dict(r_mem=0.1, mem_req=1, instr_per_wave=10, max_wg_per_cu=2, waves_per_simd=1)
     bad = dict(good, r_mem=1.5)

@@ -365,3 +365,51 @@ def test_jobs_too_short_to_pair_run_alone_without_holding_lanes(L):
     start = lambda j: j[2][: j[3][0], 3].min()
     assert start(c2) >= end(c1)
     h.close()
+
+
+def test_opt_policy_runs_the_measured_best_pair(L):
+    """OPT: refused until measured co-runs are loaded; then every decision
+    that pairs the two kinds uses the row of highest measured CP, and every
+    workgroup runs once."""
+    h = Harness(L, use_prune=0)
+    jobs = [h.job(64, i, kind=i % 2, us=20) for i in range(6)]
+    with pytest.raises(K.KerneletError) as e:
+        h.rt.schedule("opt")
+    assert e.value.code == -5
+    with pytest.raises(K.KerneletError):
+        h.rt.set_pair_measures([dict(a=h.kids[0], b=h.kids[0], b1=1, b2=1, rel_a=1, rel_b=1)])
+    rows = [dict(a=h.kids[0], b=h.kids[1], b1=2, b2=6, rel_a=0.7, rel_b=0.6),
+            dict(a=h.kids[1], b=h.kids[0], b1=3, b2=5, rel_a=0.9, rel_b=0.8),
+            dict(a=h.kids[0], b=h.kids[1], b1=4, b2=4, rel_a=0.5, rel_b=0.4)]
+    h.rt.set_pair_measures(rows)
+    _run_with_deadline(lambda: h.rt.schedule("opt", blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    kind = {j[0]: i % 2 for i, j in enumerate(jobs)}
+    dec = [d for d in h.rt.decisions() if d["j2"] >= 0]
+    assert dec
+    for d in dec:
+        # the (kind 1 at 3, kind 0 at 5) row, whichever kind comes first
+        want = (5, 3) if kind[d["j1"]] == 0 else (3, 5)
+        assert (d["b1"], d["b2"]) == want
+        assert abs(d["value"] - (1 - 1 / 1.7)) < 1e-12
+
+
+def test_random_policy_is_seeded_and_runs_everything(L):
+    """RANDOM: the same seed gives the same plan on a fresh runtime; every
+    chosen ratio fits on a CU; every workgroup runs once."""
+    plans = []
+    for seed in (7, 7, 8):
+        h = Harness(L, use_prune=0, random_seed=seed)
+        jobs = [h.job(64, i, kind=i % 2, us=10) for i in range(8)]
+        _run_with_deadline(lambda: h.rt.schedule("random", blocking=True, wait_done=True))
+        for j in jobs:
+            h.rt.wait(j[0], 5_000_000_000)
+            assert np.all(j[1] == 1)
+        dec = h.rt.decisions()
+        assert any(d["j2"] >= 0 for d in dec)
+        assert all(d["b1"] + d["b2"] <= 8 for d in dec if d["j2"] >= 0)
+        plans.append([(d["b1"], d["b2"]) for d in dec if d["j2"] >= 0])
+        h.close()
+    assert plans[0] == plans[1]

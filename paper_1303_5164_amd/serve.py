@@ -23,6 +23,7 @@ Usage: python -m paper_1303_5164_amd.serve --out gpurun_out/serve.json
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -147,6 +148,7 @@ class Server:
         self.base_scale = base_scale
         self.prof = profiles.load()
         self.inputs, self.ref, self.solo_ms = {}, {}, {}
+        self.client_streams = []
         self.log = log or (lambda s: None)
         for kind in self.kinds:
             for c in SIZE_LOG2:
@@ -174,6 +176,12 @@ class Server:
             cfg.setdefault(k, v)
         rt = R.Runtime(self.device, **cfg)
         kids = {k: rt.register_builtin(k, self.prof[k]) for k in self.W.KERNELS}
+        # the measured co-run table (OPT) and the surrogate's weights
+        from . import surrogate
+        with open(surrogate.CORUNS) as f:
+            rt.set_pair_measures(json.load(f)["rows"], kids)
+        import numpy as np
+        rt.set_surrogate(np.load(surrogate.WEIGHTS_MEASURED))
         return rt, kids
 
     def references(self, reps=3):
@@ -217,8 +225,10 @@ class Server:
         errors = []
         t_base = [0]
 
-        def client(mine):
-            s = torch.cuda.Stream(self.dev)
+        go = threading.Event()
+
+        def client(mine, s):
+            go.wait()
             try:
                 for r in mine:
                     delay = t_base[0] + r["t"] - time.perf_counter()
@@ -235,11 +245,21 @@ class Server:
                     ev.set()
 
         rt.schedule(policy, blocking=False)
-        threads = [threading.Thread(target=client, args=(m,), daemon=True)
-                   for m in by_client.values()]
-        t_base[0] = time.perf_counter() + 0.05
+        # one stream per client, the same streams in every run: the device
+        # memory pool caches blocks per stream, so fresh streams would send
+        # the first requests of a run to the device allocator
+        while len(self.client_streams) < len(by_client):
+            self.client_streams.append(torch.cuda.Stream(self.dev))
+        threads = [threading.Thread(target=client, args=(m, self.client_streams[k]), daemon=True)
+                   for k, m in enumerate(by_client.values())]
+        # a cyclic garbage collection of the interpreter stalls every client
+        # thread for tens of milliseconds: collect now, not while serving
+        gc.collect()
+        gc.disable()
         for th in threads:
             th.start()
+        t_base[0] = time.perf_counter() + 0.05
+        go.set()
         recs = []
         n_verified = 0
         bad = []
@@ -270,6 +290,7 @@ class Server:
                 th.join()
             st = rt.stats()
         finally:
+            gc.enable()
             rt.close()
         t0 = min(r["submit_ns"] for r in recs)
         t1 = max(r["done_ns"] for r in recs)
@@ -281,6 +302,11 @@ class Server:
             "p99_turnaround_ms": percentile(tat, 0.99),
             "mean_turnaround_ms": sum(tat) / n,
             "max_client_lag_ms": max(r["lag_ms"] for r in recs),
+            "p99_client_lag_ms": percentile([r["lag_ms"] for r in recs], 0.99),
+            "worst_client_lags": [
+                dict(t_s=round(reqs[i]["t"], 4), lag_ms=round(recs[i]["lag_ms"], 2),
+                     kind=recs[i]["kind"], size=recs[i]["size"], client=recs[i]["client"])
+                for i in sorted(range(n), key=lambda i: -recs[i]["lag_ms"])[:8]],
             "resident_peak_bytes": st["resident_peak"],
             "decisions": st["decisions"], "slices": st["slices_launched"],
             "verified": n_verified, "mismatches": len(bad), "mismatched": bad[:20],
@@ -300,8 +326,13 @@ def main():
     ap.add_argument("--base-scale", type=float, default=1.0)
     ap.add_argument("--verify-every", type=int, default=20)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--min-pair-us", type=float, default=None,
-                    help="pairing threshold (default: the profile table's)")
+    ap.add_argument("--warmup", type=int, default=-1,
+                    help="requests served once under FIFO before the measured runs (-1: "
+                         "all): the first pass grows the device memory pool and loads the "
+                         "device code of the checks, both of which delay the clients")
+    ap.add_argument("--min-pair-us", default=None,
+                    help="pairing threshold in microseconds, or a comma list to run every "
+                         "co-scheduling policy at each (default: the profile table's)")
     a = ap.parse_args()
 
     def log(s):
@@ -316,14 +347,27 @@ def main():
     out = {"instances": a.instances, "clients": a.clients, "load": a.load,
            "rate_per_s": rate, "mean_service_ms": es, "base_scale": a.base_scale,
            "solo_ms": {f"{k}:{c}": v for (k, c), v in srv.solo_ms.items()}, "runs": []}
+    if a.warmup != 0:
+        w = reqs if a.warmup < 0 else reqs[:a.warmup]
+        # verifying as the measured runs do: the first comparison on the main
+        # thread loads its device code while holding the interpreter lock,
+        # stalling every client for ~90 ms
+        _, summ = srv.serve(w, "fifo", budget=a.budget_gb * (1 << 30),
+                            verify_every=a.verify_every)
+        log(f"warm-up {len(w)} requests: p99 {summ['p99_turnaround_ms']:.3f} ms, "
+            f"client lag {summ['max_client_lag_ms']:.1f} ms")
+    thresholds = ([None] if a.min_pair_us is None else
+                  [float(x) for x in str(a.min_pair_us).split(",")])
     for pol in a.policies.split(","):
-        over = {}
-        if a.min_pair_us is not None:
-            over["min_pair_slots"] = a.min_pair_us * 1e-6 * 2.4e9 / 4.0
-        _, summ = srv.serve(reqs, pol, budget=a.budget_gb * (1 << 30),
-                            verify_every=a.verify_every, **over)
-        log(json.dumps(summ))
-        out["runs"].append(summ)
+        for thr in (thresholds if pol != "fifo" else [None]):
+            over = {}
+            if thr is not None:
+                over["min_pair_slots"] = thr * 1e-6 * 2.4e9 / 4.0
+            _, summ = srv.serve(reqs, pol, budget=a.budget_gb * (1 << 30),
+                                verify_every=a.verify_every, **over)
+            summ["min_pair_us"] = thr
+            log(json.dumps(summ))
+            out["runs"].append(summ)
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
 

@@ -230,6 +230,20 @@ const char* kernelet_last_error(void);
 kl_status kernelet_register(kl_runtime* rt, const kl_kernel_desc* d,
                             kl_kernel* out);
 
+/* Register a kernel type from a gfx950 code object (Section 4.1: a compiled
+ * kernel made sliceable by rewriting it).  `image` (host memory, `bytes`
+ * long; read during the call) holds the kernel `symbol`, which takes
+ * (ArgsT args, kl_slice s) by value: the form paper_1303_5164_amd/
+ * irslice.py gives a kernel written without slicing.  d->host_fn must be
+ * NULL; d->name, block_threads, args_bytes (sizeof(ArgsT)), flags and
+ * profile as for kernelet_register.  The code object is loaded on the
+ * runtime's device and unloaded at shutdown; jobs of the type are launched
+ * through it like any other.  Errors: KL_EINVAL, KL_EEXIST (duplicate
+ * name), KL_EHIP (the image does not load or lacks the symbol). */
+kl_status kernelet_register_image(kl_runtime* rt, const kl_kernel_desc* d,
+                                  const void* image, uint64_t bytes, const char* symbol,
+                                  kl_kernel* out);
+
 /* Look up one of the library's eight workload kernels by name ("poly",
  * "gather", "sgemm", "spmv", "stencil", "bs", "hist", "lookup") and fill a
  * descriptor for kernelet_register.  The descriptor's strings are static. */

@@ -151,7 +151,7 @@ SYMBOLS = [
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
     "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
-    "kernelet_set_pair_measures",
+    "kernelet_set_pair_measures", "kernelet_register_image",
 ]
 
 _lib = None
@@ -185,6 +185,8 @@ def configure(L):
         "kernelet_get_config": [C.c_void_p, C.POINTER(Config)],
         "kernelet_shutdown": [C.c_void_p],
         "kernelet_register": [C.c_void_p, C.POINTER(KernelDesc), C.POINTER(i32)],
+        "kernelet_register_image": [C.c_void_p, C.POINTER(KernelDesc), C.c_void_p, u64,
+                                    C.c_char_p, C.POINTER(i32)],
         "kernelet_builtin": [C.c_char_p, C.POINTER(KernelDesc)],
         "kernelet_builtin_grid": [C.c_char_p, C.c_void_p, u32, C.POINTER(Dim3)],
         "kernelet_set_profile": [C.c_void_p, i32, C.POINTER(Profile)],

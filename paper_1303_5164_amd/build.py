@@ -52,7 +52,23 @@ def build(verbose: bool = False) -> str:
     _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp,
           "-lpthread"])
     os.replace(tmp, LIB)
+    build_plain()
     return LIB
+
+
+PLAIN_SOURCE = os.path.join(CSRC, "plain_kernels.hip")
+PLAIN_IMAGE = os.path.join(HERE, "plain_kernels_sliced.hsaco")
+PLAIN_KERNELS = ["kl_plain_matadd", "kl_plain_visit3d"]
+
+
+def build_plain() -> str:
+    """The kernels written without slicing, made sliceable by rewriting
+    their device IR, in one code object."""
+    from . import irslice
+    tmp = PLAIN_IMAGE + ".tmp"
+    irslice.slice_source(PLAIN_SOURCE, PLAIN_KERNELS, tmp)
+    os.replace(tmp, PLAIN_IMAGE)
+    return PLAIN_IMAGE
 
 
 if __name__ == "__main__":

@@ -94,6 +94,9 @@ struct EvPool {
 struct KernelType {
     std::string name;
     const void* fn = nullptr;
+    // a kernel loaded from a code object (kernelet_register_image)
+    hipModule_t mod = nullptr;
+    hipFunction_t mfn = nullptr;
     uint32_t block = 256, args_bytes = 0, flags = 0;
     const char* builtin = nullptr;
     kl_profile prof{};
@@ -393,8 +396,10 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
         }
         KL_HIP(hipEventRecord(ta, ln.s));
     }
-    hipError_t e = hipLaunchKernel(kt.fn, dim3(count), dim3(kt.block), params,
-                                   ln.dyn_lds, ln.s);
+    hipError_t e = kt.mfn ? hipModuleLaunchKernel(kt.mfn, count, 1, 1, kt.block, 1, 1,
+                                                  (unsigned)ln.dyn_lds, ln.s, params, nullptr)
+                          : hipLaunchKernel(kt.fn, dim3(count), dim3(kt.block), params,
+                                            ln.dyn_lds, ln.s);
     if (e != hipSuccess) {
         set_error(std::string("hipLaunchKernel(") + kt.name + "): " + hipGetErrorString(e));
         j.error = true;
@@ -951,6 +956,8 @@ kl_status kernelet_shutdown(kl_runtime* rt) {
     }
     for (auto e : rt->tev_free) (void)hipEventDestroy(e);
     if (rt->sur_stream) (void)hipStreamDestroy(rt->sur_stream);
+    for (auto& k : rt->kernels)
+        if (k.mod) (void)hipModuleUnload(k.mod);
     (void)hipFree(rt->sur_params);
     (void)hipFree(rt->sur_x);
     (void)hipFree(rt->sur_y);
@@ -960,26 +967,72 @@ kl_status kernelet_shutdown(kl_runtime* rt) {
     return KL_OK;
 }
 
-kl_status kernelet_register(kl_runtime* rt, const kl_kernel_desc* d, kl_kernel* out) {
-    if (!rt || !d || !out || !d->name || !d->host_fn) {
-        set_error("kernelet_register: null argument");
-        return KL_EINVAL;
-    }
+// Checks shared by the two ways of registering a kernel.
+static kl_status check_desc(kl_runtime* rt, const kl_kernel_desc* d, const char* who) {
     if (d->block_threads == 0 || d->block_threads % 256 || d->block_threads > 1024 ||
         d->args_bytes == 0 || d->args_bytes > 256) {
-        set_error("kernelet_register: block_threads must be 256, 512, 768 or 1024 and "
+        set_error(std::string(who) + ": block_threads must be 256, 512, 768 or 1024 and "
                   "args_bytes in [1, 256]");
         return KL_EINVAL;
     }
     if (d->profile) {
         if (kl_status s = check_profile(*d->profile)) return s;
     }
-    std::lock_guard<std::mutex> g(rt->mu);
     for (auto& k : rt->kernels)
         if (k.name == d->name) {
-            set_error(std::string("kernelet_register: duplicate name ") + d->name);
+            set_error(std::string(who) + ": duplicate name " + d->name);
             return KL_EEXIST;
         }
+    return KL_OK;
+}
+
+kl_status kernelet_register_image(kl_runtime* rt, const kl_kernel_desc* d, const void* image,
+                                  uint64_t bytes, const char* symbol, kl_kernel* out) {
+    if (!rt || !d || !out || !d->name || !image || bytes == 0 || !symbol) {
+        set_error("kernelet_register_image: null argument");
+        return KL_EINVAL;
+    }
+    if (d->host_fn) {
+        set_error("kernelet_register_image: the descriptor's host_fn must be NULL");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    if (kl_status s = check_desc(rt, d, "kernelet_register_image")) return s;
+    KL_HIP(hipSetDevice(rt->device));
+    // the loader reads the image during the call; a copy keeps it aligned
+    std::vector<uint64_t> img((bytes + 7) / 8);
+    std::memcpy(img.data(), image, bytes);
+    KernelType kt;
+    KL_HIP(hipModuleLoadData(&kt.mod, img.data()));
+    if (hipModuleGetFunction(&kt.mfn, kt.mod, symbol) != hipSuccess) {
+        (void)hipModuleUnload(kt.mod);
+        set_error(std::string("kernelet_register_image: no kernel ") + symbol + " in the image");
+        return KL_EHIP;
+    }
+    int lds = 0;
+    if (hipFuncGetAttribute(&lds, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, kt.mfn) == hipSuccess)
+        kt.static_lds = lds;
+    kt.name = d->name;
+    kt.block = d->block_threads;
+    kt.args_bytes = d->args_bytes;
+    kt.flags = d->flags;
+    if (d->profile) {
+        kt.prof = *d->profile;
+        kt.has_prof = true;
+        rt->planner->set_type((int)rt->kernels.size(), kt.prof);
+    }
+    rt->kernels.push_back(kt);
+    *out = (kl_kernel)(rt->kernels.size() - 1);
+    return KL_OK;
+}
+
+kl_status kernelet_register(kl_runtime* rt, const kl_kernel_desc* d, kl_kernel* out) {
+    if (!rt || !d || !out || !d->name || !d->host_fn) {
+        set_error("kernelet_register: null argument");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    if (kl_status s = check_desc(rt, d, "kernelet_register")) return s;
     KernelType kt;
     kt.name = d->name;
     kt.fn = d->host_fn;
@@ -1008,6 +1061,7 @@ kl_status kernelet_kernel_info(kl_runtime* rt, kl_kernel k, int32_t* max_wg_per_
         return KL_EINVAL;
     }
     const void* fn;
+    hipFunction_t mfn;
     uint32_t block;
     {
         std::lock_guard<std::mutex> g(rt->mu);
@@ -1016,9 +1070,20 @@ kl_status kernelet_kernel_info(kl_runtime* rt, kl_kernel k, int32_t* max_wg_per_
             return KL_ENOTFOUND;
         }
         fn = rt->kernels[k].fn;
+        mfn = rt->kernels[k].mfn;
         block = rt->kernels[k].block;
     }
     KL_HIP(hipSetDevice(rt->device));
+    if (mfn) {
+        int nb = 0, regs = 0, lds = 0;
+        KL_HIP(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfn, (int)block, 0));
+        KL_HIP(hipFuncGetAttribute(&regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, mfn));
+        KL_HIP(hipFuncGetAttribute(&lds, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, mfn));
+        if (max_wg_per_cu) *max_wg_per_cu = nb;
+        if (vgpr) *vgpr = regs;
+        if (lds_bytes) *lds_bytes = lds;
+        return KL_OK;
+    }
     hipFuncAttributes attr;
     KL_HIP(hipFuncGetAttributes(&attr, fn));
     int nb = 0;

@@ -142,6 +142,22 @@ class Runtime:
         self.kernels[desc.name.decode()] = k.value
         return k.value
 
+    def register_image(self, name: str, image: bytes, symbol: str, args_bytes: int,
+                       profile=None, block_threads: int = 256) -> int:
+        """Register kernel `symbol` of a code object (bytes) that takes
+        (Args, kl_slice), e.g. one made by irslice from a kernel written
+        without slicing."""
+        desc = KernelDesc(name.encode(), None, block_threads, args_bytes, 0, None)
+        if profile is not None:
+            prof = make_profile(profile)
+            desc.profile = C.pointer(prof)
+        buf = C.create_string_buffer(bytes(image), len(image))
+        k = C.c_int32()
+        self._c("kernelet_register_image", self.h, C.byref(desc), buf, len(image),
+                symbol.encode(), C.byref(k))
+        self.kernels[name] = k.value
+        return k.value
+
     def register_builtin(self, name: str, profile=None) -> int:
         return self.register(builtin_desc(name), profile)
 

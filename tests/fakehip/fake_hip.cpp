@@ -8,6 +8,7 @@
 #include <deque>
 #include <functional>
 #include <map>
+#include <string>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -82,7 +83,23 @@ void stream_main(FakeStream* s) {
 }
 }  // namespace
 
+struct FakeModule {
+    int loaded;
+};
+struct FakeModuleFn {
+    int (*fn)(const void* args, const kl_slice* s);
+    uint32_t args_bytes;
+};
+namespace {
+std::map<std::string, FakeModuleFn> g_symbols;  // guarded by g_mu
+}
+
 extern "C" {
+// Register a host function as the kernel `name` of every fake code object.
+void fake_register_symbol(const char* name, fake_kernel_fn fn, uint32_t args_bytes) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_symbols[name] = FakeModuleFn{fn, args_bytes};
+}
 // Register a host function that stands for a GPU kernel.
 void fake_register_kernel(const void* key, fake_kernel_fn fn, uint32_t args_bytes) {
     std::lock_guard<std::mutex> g(g_mu);
@@ -178,6 +195,45 @@ hipError_t hipLaunchKernel(const void* fn, dim3 grid, dim3, void** args, size_t,
     if (op.slice.count != grid.x) return hipErrorInvalidValue;
     s->q.push_back(std::move(op));
     g_cv.notify_all();
+    return hipSuccess;
+}
+hipError_t hipModuleLoadData(hipModule_t* m, const void* image) {
+    if (std::strcmp((const char*)image, "fake-module") != 0) return hipErrorInvalidValue;
+    *m = new FakeModule{1};
+    return hipSuccess;
+}
+hipError_t hipModuleUnload(hipModule_t m) {
+    delete m;
+    return hipSuccess;
+}
+hipError_t hipModuleGetFunction(hipFunction_t* f, hipModule_t, const char* name) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_symbols.find(name);
+    if (it == g_symbols.end()) return hipErrorInvalidValue;
+    *f = &it->second;
+    return hipSuccess;
+}
+hipError_t hipModuleLaunchKernel(hipFunction_t f, unsigned gx, unsigned, unsigned, unsigned,
+                                 unsigned, unsigned, unsigned, hipStream_t s, void** args,
+                                 void**) {
+    std::lock_guard<std::mutex> g(g_mu);
+    Op op;
+    op.kind = 0;
+    op.k = FakeKernel{f->fn, f->args_bytes};
+    op.args.assign((const uint8_t*)args[0], (const uint8_t*)args[0] + f->args_bytes);
+    std::memcpy(&op.slice, args[1], sizeof(kl_slice));
+    if (op.slice.count != gx) return hipErrorInvalidValue;
+    s->q.push_back(std::move(op));
+    g_cv.notify_all();
+    return hipSuccess;
+}
+hipError_t hipFuncGetAttribute(int* v, hipFunction_attribute a, hipFunction_t) {
+    *v = a == HIP_FUNC_ATTRIBUTE_NUM_REGS ? 32 : 0;
+    return hipSuccess;
+}
+hipError_t hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(int* n, hipFunction_t, int,
+                                                              size_t) {
+    *n = 8;
     return hipSuccess;
 }
 hipError_t hipFuncGetAttributes(hipFuncAttributes* a, const void*) {

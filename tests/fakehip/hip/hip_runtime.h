@@ -58,6 +58,26 @@ hipError_t hipOccupancyMaxActiveBlocksPerMultiprocessor(int* n, const void* fn, 
                                                         size_t dyn);
 const char* hipGetErrorString(hipError_t e);
 
+// code objects: an image is the text "fake-module"; its functions are the
+// host functions registered by symbol with fake_register_symbol
+struct FakeModule;
+struct FakeModuleFn;
+typedef FakeModule* hipModule_t;
+typedef const FakeModuleFn* hipFunction_t;
+typedef enum {
+    HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES = 1,
+    HIP_FUNC_ATTRIBUTE_NUM_REGS = 4
+} hipFunction_attribute;
+hipError_t hipModuleLoadData(hipModule_t* m, const void* image);
+hipError_t hipModuleUnload(hipModule_t m);
+hipError_t hipModuleGetFunction(hipFunction_t* f, hipModule_t m, const char* name);
+hipError_t hipModuleLaunchKernel(hipFunction_t f, unsigned gx, unsigned gy, unsigned gz,
+                                 unsigned bx, unsigned by, unsigned bz, unsigned shmem,
+                                 hipStream_t s, void** params, void** extra);
+hipError_t hipFuncGetAttribute(int* v, hipFunction_attribute a, hipFunction_t f);
+hipError_t hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(int* n, hipFunction_t f,
+                                                              int block, size_t dyn);
+
 // memory: plain host memory; copies are synchronous
 typedef enum { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2 } hipMemcpyKind;
 hipError_t hipMalloc(void** p, size_t n);

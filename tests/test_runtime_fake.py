@@ -413,3 +413,33 @@ def test_random_policy_is_seeded_and_runs_everything(L):
         plans.append([(d["b1"], d["b2"]) for d in dec if d["j2"] >= 0])
         h.close()
     assert plans[0] == plans[1]
+
+
+def test_code_object_kernel_is_sliced_like_any_other(L):
+    """kernelet_register_image: a kernel loaded from a code object (here the
+    test double's "fake-module", whose kernel is a host function) is launched
+    through the module API with (Args, kl_slice); sliced and co-scheduled,
+    every workgroup still runs once.  Bad images and symbols are refused."""
+    L.fake_register_symbol.argtypes = [C.c_char_p, C.c_void_p, C.c_uint32]
+    L.fake_register_symbol(b"kl_plain_visit", C.cast(L.fake_visit, C.c_void_p).value,
+                           C.sizeof(VisitArgs))
+    h = Harness(L, use_prune=0)
+    img = b"fake-module\0"
+    k = h.rt.register_image("visit_image", img, "kl_plain_visit", C.sizeof(VisitArgs), PROF[1])
+    with pytest.raises(K.KerneletError):
+        h.rt.register_image("bad_image", b"not-a-module\0", "kl_plain_visit", C.sizeof(VisitArgs))
+    with pytest.raises(K.KerneletError):
+        h.rt.register_image("bad_symbol", img, "no_such_kernel", C.sizeof(VisitArgs))
+    with pytest.raises(K.KerneletError):
+        h.rt.register_image("visit_image", img, "kl_plain_visit", C.sizeof(VisitArgs))
+    h.kids.append(k)
+    jobs = [h.job(96, i, kind=2 if i % 2 else 0, us=10) for i in range(6)]
+    for j in jobs[1::2]:
+        h.rt.slice(j[0], 7)
+    _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    info = h.rt.kernel_info(k)
+    assert info["max_wg_per_cu"] == 8
+    h.close()

@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
     ap.add_argument("--lds-reserve", type=int, default=None)
     ap.add_argument("--cp-min", type=float, default=None)
+    ap.add_argument("--solo-overlap", type=int, default=None,
+                    help="1: a kernel run alone does not hold the other lane back")
     ap.add_argument("--estimates", action="store_true",
                     help="use the first-order profile estimates, not the measured table")
     ap.add_argument("--copy-probe", action="store_true",
@@ -201,6 +203,8 @@ def main():
         over["lds_reserve"] = args.lds_reserve
     if args.cp_min is not None:
         over["cp_min"] = args.cp_min
+    if args.solo_overlap is not None:
+        over["solo_overlap"] = args.solo_overlap
     legs = [l for l in args.legs.split(",") if l]
     main_leg = "kernelet" if "kernelet" in legs else legs[0]
     over["surrogate_topk"] = args.topk if args.topk is not None else 0
@@ -316,7 +320,8 @@ def main():
                    "instances_per_type": args.instances, "instances": n_inst,
                    "policy": args.policy, "parallelism": "single GPU, 2 co-execution lanes",
                    "inflight": rt.cfg.inflight, "lds_reserve": rt.cfg.lds_reserve,
-                   "cp_min": rt.cfg.cp_min, "beta": rt.cfg.beta, "beta_lds": rt.cfg.beta_lds,
+                   "cp_min": rt.cfg.cp_min, "solo_overlap": rt.cfg.solo_overlap,
+                   "beta": rt.cfg.beta, "beta_lds": rt.cfg.beta_lds,
                    "min_pair_slots": rt.cfg.min_pair_slots,
                    "profiles": "estimates" if args.estimates else "measured",
                    "surrogate": (None if sur_weights is None else

@@ -137,7 +137,10 @@ typedef struct {
     double alpha_p, alpha_m; /* pruning thresholds (0.4, 0.1) */
     int32_t use_prune;
     int32_t ratio_mode;    /* kl_ratio_mode (KL_MODE_CP) */
-    double cp_min;         /* co-run only if predicted profit exceeds this */
+    double cp_min;         /* the best pair is taken only if its profit
+                              (Eq. 1) exceeds this; else the earliest job
+                              runs alone (-1: any pair not predicted to
+                              halve the two kernels' throughput)          */
     double mem_latency;    /* memory latency with an idle memory system, slots */
     double beta;           /* latency added per outstanding request, slots */
     int32_t lanes;         /* co-execution streams (2) */
@@ -158,7 +161,11 @@ typedef struct {
                               of kernelet_simulate) takes outputs 2k and
                               2k + 1 of the SplitMix64 stream whose state
                               starts at this seed (0)                      */
-    int32_t reserved[6];
+    int32_t solo_overlap;  /* a kernel run alone (no profitable pair, R10):
+                              0 the other lanes wait for it; 1 the next
+                              decision's launches may start beside it and
+                              take the compute units it frees (0)         */
+    int32_t reserved[5];
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this

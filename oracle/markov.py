@@ -24,7 +24,7 @@ more than one class, each with its own latency; the paper's instance is
 coalesced / uncoalesced memory stalls, and we also allow a fixed-latency
 compute stall.
 
-Readings where the paper is silent or garbled (each is listed in the design doc):
+Readings where the paper is silent or garbled:
   * return probability is min(1, D / L) with D = max(#ready, 1), the round
     length; the printed (W - I)/L makes the all-idle state absorbing;
   * the latency of a memory class grows linearly with the outstanding memory

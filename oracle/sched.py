@@ -18,11 +18,14 @@ issuing it while both kernels still have thread blocks; then decide again
 on the pending set, which now holds the residual of the kernel that did not
 finish and every kernel that arrived meanwhile.
 
-Readings (listed in the design doc): ties between pairs go to the pair whose
-earlier kernel was submitted first, then whose later kernel was; with a
-single pending kernel type, or when the best predicted profit is not above
-`cp_min`, the earliest pending kernel runs alone at its own full occupancy
-(a co-schedule of one slice, which the problem definition allows).
+Readings of the paper: ties between pairs go to the pair whose earlier
+kernel was submitted first, then whose later kernel was.  FindCoSchedule
+takes the pair of largest predicted profit whatever its sign (its candidate
+space holds pairs only); the earliest pending kernel runs alone at its own
+full occupancy (a co-schedule of one slice, which the problem definition
+allows) only with a single pending kernel type, when no pair fits on a CU,
+or when the best profit is not above `cp_min` (default -1: a pair predicted
+to halve the two kernels' throughput).
 
 Virtual clock: one time unit is one issue slot of one SIMD.  A kernel whose
 waves reach IPC c on each SIMD finishes n_cu * c / (waves_per_wg * I)
@@ -65,7 +68,7 @@ class Config:
     beta_lds: float = 0.0
     min_pair_slots: float = 0.0
     mode: str = "cp"
-    cp_min: float = 0.0
+    cp_min: float = -1.0
     random_seed: int = 0
     wmax: int = 8
     vgpr_file: int = 512

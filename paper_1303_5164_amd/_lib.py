@@ -51,7 +51,8 @@ class Config(C.Structure):
                 ("beta", C.c_double), ("lanes", C.c_int32), ("inflight", C.c_int32),
                 ("lds_reserve", C.c_int32), ("max_slices", C.c_int32),
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
-                ("random_seed", C.c_uint32), ("reserved", C.c_int32 * 6),
+                ("random_seed", C.c_uint32), ("solo_overlap", C.c_int32),
+                ("reserved", C.c_int32 * 5),
                 ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 

@@ -203,7 +203,7 @@ static kl_config defaults() {
     c.alpha_m = 0.1;
     c.use_prune = 1;
     c.ratio_mode = KL_MODE_CP;
-    c.cp_min = 0.0;
+    c.cp_min = -1.0;
     c.mem_latency = 400.0;
     c.beta = 0.0;
     c.lanes = 2;
@@ -220,6 +220,7 @@ static kl_status check_cfg(const kl_config& c) {
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
+        c.solo_overlap < 0 || c.solo_overlap > 1 ||
         c.hbm_budget < 0) {
         set_error("invalid kl_config field");
         return KL_EINVAL;
@@ -720,7 +721,8 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
         Lane& ln = rt->lanes[li];
         if (ln.job == KL_NO_JOB) continue;
         Job& j = rt->jobs.at(ln.job);
-        const bool hold_others = solo && !(j.next == 0 && too_short_to_pair(rt, j));
+        const bool hold_others = solo && !rt->cfg.solo_overlap &&
+                                 !(j.next == 0 && too_short_to_pair(rt, j));
         while ((int)ln.inflight.size() < rt->cfg.inflight && j.next < j.total) {
             kl_status s = launch_slice(rt, li, j.id, ln.slice);
             if (s) return s;

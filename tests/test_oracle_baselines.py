@@ -77,9 +77,15 @@ def test_opt_takes_the_best_measured_row_in_either_order():
     model = sched.Model(types, cfg)
     assert abs(d.cipc1 - 0.8 * model.solo_ipc(0)) < 1e-15
     assert abs(d.cipc2 - 0.9 * model.solo_ipc(2)) < 1e-15
-    # a pair without rows is never chosen; no profitable row: alone
+    # the best measured pair is taken even at a loss (CP -0.11 > cp_min -1),
+    # but not when cp_min asks for a profit
     d = sched.find_opt(pend[1:], sched.Model(types, cfg), rows)
+    assert (d.j1, d.j2, d.b1, d.b2) == (1, 2, 4, 4)
+    d = sched.find_opt(pend[1:], sched.Model(types, sched.Config(cp_min=0.0)), rows)
     assert d.j2 == -1 and d.j1 == 1
+    # a pair without rows is never chosen
+    d = sched.find_opt([pend[0], pend[1]], sched.Model(types, cfg), rows[1:])
+    assert d.j2 == -1 and d.j1 == 0
     d = sched.find_opt(pend, sched.Model(types, sched.Config(cp_min=0.5)), rows)
     assert d.j2 == -1 and d.j1 == 0
 

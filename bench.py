@@ -43,11 +43,13 @@ def parse():
     ap.add_argument("--surrogate-weights", default=None,
                     help="surrogate parameters (.npy); default: the packaged weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fifo,kernelet,surrogate,opt",
+    ap.add_argument("--legs", default="fifo,kernelet,surrogate,opt,cke",
                     help="fifo: one in-order stream; kernelet: --policy; surrogate: the "
                          "surrogate network deciding (weights trained with measured co-runs); "
                          "opt: the greedy algorithm on measured co-run profits (the paper's "
-                         "OPT baseline)")
+                         "OPT baseline); cke: plain concurrent execution on the two lanes "
+                         "(the two earliest jobs of different kernels, whole launches, no "
+                         "model)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
     ap.add_argument("--lds-reserve", type=int, default=None)
@@ -268,7 +270,8 @@ def main():
             jobs = [W.submit(rt, kids, inst) for inst in insts]
             torch.cuda.synchronize()
             t0 = time.monotonic_ns()
-            pol = {"fifo": "fifo", "surrogate": "surrogate", "opt": "opt"}.get(leg, args.policy)
+            pol = {"fifo": "fifo", "surrogate": "surrogate", "opt": "opt",
+                   "cke": "fixed"}.get(leg, args.policy)
             rt.schedule(pol, blocking=True, wait_done=True)
             torch.cuda.synchronize()
             t1 = time.monotonic_ns()
@@ -342,7 +345,7 @@ def main():
     for l, pl in pairs.items():
         name = "coschedules" if l == main_leg else f"{l}_coschedules"
         out[name] = dict(sorted(pl.items(), key=lambda kv: -kv[1]))
-    for l in ("surrogate", "opt"):
+    for l in ("surrogate", "opt", "cke"):
         if l in legs and main_leg != l:
             out[f"{l}_kernels_per_s"] = round(n_inst / med[l], 3)
             if "fifo" in legs:

@@ -228,3 +228,29 @@ def test_builtin_descriptors_and_grids():
     with pytest.raises(K.KerneletError) as e:
         K.builtin_desc("nope")
     assert e.value.code == -4
+
+
+def test_empty_and_degenerate_inputs_are_refused():
+    """Every built-in kernel refuses an empty input (and the stencil an
+    in-place sweep) at grid time, before anything is launched."""
+    p = 16
+    cases = {
+        "poly": _lib.PolyArgs(p, p, p, 0, 8),
+        "gather": _lib.GatherArgs(p, p, p, 0, 8),
+        "sgemm": _lib.SgemmArgs(p, p, p, 0, 128, 16),
+        "spmv": _lib.SpmvArgs(p, p, p, p, p, 0, 8, 8, 0),
+        "stencil": _lib.StencilArgs(p, p + 16, 0, 8, 0.5, 0.125),
+        "bs": _lib.BsArgs(p, p, p, p, p, 0, 0.02, 0.3),
+        "hist": _lib.HistArgs(p, p, 0),
+        "lookup": _lib.LookupArgs(p, p, p, p, 0, 4),
+    }
+    for name, a in cases.items():
+        with pytest.raises(K.KerneletError) as e:
+            K.builtin_grid(name, a)
+        assert e.value.code == -1, name
+    with pytest.raises(K.KerneletError):
+        K.builtin_grid("stencil", _lib.StencilArgs(p, p, 8, 8, 0.5, 0.125))
+    # the smallest inputs that are accepted: one workgroup
+    assert K.builtin_grid("poly", _lib.PolyArgs(p, p, p, 1, 1)) == (1, 1, 1)
+    assert K.builtin_grid("stencil", _lib.StencilArgs(p, p + 16, 1, 4, 0.5, 0.125)) == (1, 1, 1)
+    assert K.builtin_grid("lookup", _lib.LookupArgs(p, p, p, p, 1, 4)) == (1, 1, 1)

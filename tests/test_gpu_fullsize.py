@@ -2,10 +2,14 @@
 configuration the bench times: two instances of every kernel submitted
 together and co-scheduled by the Markov policy with the measured profiles
 (contention slopes, pairing threshold, LDS-capped slices), then by the
-surrogate policy.  Outputs are checked against the oracle in full where
-that is cheap (polynomial, gather, SpMV, histogram) and on seeded samples
-the oracle computes point by point elsewhere (SGEMM entries, stencil points
-after 10 sweeps, Black-Scholes options, lookup queries)."""
+surrogate policy, OPT on the measured co-run table, a Monte Carlo sample
+and plain concurrent execution of whole launches.  Outputs are checked
+against the oracle in full where that is cheap (polynomial, gather, SpMV,
+histogram) and on seeded samples the oracle computes point by point
+elsewhere (SGEMM entries, stencil points after 10 sweeps, Black-Scholes
+options, lookup queries)."""
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -51,10 +55,13 @@ def mix():
 
 def _run(insts, policy):
     prof = profiles.load()
-    with K.Runtime(0, surrogate_topk=0, **profiles.model_config()) as rt:
+    with K.Runtime(0, surrogate_topk=0, random_seed=11, **profiles.model_config()) as rt:
         kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
         if policy == "surrogate":
             rt.set_surrogate(np.load(S.WEIGHTS_MEASURED))
+        if policy == "opt":
+            with open(S.CORUNS) as f:
+                rt.set_pair_measures(json.load(f)["rows"], kids)
         for inst in insts:
             inst.reset()
         torch.cuda.synchronize()
@@ -71,7 +78,7 @@ def _out(inst, name=None):
     return inst.tensors[name or inst.result].cpu().numpy()
 
 
-@pytest.mark.parametrize("policy", ["markov", "surrogate"])
+@pytest.mark.parametrize("policy", ["markov", "surrogate", "opt", "random", "fixed"])
 def test_full_mix_matches_oracle(mix, policy):
     hosts, insts = mix
     dec = _run(insts, policy)

@@ -78,6 +78,24 @@ def _matching_paren(s: str, i: int) -> int:
     raise SliceError("unbalanced parentheses in a definition")
 
 
+def _split_top(s: str):
+    """The comma-separated items of s at parenthesis depth 0."""
+    out, depth, cur = [], 0, ""
+    for ch in s:
+        if ch == "(":
+            depth += 1
+        elif ch == ")":
+            depth -= 1
+        if ch == "," and depth == 0:
+            out.append(cur.strip())
+            cur = ""
+        else:
+            cur += ch
+    if cur.strip():
+        out.append(cur.strip())
+    return out
+
+
 def _functions(lines):
     """(name, first line, last line) of every function definition."""
     out, i = [], 0
@@ -129,8 +147,8 @@ def rewrite(ir: str, kernel: str) -> str:
     d = lines[k0]
     p0 = d.index("(", d.index("@" + kernel))
     p1 = _matching_paren(d, p0)
-    params = d[p0 + 1:p1]
-    if params.count("byref(") != 1 or re.search(r"\)\s*align \d+[^,]*,", params):
+    params = _split_top(d[p0 + 1:p1])
+    if len(params) != 1 or "byref(" not in params[0]:
         raise SliceError(f"@{kernel} must take exactly one argument block by value")
     lines[k0] = (d[:p1] + ", ptr addrspace(4) noundef readonly byref(%kl.slice) align 4 "
                  "%kl.s" + d[p1:])

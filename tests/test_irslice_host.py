@@ -81,6 +81,12 @@ extern "C" __global__ void k(A a) { a.o[threadIdx.x] = which(); }
         "two_args": """
 extern "C" __global__ void k(A a, uint32_t extra) { a.o[blockIdx.x] = extra; }
 """,
+        "scalar_first": """
+extern "C" __global__ void k(uint32_t extra, A a) { a.o[blockIdx.x] = extra; }
+""",
+        "no_block": """
+extern "C" __global__ void k(uint32_t* o) { o[blockIdx.x] = 1; }
+""",
         "dispatch": """
 extern "C" __global__ void k(A a) {
     const uint32_t* p = (const uint32_t*)__builtin_amdgcn_dispatch_ptr();

@@ -28,6 +28,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <sys/prctl.h>
 #include <thread>
 #include <vector>
 
@@ -761,8 +762,22 @@ static bool any_inflight(kl_runtime* rt) {
 
 // The dispatcher loop.  Blocking: until every job is launched.  Worker:
 // until stop.
+// Short waits of the dispatcher sleep for the time asked, not for the
+// kernel's default timer slack (50 us), which would add that much to every
+// slice a lane retires; restored on exit.
+struct TimerSlack {
+    int prev;
+    TimerSlack() : prev(prctl(PR_GET_TIMERSLACK, 0, 0, 0, 0)) {
+        prctl(PR_SET_TIMERSLACK, 1000UL, 0, 0, 0);
+    }
+    ~TimerSlack() {
+        if (prev > 0) prctl(PR_SET_TIMERSLACK, (unsigned long)prev, 0, 0, 0);
+    }
+};
+
 static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
                           bool wait_done) {
+    TimerSlack slack;
     std::unique_lock<std::mutex> lk(rt->mu);
     rt->scheduling = true;
     rt->cs_active = false;

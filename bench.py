@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
     ap.add_argument("--lds-reserve", type=int, default=None)
     ap.add_argument("--cp-min", type=float, default=None)
+    ap.add_argument("--pair-same-type", type=int, default=None,
+                    help="1: two instances of one kernel may form a pair")
     ap.add_argument("--min-pair-us", type=float, default=None,
                     help="pairing threshold (default: the profile table's)")
     ap.add_argument("--solo-overlap", type=int, default=None,
@@ -209,6 +211,8 @@ def main():
         over["cp_min"] = args.cp_min
     if args.solo_overlap is not None:
         over["solo_overlap"] = args.solo_overlap
+    if args.pair_same_type is not None:
+        over["pair_same_type"] = args.pair_same_type
     if args.min_pair_us is not None:
         over["min_pair_slots"] = args.min_pair_us * 1e-6 * 2.4e9 / 4.0
     legs = [l for l in args.legs.split(",") if l]

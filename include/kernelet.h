@@ -165,7 +165,12 @@ typedef struct {
                               0 the other lanes wait for it; 1 the next
                               decision's launches may start beside it and
                               take the compute units it frees (0)         */
-    int32_t reserved[5];
+    int32_t pair_same_type; /* 1: the two earliest pending instances of a
+                              kernel type are both candidates, so they may
+                              pair (the PUR/MUR rule prunes such a pair
+                              unless nothing else survives); 0: only the
+                              earliest instance of each type (1)          */
+    int32_t reserved[4];
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this

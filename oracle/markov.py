@@ -249,7 +249,8 @@ def feasible_ratios(p1: KProfile, p2: KProfile, wmax=8, vgpr_file=512,
     return out
 
 
-def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", beta_lds=0.0, **kw):
+def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", beta_lds=0.0,
+               same=False, **kw):
     """Search the feasible (b1, b2) of a pair.
 
     mode "balanced": maximise CP_eff = 1 - max(T1, T2) / (T1s + T2s) with
@@ -260,12 +261,17 @@ def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", beta_lds=0
     mode "cp": maximise Eq. (1) directly.
     mode "literal": minimise Delta T of Eq. (8), ties to the larger CP.
     Returns (b1, b2, cp_value, cipc1, cipc2); first maximum in (b1, b2)
-    lexicographic order wins ties.
+    lexicographic order wins ties.  same: p1 and p2 are instances of one
+    kernel; identical kernels lump (the joint chain depends on the total
+    waves only), so every split of a total has the same profit and only the
+    balanced split of each total (b2 - b1 in {0, 1}) is searched.
     """
     s1 = ipc_homogeneous(p1.kernel, p1.max_wg_per_cu * p1.wave_per_wg, beta, beta_lds)
     s2 = ipc_homogeneous(p2.kernel, p2.max_wg_per_cu * p2.wave_per_wg, beta, beta_lds)
     best = None
     for b1, b2 in feasible_ratios(p1, p2, **kw):
+        if same and not 0 <= b2 - b1 <= 1:
+            continue
         c1, c2 = ipc_pair(p1.kernel, b1 * p1.wave_per_wg,
                           p2.kernel, b2 * p2.wave_per_wg, beta, beta_lds)
         cpv = cp((c1, c2), (s1, s2))

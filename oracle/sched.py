@@ -70,6 +70,7 @@ class Config:
     mode: str = "cp"
     cp_min: float = -1.0
     random_seed: int = 0
+    pair_same_type: bool = True
     wmax: int = 8
     vgpr_file: int = 512
     lds_cu: int = 160 * 1024
@@ -108,7 +109,8 @@ class Model:
             c = self.cfg
             self._pair[key] = markov.best_ratio(
                 self.types[t1].prof, self.types[t2].prof, c.beta, c.mode,
-                beta_lds=c.beta_lds, wmax=c.wmax, vgpr_file=c.vgpr_file, lds_cu=c.lds_cu)
+                beta_lds=c.beta_lds, same=t1 == t2, wmax=c.wmax, vgpr_file=c.vgpr_file,
+                lds_cu=c.lds_cu)
         return self._pair[key]
 
     def rate(self, t, ipc):
@@ -117,14 +119,17 @@ class Model:
 
 
 def _candidates(pending, model: Model):
-    """Step 1 of FindCoSchedule: the earliest pending job of each type (by
-    submission), less the jobs too short to pair; and the decision to run
-    the earliest pending job alone."""
+    """Step 1 of FindCoSchedule: the earliest pending job of each type (the
+    two earliest with pair_same_type: two instances of one kernel are two
+    kernels of the candidate space), by submission, less the jobs too short
+    to pair; and the decision to run the earliest pending job alone."""
     cfg = model.cfg
-    reps = {}
+    per_type = 2 if cfg.pair_same_type else 1
+    order, count = [], {}
     for j in sorted(pending, key=lambda j: j.id):
-        reps.setdefault(j.type, j)
-    order = sorted(reps.values(), key=lambda j: j.id)
+        if count.get(j.type, 0) < per_type:
+            count[j.type] = count.get(j.type, 0) + 1
+            order.append(j)
     first = order[0]
     solo = Decision(first.id, -1, model.types[first.type].prof.max_wg_per_cu,
                     0, 0.0, model.solo_ipc(first.type), 0.0)
@@ -148,10 +153,14 @@ def find_coschedule(pending, model: Model) -> Decision:
         pairs = [(a, b) for a, b in pairs if (pos[a.id], pos[b.id]) in keep]
     best = None
     for a, b in pairs:
-        r = model.pair(a.type, b.type)
+        # each unordered type pair is evaluated once, lower type first
+        sw = a.type > b.type
+        r = model.pair(b.type, a.type) if sw else model.pair(a.type, b.type)
         if r is None:
             continue
         b1, b2, val, c1, c2 = r
+        if sw:
+            b1, b2, c1, c2 = b2, b1, c2, c1
         if best is None or val > best.value:
             best = Decision(a.id, b.id, b1, b2, val, c1, c2)
     if best is None or best.value <= cfg.cp_min:

@@ -52,7 +52,7 @@ class Config(C.Structure):
                 ("lds_reserve", C.c_int32), ("max_slices", C.c_int32),
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
                 ("random_seed", C.c_uint32), ("solo_overlap", C.c_int32),
-                ("reserved", C.c_int32 * 5),
+                ("pair_same_type", C.c_int32), ("reserved", C.c_int32 * 4),
                 ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 

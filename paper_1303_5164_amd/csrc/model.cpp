@@ -233,13 +233,19 @@ void surrogate_features(const kl_profile& p, int b, int wmax, float* f) {
     f[7] = (float)b / (float)(wmax > 0 ? wmax : 8);
 }
 
+// `same`: the two are instances of one kernel type.  Identical kernels
+// lump (their joint chain depends on the total only), so every split of a
+// total gives the same profit; only the balanced split of each total
+// (b2 - b1 in {0, 1}) is searched.
 static Ratio best_ratio_with(const kl_profile& p1, const kl_profile& p2,
-                             const kl_config& cfg, double s1, double s2) {
+                             const kl_config& cfg, double s1, double s2,
+                             bool same = false) {
     Ratio best;
     double bkey0 = 0, bkey1 = 0;
     KernelModel km[2] = {kernel_model(p1, cfg), kernel_model(p2, cfg)};
     for (int b1 = 1; b1 <= p1.max_wg_per_cu; ++b1) {
         for (int b2 = 1; b2 <= p2.max_wg_per_cu; ++b2) {
+            if (same && (b2 < b1 || b2 > b1 + 1)) continue;
             if (!ratio_feasible(p1, p2, cfg, b1, b2)) continue;
             int w[2] = {b1 * p1.waves_per_simd, b2 * p2.waves_per_simd};
             double c[2];
@@ -332,7 +338,7 @@ Ratio Planner::pair(int t1, int t2) {
     }
     double s1 = solo(t1), s2 = solo(t2);
     auto t0 = std::chrono::steady_clock::now();
-    Ratio r = best_ratio_with(types_[t1], types_[t2], cfg_, s1, s2);
+    Ratio r = best_ratio_with(types_[t1], types_[t2], cfg_, s1, s2, t1 == t2);
     model_us += std::chrono::duration<double, std::micro>(
                     std::chrono::steady_clock::now() - t0).count();
     pair_[key] = r;
@@ -354,12 +360,15 @@ bool Planner::candidates(const std::vector<PendingJob>& pending, std::vector<Pen
     std::vector<PendingJob> v(pending);
     std::sort(v.begin(), v.end(),
               [](const PendingJob& a, const PendingJob& b) { return a.id < b.id; });
-    std::vector<PendingJob>& order = *out;  // earliest job of each type, by id
+    // the earliest job of each type, by id (the two earliest with
+    // pair_same_type, so that two instances of one kernel can pair)
+    std::vector<PendingJob>& order = *out;
     order.clear();
+    const int per_type = cfg_.pair_same_type ? 2 : 1;
     for (const auto& j : v) {
-        bool seen = false;
-        for (const auto& o : order) seen |= o.type == j.type;
-        if (!seen) order.push_back(j);
+        int seen = 0;
+        for (const auto& o : order) seen += o.type == j.type;
+        if (seen < per_type) order.push_back(j);
     }
     const PendingJob first = order[0];
     solo_d->j1 = first.id;
@@ -558,8 +567,15 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
                           (op.first == b.type && op.second == a.type);
             if (!listed) continue;
         }
-        Ratio r = pair(a.type, b.type);
+        // one evaluation per unordered type pair (its lower type first), so
+        // that both orders of one pair get bit-identical values
+        const bool sw = a.type > b.type;
+        Ratio r = sw ? pair(b.type, a.type) : pair(a.type, b.type);
         if (!r.ok) continue;
+        if (sw) {
+            std::swap(r.b1, r.b2);
+            std::swap(r.cipc1, r.cipc2);
+        }
         if (!have || r.value > best.value) {
             have = true;
             best.j1 = a.id;

@@ -205,6 +205,7 @@ static kl_config defaults() {
     c.use_prune = 1;
     c.ratio_mode = KL_MODE_CP;
     c.cp_min = -1.0;
+    c.pair_same_type = 1;
     c.mem_latency = 400.0;
     c.beta = 0.0;
     c.lanes = 2;
@@ -221,7 +222,8 @@ static kl_status check_cfg(const kl_config& c) {
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
-        c.solo_overlap < 0 || c.solo_overlap > 1 ||
+        c.solo_overlap < 0 || c.solo_overlap > 1 || c.pair_same_type < 0 ||
+        c.pair_same_type > 1 ||
         c.hbm_budget < 0) {
         set_error("invalid kl_config field");
         return KL_EINVAL;

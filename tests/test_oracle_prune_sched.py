@@ -128,9 +128,29 @@ def test_find_coschedule_is_brute_force_argmax():
 
 def test_single_type_runs_solo():
     types = _types()
-    model = sched.Model(types, sched.Config())
+    model = sched.Model(types, sched.Config(pair_same_type=False))
     d = sched.find_coschedule([sched.Job(3, 1, 10), sched.Job(1, 1, 10)], model)
     assert d.j2 == -1 and d.j1 == 1 and d.b1 == 8
+
+
+def test_two_instances_of_one_kernel_pair_at_a_balanced_split():
+    """With two instances of one kernel pending, the pair runs at the
+    balanced split of the best total, and its profit is the homogeneous
+    chain's at that total (identical kernels lump)."""
+    types = _types()
+    cfg = sched.Config()
+    model = sched.Model(types, cfg)
+    d = sched.find_coschedule([sched.Job(3, 1, 10), sched.Job(1, 1, 10)], model)
+    assert (d.j1, d.j2) == (1, 3) and 0 <= d.b2 - d.b1 <= 1
+    k = types[1].prof.kernel
+    tot = M.ipc_homogeneous(k, d.b1 + d.b2)
+    assert abs((d.cipc1 + d.cipc2) - tot) <= 1e-12 * tot
+    s = model.solo_ipc(1)
+    assert abs(d.value - (1.0 - s / tot)) <= 1e-12
+    # every total's balanced split was a candidate: none beats the choice
+    for t in range(2, 9):
+        c = M.ipc_homogeneous(k, t)
+        assert 1.0 - s / c <= d.value + 1e-12
 
 
 def test_simulation_executes_every_workgroup_once_and_beats_fifo():

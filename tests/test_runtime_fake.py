@@ -304,7 +304,7 @@ def test_surrogate_policy_ranks_pairs_and_runs_everything(L):
     """SURROGATE: refused without weights; with weights, candidates of the
     surviving pairs are scored in one batch and only the top pair goes to
     the Markov model; every workgroup still runs once."""
-    h = Harness(L, surrogate_topk=1, use_prune=0)
+    h = Harness(L, surrogate_topk=1, use_prune=0, pair_same_type=0)
     d = _lib.KernelDesc(b"fake2", C.addressof(L._keys[0]), 256, C.sizeof(VisitArgs), 0, None)
     h.kids.append(h.rt.register(d, dict(PROF[0], r_mem=0.05, pur=0.5, mur=0.3)))
     jobs = [h.job(32, i, kind=i % 3, us=20) for i in range(9)]

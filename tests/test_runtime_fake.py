@@ -443,3 +443,24 @@ def test_code_object_kernel_is_sliced_like_any_other(L):
     info = h.rt.kernel_info(k)
     assert info["max_wg_per_cu"] == 8
     h.close()
+
+
+def test_solo_runs_hold_the_other_lane_unless_overlap_is_set(L):
+    """A kernel run alone (here: one kernel type, same-type pairs off) makes
+    the other lane wait for it; with solo_overlap the next one starts beside
+    it.  Every workgroup runs once either way."""
+    spans = {}
+    for ov in (0, 1):
+        h = Harness(L, pair_same_type=0, solo_overlap=ov)
+        jobs = [h.job(48, i, kind=0, us=40) for i in range(4)]
+        _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+        for j in jobs:
+            h.rt.wait(j[0], 5_000_000_000)
+            assert np.all(j[1] == 1)
+        assert all(d["j2"] < 0 for d in h.rt.decisions())
+        spans[ov] = [(j[2][: j[3][0], 3].min(), j[2][: j[3][0], 4].max()) for j in jobs]
+        h.close()
+    held = spans[0]
+    assert all(held[i + 1][0] >= held[i][1] for i in range(len(held) - 1))
+    free = spans[1]
+    assert any(free[i + 1][0] < free[i][1] for i in range(len(free) - 1))

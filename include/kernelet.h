@@ -338,6 +338,14 @@ kl_status kernelet_wait(kl_runtime* rt, kl_job j, int64_t timeout_ns);
 /* Block until every launched slice has finished. */
 kl_status kernelet_synchronize(kl_runtime* rt);
 
+/* Order every later launch of the runtime after the work queued so far on
+ * `stream` (a hipStream_t of the runtime's device; NULL = the null stream):
+ * an event is recorded on it now and every lane waits for it before its
+ * next launch.  For inputs produced asynchronously, e.g. by torch on its
+ * current stream, without a host synchronisation.  KL_EHIP if the stream
+ * cannot be used. */
+kl_status kernelet_stream_barrier(kl_runtime* rt, void* stream);
+
 /* Cancel a job that has not started.  KL_ESTATE once it has. */
 kl_status kernelet_cancel(kl_runtime* rt, kl_job j);
 

@@ -152,7 +152,7 @@ SYMBOLS = [
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
     "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
-    "kernelet_set_pair_measures", "kernelet_register_image",
+    "kernelet_set_pair_measures", "kernelet_register_image", "kernelet_stream_barrier",
 ]
 
 _lib = None
@@ -202,6 +202,7 @@ def configure(L):
         "kernelet_schedule": [C.c_void_p, C.c_int, u32],
         "kernelet_wait": [C.c_void_p, i64, i64],
         "kernelet_synchronize": [C.c_void_p],
+        "kernelet_stream_barrier": [C.c_void_p, C.c_void_p],
         "kernelet_cancel": [C.c_void_p, i64],
         "kernelet_job_times": [C.c_void_p, i64, C.POINTER(i64), C.POINTER(i64),
                                C.POINTER(i64)],

@@ -1357,6 +1357,30 @@ kl_status kernelet_synchronize(kl_runtime* rt) {
     return KL_OK;
 }
 
+kl_status kernelet_stream_barrier(kl_runtime* rt, void* stream) {
+    if (!rt) {
+        set_error("null runtime");
+        return KL_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(rt->mu);
+    KL_HIP(hipSetDevice(rt->device));
+    int e = rt->pool.get();
+    if (e < 0) {
+        set_error("hipEventCreate failed");
+        return KL_EHIP;
+    }
+    // each wait takes the event as recorded now; the pool may reuse it later
+    hipError_t r = hipEventRecord(rt->pool.ev[e], (hipStream_t)stream);
+    for (size_t i = 0; r == hipSuccess && i < rt->lanes.size(); ++i)
+        r = hipStreamWaitEvent(rt->lanes[i].s, rt->pool.ev[e], 0);
+    rt->pool.unref(e);
+    if (r != hipSuccess) {
+        set_error(std::string("kernelet_stream_barrier: ") + hipGetErrorString(r));
+        return KL_EHIP;
+    }
+    return KL_OK;
+}
+
 kl_status kernelet_cancel(kl_runtime* rt, kl_job jid) {
     if (!rt) {
         set_error("null runtime");

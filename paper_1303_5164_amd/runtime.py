@@ -233,6 +233,16 @@ class Runtime:
     def synchronize(self) -> None:
         self._c("kernelet_synchronize", self.h)
 
+    def stream_barrier(self, stream=None) -> None:
+        """Order later launches after the work queued on `stream` (a raw
+        hipStream_t handle, or an object with `cuda_stream`; default:
+        torch's current stream)."""
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        h = getattr(stream, "cuda_stream", stream)
+        self._c("kernelet_stream_barrier", self.h, C.c_void_p(h))
+
     def cancel(self, job: int) -> None:
         self._c("kernelet_cancel", self.h, job)
 

@@ -167,3 +167,34 @@ def test_polynomial_and_gather_four_slices_each_markov(rtk):
     assert all(d["slice1"] in (1024, 4096) for d in dec if d["j2"] >= 0)
     assert np.array_equal(result(pa), oracle.poly_f32_horner(hp["x"], hp["coef"]))
     assert np.array_equal(result(ga), oracle.gather(hg["idx"], hg["table"]))
+
+
+def test_inputs_written_on_a_torch_stream_without_host_sync(rtk):
+    """The polynomial's inputs are written on a torch side stream behind ~30
+    ms of other work, with no host synchronisation: kernelet_stream_barrier
+    orders the runtime's launches after them, and the result is the
+    oracle's."""
+    rt, kids = rtk
+    dev = torch.device("cuda:0")
+    h = synth.poly(0, n=(1 << 20) + 256, ncoef=257)
+    x_pin = torch.from_numpy(h["x"]).pin_memory()
+    c_pin = torch.from_numpy(h["coef"]).pin_memory()
+    side = torch.cuda.Stream()
+    x = torch.empty(x_pin.numel(), dtype=torch.float32, device=dev)
+    coef = torch.empty(c_pin.numel(), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        m = torch.full((4096, 4096), 1e-3, dtype=torch.float32, device=dev)
+        for _ in range(4):
+            m = m @ m
+        x.copy_(x_pin, non_blocking=True)
+        coef.copy_(c_pin, non_blocking=True)
+    inst = W.build("poly", {"x": x, "coef": coef}, {}, dev)
+    rt.stream_barrier(side)
+    jobs = W.submit(rt, kids, inst)
+    rt.schedule("fifo", blocking=True, wait_done=True)
+    for j in jobs:
+        rt.wait(j, 60_000_000_000)
+    torch.cuda.synchronize()
+    rt.reap()
+    assert np.array_equal(result(inst), oracle.poly_f32_horner(h["x"], h["coef"]))

@@ -465,3 +465,16 @@ def test_solo_runs_hold_the_other_lane_unless_overlap_is_set(L):
     assert all(held[i + 1][0] >= held[i][1] for i in range(len(held) - 1))
     free = spans[1]
     assert any(free[i + 1][0] < free[i][1] for i in range(len(free) - 1))
+
+
+def test_stream_barrier_on_the_null_stream(L):
+    """kernelet_stream_barrier records an event on a stream and makes every
+    lane wait for it; on the (empty) null stream the jobs run at once."""
+    h = Harness(L)
+    h.rt.stream_barrier(0)
+    jobs = [h.job(32, i, kind=i % 2) for i in range(4)]
+    _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    h.close()

@@ -7,8 +7,11 @@ nnz/row, 5-point stencil 8192^2 x 10 sweeps, Black-Scholes 2^25 options,
 keys, degree-256 polynomial of 2^20 values, random gather of 2^22 from a
 2^24 table), `--instances` of each type, submitted in a seeded interleaved
 order, registered, profiled, scheduled (Markov-model greedy pairs over
-sliced, co-running kernels) and executed to completion.  The same instances
-also run under FIFO (one in-order stream, unsliced) in every step.
+sliced, co-running kernels) and executed to completion.  In every step the
+same instances also run under FIFO (one in-order stream, unsliced), the
+surrogate network deciding, OPT (the greedy algorithm on the measured
+co-run table) and plain concurrent execution on the two lanes; the legs
+alternate so that all see the same device state.
 
 Prints one JSON line (see the keys below).
 """

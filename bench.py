@@ -10,8 +10,9 @@ order, registered, profiled, scheduled (Markov-model greedy pairs over
 sliced, co-running kernels) and executed to completion.  In every step the
 same instances also run under FIFO (one in-order stream, unsliced), the
 surrogate network deciding, OPT (the greedy algorithm on the measured
-co-run table) and plain concurrent execution on the two lanes; the legs
-alternate so that all see the same device state.
+co-run table), the two earliest jobs of different kernels side by side
+(FIXED, no model) and plain concurrent execution over two and three
+streams; the legs alternate so that all see the same device state.
 
 Prints one JSON line (see the keys below).
 """
@@ -46,13 +47,14 @@ def parse():
     ap.add_argument("--surrogate-weights", default=None,
                     help="surrogate parameters (.npy); default: the packaged weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fifo,kernelet,surrogate,opt,cke",
+    ap.add_argument("--legs", default="fifo,kernelet,surrogate,opt,fixed,cke,cke3",
                     help="fifo: one in-order stream; kernelet: --policy; surrogate: the "
                          "surrogate network deciding (weights trained with measured co-runs); "
                          "opt: the greedy algorithm on measured co-run profits (the paper's "
-                         "OPT baseline); cke: plain concurrent execution on the two lanes "
-                         "(the two earliest jobs of different kernels, whole launches, no "
-                         "model)")
+                         "OPT baseline); fixed: the two earliest jobs of different kernels "
+                         "side by side, whole launches, no model; cke, cke3: plain concurrent "
+                         "execution over two or three streams (each takes the earliest "
+                         "runnable job and runs it whole; no model, no slicing)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
     ap.add_argument("--lds-reserve", type=int, default=None)
@@ -240,6 +242,7 @@ def main():
         with open(surrogate.CORUNS) as f:
             opt_rows = json.load(f)["rows"]
         rt.set_pair_measures(opt_rows, kids)
+    rt_main, kids_main = rt, kids
     setup_s = time.perf_counter() - t_setup
 
     # algorithmic work of each kernel per instance (all its launches) and its
@@ -270,9 +273,15 @@ def main():
     ktime = {k: [0.0, 0, 0] for k in W.KERNELS}
     decisions = 0
     pairs = {}
+    # plain concurrent execution over three streams runs on a runtime of its own
+    runtimes = {}
+    if "cke3" in legs:
+        r3 = K.Runtime(0, **dict(over, lanes=3))
+        runtimes["cke3"] = (r3, {k: r3.register_builtin(k, prof[k]) for k in W.KERNELS})
     for step in range(args.warmup + args.steps):
         timed_step = step >= args.warmup
         for leg in legs:
+            rt, kids = runtimes.get(leg, (rt_main, kids_main))
             for inst in insts:
                 inst.reset()
             if timed_step:
@@ -281,8 +290,8 @@ def main():
             jobs = [W.submit(rt, kids, inst) for inst in insts]
             torch.cuda.synchronize()
             t0 = time.monotonic_ns()
-            pol = {"fifo": "fifo", "surrogate": "surrogate", "opt": "opt",
-                   "cke": "fixed"}.get(leg, args.policy)
+            pol = {"fifo": "fifo", "surrogate": "surrogate", "opt": "opt", "fixed": "fixed",
+                   "cke": "concurrent", "cke3": "concurrent"}.get(leg, args.policy)
             rt.schedule(pol, blocking=True, wait_done=True)
             torch.cuda.synchronize()
             t1 = time.monotonic_ns()
@@ -311,6 +320,9 @@ def main():
             print(f"# step {step} {leg}: {(t1 - t0) / 1e6:.2f} ms", file=sys.stderr,
                   flush=True)
 
+    rt, kids = rt_main, kids_main
+    for r, _ in runtimes.values():
+        r.close()
     n_inst = len(insts)
     med = {l: float(np.median(times[l])) for l in legs}
     value = n_inst / med[main_leg]
@@ -356,7 +368,7 @@ def main():
     for l, pl in pairs.items():
         name = "coschedules" if l == main_leg else f"{l}_coschedules"
         out[name] = dict(sorted(pl.items(), key=lambda kv: -kv[1]))
-    for l in ("surrogate", "opt", "cke"):
+    for l in ("surrogate", "opt", "fixed", "cke", "cke3"):
         if l in legs and main_leg != l:
             out[f"{l}_kernels_per_s"] = round(n_inst / med[l], 3)
             if "fifo" in legs:

@@ -111,10 +111,14 @@ typedef enum {
                               measured beforehand (the paper's OPT baseline,
                               Section 5): the pair and ratio of highest
                               measured CP; needs kernelet_set_pair_measures */
-    KL_POLICY_RANDOM = 5   /* Algorithm 1 with the pair and slice ratio drawn
+    KL_POLICY_RANDOM = 5,  /* Algorithm 1 with the pair and slice ratio drawn
                               at random: one sample of the paper's Monte
                               Carlo baseline MC(s) (Section 5); draws from
                               SplitMix64 seeded by cfg.random_seed */
+    KL_POLICY_CONCURRENT = 6 /* no model, no slicing (a baseline): each of the
+                              cfg.lanes streams takes the earliest runnable
+                              job not yet launched whenever its in-flight
+                              window has room, and launches it whole */
 } kl_policy;
 
 #define KL_BLOCKING 1u           /* return when every pending job is launched */

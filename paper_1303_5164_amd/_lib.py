@@ -14,7 +14,8 @@ ERRORS = {-1: "KL_EINVAL", -2: "KL_ENOMEM", -3: "KL_EEXIST", -4: "KL_ENOTFOUND",
           -9: "KL_EINTERNAL"}
 KL_NO_JOB = -1
 
-POLICY = {"fifo": 0, "markov": 1, "surrogate": 2, "fixed": 3, "opt": 4, "random": 5}
+POLICY = {"fifo": 0, "markov": 1, "surrogate": 2, "fixed": 3, "opt": 4, "random": 5,
+          "concurrent": 6}
 KL_BLOCKING = 1
 KL_REPLAN_ON_ARRIVAL = 2
 KL_WAIT_DONE = 4

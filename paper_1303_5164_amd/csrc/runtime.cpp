@@ -501,6 +501,33 @@ static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
     return KL_OK;
 }
 
+// Plain concurrent execution (KL_POLICY_CONCURRENT): every lane, while its
+// in-flight window has room, takes the earliest runnable job not yet
+// launched and launches it whole; dependencies across lanes are kept by
+// launch_slice's event waits.
+static kl_status concurrent_step(kl_runtime* rt, bool* progressed) {
+    for (int li = 0; li < (int)rt->lanes.size(); ++li) {
+        Lane& ln = rt->lanes[li];
+        ln.dyn_lds = 0;
+        ln.job = KL_NO_JOB;
+        while ((int)ln.inflight.size() < rt->cfg.inflight) {
+            Job* next = nullptr;
+            for (kl_job id : rt->live) {
+                Job& j = rt->jobs.at(id);
+                if (runnable(j) && j.next == 0) {
+                    next = &j;
+                    break;
+                }
+            }
+            if (!next) break;
+            kl_status s = launch_slice(rt, li, next->id, next->total);
+            if (s) return s;
+            *progressed = true;
+        }
+    }
+    return KL_OK;
+}
+
 // Surrogate scores of candidate pairs: one batched inference over every
 // feasible slice ratio of every pair; a pair's score is its best predicted
 // weighted speedup.  False (the caller then evaluates every pair with the
@@ -788,8 +815,9 @@ static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
         poll_lanes(rt);
         admit(rt);
         bool progressed = false;
-        st = policy == KL_POLICY_FIFO ? fifo_step(rt, &progressed)
-                                      : markov_step(rt, policy, &progressed);
+        st = policy == KL_POLICY_FIFO         ? fifo_step(rt, &progressed)
+             : policy == KL_POLICY_CONCURRENT ? concurrent_step(rt, &progressed)
+                                              : markov_step(rt, policy, &progressed);
         if (st) break;
         if (progressed) {
             rt->cv.notify_all();
@@ -1244,7 +1272,7 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
         set_error("null runtime");
         return KL_EINVAL;
     }
-    if (policy < KL_POLICY_FIFO || policy > KL_POLICY_RANDOM) {
+    if (policy < KL_POLICY_FIFO || policy > KL_POLICY_CONCURRENT) {
         set_error("kernelet_schedule: unknown policy");
         return KL_EINVAL;
     }
@@ -1262,7 +1290,8 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
             set_error("kernelet_schedule: the OPT policy needs kernelet_set_pair_measures");
             return KL_ESTATE;
         }
-        if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED) {
+        if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED &&
+            policy != KL_POLICY_CONCURRENT) {
             for (kl_job id : rt->live) {
                 const Job& j = rt->jobs.at(id);
                 if ((j.st == J_PENDING || j.st == J_WAIT_DEP) && !rt->kernels[j.type].has_prof) {

@@ -3,7 +3,8 @@ configuration the bench times: two instances of every kernel submitted
 together and co-scheduled by the Markov policy with the measured profiles
 (contention slopes, pairing threshold, LDS-capped slices), then by the
 surrogate policy, OPT on the measured co-run table, a Monte Carlo sample
-and plain concurrent execution of whole launches.  Outputs are checked
+and plain concurrent execution of whole launches over two and three
+streams.  Outputs are checked
 against the oracle in full where that is cheap (polynomial, gather, SpMV,
 histogram) and on seeded samples the oracle computes point by point
 elsewhere (SGEMM entries, stencil points after 10 sweeps, Black-Scholes
@@ -55,7 +56,10 @@ def mix():
 
 def _run(insts, policy):
     prof = profiles.load()
-    with K.Runtime(0, surrogate_topk=0, random_seed=11, **profiles.model_config()) as rt:
+    lanes = 3 if policy == "concurrent3" else 2
+    policy = "concurrent" if policy == "concurrent3" else policy
+    with K.Runtime(0, surrogate_topk=0, random_seed=11, lanes=lanes,
+                   **profiles.model_config()) as rt:
         kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
         if policy == "surrogate":
             rt.set_surrogate(np.load(S.WEIGHTS_MEASURED))
@@ -78,11 +82,13 @@ def _out(inst, name=None):
     return inst.tensors[name or inst.result].cpu().numpy()
 
 
-@pytest.mark.parametrize("policy", ["markov", "surrogate", "opt", "random", "fixed"])
+@pytest.mark.parametrize("policy", ["markov", "surrogate", "opt", "random", "fixed",
+                                    "concurrent", "concurrent3"])
 def test_full_mix_matches_oracle(mix, policy):
     hosts, insts = mix
     dec = _run(insts, policy)
-    assert any(d["j2"] >= 0 for d in dec), "nothing was co-scheduled"
+    if not policy.startswith("concurrent"):
+        assert any(d["j2"] >= 0 for d in dec), "nothing was co-scheduled"
     rng = np.random.default_rng(7)
     by = {}
     for inst in insts:

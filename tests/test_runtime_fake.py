@@ -478,3 +478,28 @@ def test_stream_barrier_on_the_null_stream(L):
         h.rt.wait(j[0], 5_000_000_000)
         assert np.all(j[1] == 1)
     h.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 3])
+def test_concurrent_policy_runs_jobs_whole_on_every_lane(L, lanes):
+    """KL_POLICY_CONCURRENT: no model and no profile needed; jobs run whole
+    (one launch each), several at once when there are several lanes, chains
+    in order, every workgroup once."""
+    h = Harness(L, lanes=lanes)
+    d = _lib.KernelDesc(b"noprof", C.addressof(L._keys[0]), 256, C.sizeof(VisitArgs), 0, None)
+    h.kids.append(h.rt.register(d))            # no profile
+    jobs = [h.job(40, i, kind=2, us=40) for i in range(6)]
+    c1 = h.job(24, 100, kind=2, us=30)
+    c2 = h.job(24, 101, kind=2, us=30, after=c1[0])
+    _run_with_deadline(lambda: h.rt.schedule("concurrent", blocking=True, wait_done=True))
+    for j in jobs + [c1, c2]:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    assert h.rt.stats()["slices_launched"] == len(jobs) + 2
+    assert h.rt.decisions() == []
+    span = lambda j: (j[2][: j[3][0], 3].min(), j[2][: j[3][0], 4].max())
+    assert span(c2)[0] >= span(c1)[1]
+    sp = sorted(span(j) for j in jobs)
+    overlap = any(sp[i + 1][0] < sp[i][1] for i in range(len(sp) - 1))
+    assert overlap == (lanes > 1)
+    h.close()

@@ -295,3 +295,65 @@ def best_ratio(p1: KProfile, p2: KProfile, beta=0.0, mode="balanced", beta_lds=0
         if best is None or key > best[0]:
             best = (key, (b1, b2, val, c1, c2))
     return None if best is None else best[1]
+
+
+# ------------------------------------------------------------ three kernels
+def ipc_group(kernels, waves, beta: float = 0.0, beta_lds: float = 0.0):
+    """Per-kernel IPCs of any number of co-resident kernels, every one with
+    at least one wave: the heterogeneous chain of Section 4.4 over the joint
+    stalled counts of all of them (the paper notes its model covers more
+    than two kernels)."""
+    return tuple(Chain(list(kernels), list(waves), beta, beta_lds).ipc())
+
+
+def feasible_triples(p1: KProfile, p2: KProfile, p3: KProfile, wmax=8, vgpr_file=512,
+                     lds_cu=160 * 1024):
+    """(b1, b2, b3), b1 major, ascending: every kernel at least one
+    workgroup per CU, all three fitting one CU's wave slots, VGPR file and
+    LDS together."""
+    ps = (p1, p2, p3)
+    out = []
+    for bs in itertools.product(*[range(1, p.max_wg_per_cu + 1) for p in ps]):
+        if sum(b * p.wave_per_wg for b, p in zip(bs, ps)) > wmax:
+            continue
+        if sum(b * p.wave_per_wg * p.vgpr for b, p in zip(bs, ps)) > vgpr_file:
+            continue
+        if sum(b * p.lds for b, p in zip(bs, ps)) > lds_cu:
+            continue
+        out.append(bs)
+    return out
+
+
+def best_triple(p1: KProfile, p2: KProfile, p3: KProfile, beta=0.0, mode="balanced",
+                beta_lds=0.0, **kw):
+    """The pair search of best_ratio carried to three kernels: over the
+    feasible (b1, b2, b3) the objective of `mode` with the three-kernel
+    chain (cp: Eq. (1) summed over the three; balanced: 1 - max_i T_i /
+    sum_i T_is; literal: smallest spread max_i T_i - min_i T_i, ties to the
+    larger CP).  Returns (b1, b2, b3, value, c1, c2, c3) or None; the
+    first maximum in lexicographic order wins ties."""
+    ps = (p1, p2, p3)
+    solo = [ipc_homogeneous(p.kernel, p.max_wg_per_cu * p.wave_per_wg, beta, beta_lds)
+            for p in ps]
+    best = None
+    for bs in feasible_triples(p1, p2, p3, **kw):
+        c = ipc_group([p.kernel for p in ps], [b * p.wave_per_wg for b, p in zip(bs, ps)],
+                      beta, beta_lds)
+        cpv = cp(c, solo)
+        n = [b * p.wave_per_wg * p.instr_per_wave for b, p in zip(bs, ps)]
+        T = [ni / ci for ni, ci in zip(n, c)]
+        Ts = [ni / si for ni, si in zip(n, solo)]
+        if mode == "balanced":
+            key = (1.0 - max(T) / sum(Ts),)
+            val = key[0]
+        elif mode == "cp":
+            key = (cpv,)
+            val = cpv
+        elif mode == "literal":
+            key = (-(max(T) - min(T)), cpv)
+            val = cpv
+        else:
+            raise ValueError(mode)
+        if best is None or key > best[0]:
+            best = (key, (*bs, val, *c))
+    return None if best is None else best[1]

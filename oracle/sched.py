@@ -27,6 +27,10 @@ allows) only with a single pending kernel type, when no pair fits on a CU,
 or when the best profit is not above `cp_min` (default -1: a pair predicted
 to halve the two kernels' throughput).
 
+Co-schedules of three kernels (group_max 3) are an extension the paper
+leaves out (it schedules pairs, Section 4.2; its model covers more kernels,
+Section 4.4): see extend().
+
 Virtual clock: one time unit is one issue slot of one SIMD.  A kernel whose
 waves reach IPC c on each SIMD finishes n_cu * c / (waves_per_wg * I)
 workgroups per unit (I = instructions per wave).  Progress is fluid (slice
@@ -71,6 +75,7 @@ class Config:
     cp_min: float = -1.0
     random_seed: int = 0
     pair_same_type: bool = True
+    group_max: int = 2
     wmax: int = 8
     vgpr_file: int = 512
     lds_cu: int = 160 * 1024
@@ -86,6 +91,9 @@ class Decision:
     value: float
     cipc1: float
     cipc2: float
+    j3: int = -1     # a third kernel (group_max 3), -1: none
+    b3: int = 0
+    cipc3: float = 0.0
 
 
 class Model:
@@ -93,7 +101,7 @@ class Model:
 
     def __init__(self, types: dict, cfg: Config):
         self.types, self.cfg = types, cfg
-        self._pair, self._solo = {}, {}
+        self._pair, self._solo, self._triple = {}, {}, {}
 
     def solo_ipc(self, t):
         if t not in self._solo:
@@ -112,6 +120,23 @@ class Model:
                 beta_lds=c.beta_lds, same=t1 == t2, wmax=c.wmax, vgpr_file=c.vgpr_file,
                 lds_cu=c.lds_cu)
         return self._pair[key]
+
+    def triple(self, ta, tb, tc):
+        """best_triple of three distinct types, evaluated once per set of
+        types (in ascending type order) and returned in the order asked:
+        (b_a, b_b, b_c, value, c_a, c_b, c_c) or None."""
+        ts = (ta, tb, tc)
+        key = tuple(sorted(ts))
+        if key not in self._triple:
+            c = self.cfg
+            self._triple[key] = markov.best_triple(
+                *[self.types[t].prof for t in key], c.beta, c.mode, beta_lds=c.beta_lds,
+                wmax=c.wmax, vgpr_file=c.vgpr_file, lds_cu=c.lds_cu)
+        r = self._triple[key]
+        if r is None:
+            return None
+        pos = [key.index(t) for t in ts]
+        return (*[r[i] for i in pos], r[3], *[r[4 + i] for i in pos])
 
     def rate(self, t, ipc):
         p = self.types[t].prof
@@ -165,6 +190,32 @@ def find_coschedule(pending, model: Model) -> Decision:
             best = Decision(a.id, b.id, b1, b2, val, c1, c2)
     if best is None or best.value <= cfg.cp_min:
         return solo
+    return extend(best, order, model)
+
+
+def extend(pair: Decision, order, model: Model) -> Decision:
+    """Co-schedules of three kernels (an extension: the paper schedules
+    pairs, Section 4.2, while its model covers more kernels, Section 4.4):
+    with group_max 3, the chosen pair of two different types is greedily
+    joined by the candidate (submission order) of a third type whose best
+    triple ratio (markov.best_triple, all three ratios searched afresh) has
+    the largest objective, if that is above the pair's; the first such
+    candidate wins ties.  No pruning of the third."""
+    if model.cfg.group_max < 3 or pair.j2 < 0:
+        return pair
+    types = {j.id: j.type for j in order}
+    ta, tb = types[pair.j1], types[pair.j2]
+    if ta == tb:
+        return pair
+    best = pair
+    for c in order:
+        if c.type in (ta, tb):
+            continue
+        r = model.triple(ta, tb, c.type)
+        if r is None or not r[3] > best.value:
+            continue
+        best = Decision(pair.j1, pair.j2, r[0], r[1], r[3], r[4], r[5],
+                        j3=c.id, b3=r[2], cipc3=r[6])
     return best
 
 
@@ -256,8 +307,9 @@ EPS_WG = 1e-6   # residual workgroups below this count as finished
 
 
 def simulate_kernelet(jobs, types, cfg: Config, policy="markov", measures=()):
-    """Algorithm 1 on the virtual clock.  Returns (decision log, makespan,
-    completion time per job id).  policy "markov": FindCoSchedule; "opt":
+    """Algorithm 1 on the virtual clock: a co-schedule runs until the first
+    of its kernels runs out.  Returns (decision log, makespan, completion
+    time per job id).  policy "markov": FindCoSchedule; "opt":
     find_opt over `measures`; "random": find_random, the k-th decision
     taking SplitMix64 outputs 2k and 2k + 1 of the stream seeded by
     cfg.random_seed."""
@@ -287,25 +339,23 @@ def simulate_kernelet(jobs, types, cfg: Config, policy="markov", measures=()):
             j1.rem = 0.0
             done[j1.id] = t
             continue
-        j2 = byid[d.j2]
-        r1, r2 = model.rate(j1.type, d.cipc1), model.rate(j2.type, d.cipc2)
-        t1, t2 = j1.rem / r1, j2.rem / r2
-        dt = min(t1, t2)
+        group = [(byid[d.j1], d.cipc1), (byid[d.j2], d.cipc2)]
+        if d.j3 >= 0:
+            group.append((byid[d.j3], d.cipc3))
+        rates = [model.rate(j.type, c) for j, c in group]
+        times = [j.rem / r for (j, _), r in zip(group, rates)]
+        dt = min(times)
+        first = times.index(dt)   # the first of the group to run out
         t += dt
-        if t1 <= t2:
-            j2.rem -= dt * r2
-            j1.rem = 0.0
-            done[j1.id] = t
-            if j2.rem <= EPS_WG:
-                j2.rem = 0.0
-                done[j2.id] = t
-        else:
-            j1.rem -= dt * r1
-            j2.rem = 0.0
-            done[j2.id] = t
-            if j1.rem <= EPS_WG:
-                j1.rem = 0.0
-                done[j1.id] = t
+        for i, ((j, _), r) in enumerate(zip(group, rates)):
+            if i == first:
+                j.rem = 0.0
+                done[j.id] = t
+            else:
+                j.rem -= dt * r
+                if j.rem <= EPS_WG:
+                    j.rem = 0.0
+                    done[j.id] = t
     return log, t, done
 
 

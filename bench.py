@@ -11,7 +11,8 @@ sliced, co-running kernels) and executed to completion.  In every step the
 same instances also run under FIFO (one in-order stream, unsliced), the
 surrogate network deciding, OPT (the greedy algorithm on the measured
 co-run table), the two earliest jobs of different kernels side by side
-(FIXED, no model) and plain concurrent execution over two and three
+(FIXED, no model), the Markov policy with co-schedules of up to three
+kernels on three streams, and plain concurrent execution over two and three
 streams; the legs alternate so that all see the same device state.
 
 Prints one JSON line (see the keys below).
@@ -47,12 +48,14 @@ def parse():
     ap.add_argument("--surrogate-weights", default=None,
                     help="surrogate parameters (.npy); default: the packaged weights")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="fifo,kernelet,surrogate,opt,fixed,cke,cke3",
+    ap.add_argument("--legs", default="fifo,kernelet,kernelet3,surrogate,opt,fixed,cke,cke3",
                     help="fifo: one in-order stream; kernelet: --policy; surrogate: the "
                          "surrogate network deciding (weights trained with measured co-runs); "
                          "opt: the greedy algorithm on measured co-run profits (the paper's "
                          "OPT baseline); fixed: the two earliest jobs of different kernels "
-                         "side by side, whole launches, no model; cke, cke3: plain concurrent "
+                         "side by side, whole launches, no model; kernelet3: the Markov policy "
+                         "whose pairs may be joined by a third kernel, on three streams; "
+                         "cke, cke3: plain concurrent "
                          "execution over two or three streams (each takes the earliest "
                          "runnable job and runs it whole; no model, no slicing)")
     ap.add_argument("--seed", type=int, default=0)
@@ -273,11 +276,14 @@ def main():
     ktime = {k: [0.0, 0, 0] for k in W.KERNELS}
     decisions = 0
     pairs = {}
-    # plain concurrent execution over three streams runs on a runtime of its own
+    # co-schedules of three kernels and plain concurrent execution over three
+    # streams run on a runtime of their own
     runtimes = {}
-    if "cke3" in legs:
-        r3 = K.Runtime(0, **dict(over, lanes=3))
-        runtimes["cke3"] = (r3, {k: r3.register_builtin(k, prof[k]) for k in W.KERNELS})
+    if "cke3" in legs or "kernelet3" in legs:
+        r3 = K.Runtime(0, **dict(over, lanes=3, group_max=3))
+        runtimes["cke3"] = runtimes["kernelet3"] = (
+            r3, {k: r3.register_builtin(k, prof[k]) for k in W.KERNELS})
+    triples = 0
     for step in range(args.warmup + args.steps):
         timed_step = step >= args.warmup
         for leg in legs:
@@ -291,7 +297,8 @@ def main():
             torch.cuda.synchronize()
             t0 = time.monotonic_ns()
             pol = {"fifo": "fifo", "surrogate": "surrogate", "opt": "opt", "fixed": "fixed",
-                   "cke": "concurrent", "cke3": "concurrent"}.get(leg, args.policy)
+                   "kernelet3": "markov", "cke": "concurrent",
+                   "cke3": "concurrent"}.get(leg, args.policy)
             rt.schedule(pol, blocking=True, wait_done=True)
             torch.cuda.synchronize()
             t1 = time.monotonic_ns()
@@ -312,8 +319,9 @@ def main():
                 for d in rt.decisions():
                     decisions += leg == main_leg
                     if timed_step:
-                        key = kind_of.get(d["j1"], "?") + (
-                            "+" + kind_of.get(d["j2"], "?") if d["j2"] >= 0 else "")
+                        triples += leg == "kernelet3" and d["j3"] >= 0
+                        key = "+".join(kind_of.get(d[j], "?") for j in ("j1", "j2", "j3")
+                                       if d[j] >= 0)
                         pl = pairs.setdefault(leg, {})
                         pl[key] = pl.get(key, 0) + 1
             rt.reap()
@@ -321,7 +329,10 @@ def main():
                   flush=True)
 
     rt, kids = rt_main, kids_main
-    for r, _ in runtimes.values():
+    model_ms3 = None
+    if "kernelet3" in legs:
+        model_ms3 = runtimes["kernelet3"][0].stats()["model_us_total"] / 1e3
+    for r in {id(r): r for r, _ in runtimes.values()}.values():
         r.close()
     n_inst = len(insts)
     med = {l: float(np.median(times[l])) for l in legs}
@@ -368,7 +379,10 @@ def main():
     for l, pl in pairs.items():
         name = "coschedules" if l == main_leg else f"{l}_coschedules"
         out[name] = dict(sorted(pl.items(), key=lambda kv: -kv[1]))
-    for l in ("surrogate", "opt", "fixed", "cke", "cke3"):
+    if "kernelet3" in legs:
+        out["kernelet3_triples_per_step"] = triples / max(1, args.steps)
+        out["kernelet3_model_ms_total"] = round(model_ms3, 1)
+    for l in ("kernelet3", "surrogate", "opt", "fixed", "cke", "cke3"):
         if l in legs and main_leg != l:
             out[f"{l}_kernels_per_s"] = round(n_inst / med[l], 3)
             if "fifo" in legs:

@@ -174,7 +174,14 @@ typedef struct {
                               pair (the PUR/MUR rule prunes such a pair
                               unless nothing else survives); 0: only the
                               earliest instance of each type (1)          */
-    int32_t reserved[4];
+    int32_t group_max;     /* kernels per co-schedule under KL_POLICY_MARKOV:
+                              2 pairs (the paper's Algorithm 1); 3 the pair
+                              FindCoSchedule picks may be joined by a
+                              pending kernel of a third type when the
+                              three-kernel model (Section 4.4) predicts a
+                              larger objective for the best ratio of all
+                              three than for the pair; needs lanes >= 3 (2) */
+    int32_t reserved[3];
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this
@@ -215,6 +222,10 @@ typedef struct {
     double value;        /* objective of the chosen ratio */
     double cipc1, cipc2; /* predicted co-run IPCs */
     double t_us;         /* host time of the decision since the first */
+    kl_job j3;           /* a third kernel (cfg.group_max 3), else KL_NO_JOB */
+    int32_t b3;          /* its workgroups per CU */
+    uint32_t slice3;     /* its slice size in workgroups */
+    double cipc3;        /* its predicted co-run IPC */
 } kl_decision;
 
 /* ---------------------------------------------------------------- set-up */
@@ -372,6 +383,16 @@ kl_status kernelet_predict(const kl_config* cfg, const kl_profile* p1,
                            const kl_profile* p2, int32_t w1, int32_t w2,
                            double* ipc1, double* ipc2, double* cp);
 
+/* The model on n = 1..3 co-resident kernels (host): ipc[k] (host array of
+ * n) is kernel k's IPC with waves[k] >= 1 waves per SIMD beside the others
+ * (Eqs. 5-7 with one joint state per kernel; the paper notes its model covers
+ * more than two kernels), and *cp (may be NULL) Eq. (1) over the n kernels
+ * against each alone at its own full occupancy.  KL_EINVAL for n outside
+ * 1..3, a wave count outside 1..16, more than 24 waves in all, or a bad
+ * profile. */
+kl_status kernelet_predict_group(const kl_config* cfg, const kl_profile* profiles,
+                                 const int32_t* waves, int32_t n, double* ipc, double* cp);
+
 /* Best feasible slice ratio of a pair (Section 4.4, balanced slice ratio):
  * writes b1, b2 (workgroups per CU), the objective and the two IPCs.
  * KL_ENOTFOUND when no ratio fits the CU's resources. */
@@ -382,12 +403,14 @@ kl_status kernelet_best_ratio(const kl_config* cfg, const kl_profile* p1,
 /* Greedy co-scheduling on the virtual clock of the model (no GPU): runs
  * Algorithm 1 (or FIFO if policy == KL_POLICY_FIFO) over n jobs given by
  * kernel profile index, workgroup count and arrival time; writes up to
- * max_dec decisions (j1/j2 are job indices), their count, the makespan and
+ * max_dec decisions (j1/j2/j3 are job indices), their count, the makespan and
  * each job's completion time (host arrays of n).  KL_POLICY_OPT takes its
  * pairs, ratios and co-run rates from `measures` (n_measures rows whose a
  * and b are profile indices; may be NULL otherwise); every other policy
- * takes co-run rates from the model.  Used to test the scheduler against
- * the oracle and to predict a plan's gain.  KL_EINVAL for a policy other
+ * takes co-run rates from the model; with cfg.group_max 3 the MARKOV policy
+ * may co-schedule three kernels (no lanes needed here), and a co-schedule
+ * runs until the first of its kernels runs out.  Used to test the
+ * scheduler against the oracle and to predict a plan's gain.  KL_EINVAL for a policy other
  * than FIFO, MARKOV, OPT and RANDOM or a measure naming no profile. */
 kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
                             int32_t n_profiles, const int32_t* job_profile,

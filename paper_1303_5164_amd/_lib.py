@@ -53,7 +53,8 @@ class Config(C.Structure):
                 ("lds_reserve", C.c_int32), ("max_slices", C.c_int32),
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
                 ("random_seed", C.c_uint32), ("solo_overlap", C.c_int32),
-                ("pair_same_type", C.c_int32), ("reserved", C.c_int32 * 4),
+                ("pair_same_type", C.c_int32), ("group_max", C.c_int32),
+                ("reserved", C.c_int32 * 3),
                 ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 
@@ -76,7 +77,8 @@ class Decision(C.Structure):
     _fields_ = [("j1", C.c_int64), ("j2", C.c_int64), ("b1", C.c_int32),
                 ("b2", C.c_int32), ("slice1", C.c_uint32), ("slice2", C.c_uint32),
                 ("value", C.c_double), ("cipc1", C.c_double), ("cipc2", C.c_double),
-                ("t_us", C.c_double)]
+                ("t_us", C.c_double), ("j3", C.c_int64), ("b3", C.c_int32),
+                ("slice3", C.c_uint32), ("cipc3", C.c_double)]
 
 
 # ------------------------------------------------- workload argument blocks
@@ -149,7 +151,7 @@ SYMBOLS = [
     "kernelet_submit", "kernelet_submit_chain", "kernelet_slice", "kernelet_job_occupancy", "kernelet_schedule",
     "kernelet_wait",
     "kernelet_synchronize", "kernelet_cancel", "kernelet_job_times", "kernelet_reap",
-    "kernelet_predict", "kernelet_best_ratio", "kernelet_simulate", "kernelet_stats",
+    "kernelet_predict", "kernelet_predict_group", "kernelet_best_ratio", "kernelet_simulate", "kernelet_stats",
     "kernelet_decisions", "kernelet_time_kernel", "kernelet_kernel_time",
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
     "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
@@ -210,6 +212,8 @@ def configure(L):
         "kernelet_reap": [C.c_void_p],
         "kernelet_predict": [C.POINTER(Config), C.POINTER(Profile), C.POINTER(Profile),
                              i32, i32, PD, PD, PD],
+        "kernelet_predict_group": [C.POINTER(Config), C.POINTER(Profile), C.POINTER(i32),
+                                   i32, PD, PD],
         "kernelet_best_ratio": [C.POINTER(Config), C.POINTER(Profile), C.POINTER(Profile),
                                 C.POINTER(i32), C.POINTER(i32), PD, PD, PD],
         "kernelet_simulate": [C.POINTER(Config), C.POINTER(Profile), i32,

@@ -104,95 +104,111 @@ void stationary(const std::vector<double>& P, int N, std::vector<double>& pi) {
 void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
                double beta_lds, double* ipc_out) {
     const double beta[2] = {beta_hbm, beta_lds};
-    KStates ks[2] = {enumerate(w[0], km[0].nclass),
-                     enumerate(nk > 1 ? w[1] : 0, nk > 1 ? km[1].nclass : 1)};
-    const int S1 = ks[0].size(), S2 = nk > 1 ? ks[1].size() : 1;
-    const int N = S1 * S2;
+    // kernels beyond nk have one state (no waves) and move with probability 1
+    KStates ks[3];
+    int S[3];
+    for (int k = 0; k < 3; ++k) {
+        ks[k] = enumerate(k < nk ? w[k] : 0, k < nk ? km[k].nclass : 1);
+        S[k] = ks[k].size();
+    }
+    const int N = S[0] * S[1] * S[2];
     std::vector<double> P((size_t)N * N, 0.0);
-    std::vector<double> mv[2] = {std::vector<double>(S1), std::vector<double>(S2)};
-    for (int i1 = 0; i1 < S1; ++i1) {
-        for (int i2 = 0; i2 < S2; ++i2) {
-            int nst[2][2] = {{ks[0].n0[i1], ks[0].n1[i1]},
-                             {nk > 1 ? ks[1].n0[i2] : 0, nk > 1 ? ks[1].n1[i2] : 0}};
-            int ready[2];
-            double outst[2] = {0.0, 0.0};  // requests held in each pool
-            int rtot = 0;
-            for (int k = 0; k < nk; ++k) {
-                ready[k] = w[k] - nst[k][0] - nst[k][1];
-                rtot += ready[k];
-                for (int c = 0; c < km[k].nclass; ++c)
-                    outst[km[k].cls[c].pool] += nst[k][c] * km[k].cls[c].req;
-            }
-            double D = std::max(rtot, 1);
-            for (int k = 0; k < nk; ++k) {
-                const KernelModel& m = km[k];
-                double q[2] = {0, 0};
-                for (int c = 0; c < m.nclass; ++c) {
-                    const StallClass& sc = m.cls[c];
-                    double lat = sc.req > 0 ? sc.base + beta[sc.pool] * outst[sc.pool] : sc.base;
-                    q[c] = std::min(1.0, D / lat);
+    std::vector<double> mv[3] = {std::vector<double>(S[0]), std::vector<double>(S[1]),
+                                 std::vector<double>(S[2], 1.0)};
+    int ix[3];
+    for (ix[0] = 0; ix[0] < S[0]; ++ix[0]) {
+        for (ix[1] = 0; ix[1] < S[1]; ++ix[1]) {
+            for (ix[2] = 0; ix[2] < S[2]; ++ix[2]) {
+                int nst[3][2];
+                int ready[3] = {0, 0, 0};
+                double outst[2] = {0.0, 0.0};  // requests held in each pool
+                int rtot = 0;
+                for (int k = 0; k < 3; ++k) {
+                    nst[k][0] = ks[k].n0[ix[k]];
+                    nst[k][1] = ks[k].n1[ix[k]];
                 }
-                std::vector<double>& out = mv[k];
-                std::fill(out.begin(), out.end(), 0.0);
-                int r = ready[k];
-                int n0 = nst[k][0], n1 = nst[k][1];
-                if (m.nclass == 1) {
-                    for (int a = 0; a <= r; ++a) {
-                        double pn = binom(r, a, m.cls[0].r);
-                        if (pn == 0.0) continue;
-                        for (int b = 0; b <= n0; ++b) {
-                            double pb = pn * binom(n0, b, q[0]);
-                            if (pb == 0.0) continue;
-                            out[ks[k].at(n0 - b + a, 0)] += pb;
-                        }
+                for (int k = 0; k < nk; ++k) {
+                    ready[k] = w[k] - nst[k][0] - nst[k][1];
+                    rtot += ready[k];
+                    for (int c = 0; c < km[k].nclass; ++c)
+                        outst[km[k].cls[c].pool] += nst[k][c] * km[k].cls[c].req;
+                }
+                double D = std::max(rtot, 1);
+                for (int k = 0; k < nk; ++k) {
+                    const KernelModel& m = km[k];
+                    double q[2] = {0, 0};
+                    for (int c = 0; c < m.nclass; ++c) {
+                        const StallClass& sc = m.cls[c];
+                        double lat =
+                            sc.req > 0 ? sc.base + beta[sc.pool] * outst[sc.pool] : sc.base;
+                        q[c] = std::min(1.0, D / lat);
                     }
-                } else {
-                    double p0 = m.cls[0].r, p1 = m.cls[1].r, pr = 1.0 - p0 - p1;
-                    for (int a0 = 0; a0 <= r; ++a0) {
-                        for (int a1 = 0; a0 + a1 <= r; ++a1) {
-                            int rest = r - a0 - a1;
-                            double c = kFact[r] / (kFact[a0] * kFact[a1] * kFact[rest]);
-                            double pn = c * std::pow(pr, rest) * std::pow(p0, a0) *
-                                        std::pow(p1, a1);
+                    std::vector<double>& out = mv[k];
+                    std::fill(out.begin(), out.end(), 0.0);
+                    int r = ready[k];
+                    int n0 = nst[k][0], n1 = nst[k][1];
+                    if (m.nclass == 1) {
+                        for (int a = 0; a <= r; ++a) {
+                            double pn = binom(r, a, m.cls[0].r);
                             if (pn == 0.0) continue;
-                            for (int b0 = 0; b0 <= n0; ++b0) {
-                                double pb0 = pn * binom(n0, b0, q[0]);
-                                if (pb0 == 0.0) continue;
-                                for (int b1 = 0; b1 <= n1; ++b1) {
-                                    double pb = pb0 * binom(n1, b1, q[1]);
-                                    if (pb == 0.0) continue;
-                                    out[ks[k].at(n0 - b0 + a0, n1 - b1 + a1)] += pb;
+                            for (int b = 0; b <= n0; ++b) {
+                                double pb = pn * binom(n0, b, q[0]);
+                                if (pb == 0.0) continue;
+                                out[ks[k].at(n0 - b + a, 0)] += pb;
+                            }
+                        }
+                    } else {
+                        double p0 = m.cls[0].r, p1 = m.cls[1].r, pr = 1.0 - p0 - p1;
+                        for (int a0 = 0; a0 <= r; ++a0) {
+                            for (int a1 = 0; a0 + a1 <= r; ++a1) {
+                                int rest = r - a0 - a1;
+                                double c = kFact[r] / (kFact[a0] * kFact[a1] * kFact[rest]);
+                                double pn = c * std::pow(pr, rest) * std::pow(p0, a0) *
+                                            std::pow(p1, a1);
+                                if (pn == 0.0) continue;
+                                for (int b0 = 0; b0 <= n0; ++b0) {
+                                    double pb0 = pn * binom(n0, b0, q[0]);
+                                    if (pb0 == 0.0) continue;
+                                    for (int b1 = 0; b1 <= n1; ++b1) {
+                                        double pb = pb0 * binom(n1, b1, q[1]);
+                                        if (pb == 0.0) continue;
+                                        out[ks[k].at(n0 - b0 + a0, n1 - b1 + a1)] += pb;
+                                    }
                                 }
                             }
                         }
                     }
                 }
-            }
-            double* row = &P[(size_t)(i1 * S2 + i2) * N];
-            if (nk == 1) {
-                for (int j1 = 0; j1 < S1; ++j1) row[j1] = mv[0][j1];
-            } else {
-                for (int j1 = 0; j1 < S1; ++j1) {
-                    if (mv[0][j1] == 0.0) continue;
-                    for (int j2 = 0; j2 < S2; ++j2)
-                        row[j1 * S2 + j2] = mv[0][j1] * mv[1][j2];
+                // independent moves given the state: the product over kernels
+                double* row = &P[(size_t)((ix[0] * S[1] + ix[1]) * S[2] + ix[2]) * N];
+                for (int j0 = 0; j0 < S[0]; ++j0) {
+                    if (mv[0][j0] == 0.0) continue;
+                    for (int j1 = 0; j1 < S[1]; ++j1) {
+                        const double p01 = nk > 1 ? mv[0][j0] * mv[1][j1] : mv[0][j0];
+                        if (p01 == 0.0) continue;
+                        double* r2 = row + (size_t)(j0 * S[1] + j1) * S[2];
+                        if (nk > 2)
+                            for (int j2 = 0; j2 < S[2]; ++j2) r2[j2] = p01 * mv[2][j2];
+                        else
+                            r2[0] = p01;
+                    }
                 }
             }
         }
     }
     std::vector<double> pi;
     stationary(P, N, pi);
-    double den = 0.0, num[2] = {0.0, 0.0};
-    for (int i1 = 0; i1 < S1; ++i1) {
-        for (int i2 = 0; i2 < S2; ++i2) {
-            double g = pi[i1 * S2 + i2];
-            int r1 = w[0] - ks[0].n0[i1] - ks[0].n1[i1];
-            int r2 = nk > 1 ? w[1] - ks[1].n0[i2] - ks[1].n1[i2] : 0;
-            den += g * std::max(r1 + r2, 1);
-            num[0] += g * r1;
-            num[1] += g * r2;
-        }
-    }
+    double den = 0.0, num[3] = {0.0, 0.0, 0.0};
+    for (ix[0] = 0; ix[0] < S[0]; ++ix[0])
+        for (ix[1] = 0; ix[1] < S[1]; ++ix[1])
+            for (ix[2] = 0; ix[2] < S[2]; ++ix[2]) {
+                double g = pi[(ix[0] * S[1] + ix[1]) * S[2] + ix[2]];
+                int r[3] = {0, 0, 0};
+                for (int k = 0; k < nk; ++k)
+                    r[k] = w[k] - ks[k].n0[ix[k]] - ks[k].n1[ix[k]];
+                den += g * std::max(r[0] + r[1] + r[2], 1);
+                for (int k = 0; k < 3; ++k) num[k] += g * r[k];
+            }
     for (int k = 0; k < nk; ++k) ipc_out[k] = num[k] / den;
 }
 
@@ -288,6 +304,68 @@ Ratio best_ratio(const kl_profile& p1, const kl_profile& p2, const kl_config& cf
     return best_ratio_with(p1, p2, cfg, solo_ipc(p1, cfg), solo_ipc(p2, cfg));
 }
 
+bool triple_feasible(const kl_profile* const p[3], const kl_config& cfg, const int* b) {
+    int waves = 0;
+    int64_t vgpr = 0, lds = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (b[k] < 1 || b[k] > p[k]->max_wg_per_cu) return false;
+        const int w = b[k] * p[k]->waves_per_simd;
+        waves += w;
+        vgpr += (int64_t)w * p[k]->vgpr;
+        lds += (int64_t)b[k] * p[k]->lds_bytes;
+    }
+    return waves <= cfg.wmax && vgpr <= cfg.vgpr_file && lds <= cfg.lds_cu;
+}
+
+Triple best_triple(const kl_profile* const p[3], const double* solo, const kl_config& cfg) {
+    Triple best;
+    double bkey0 = 0, bkey1 = 0;
+    KernelModel km[3] = {kernel_model(*p[0], cfg), kernel_model(*p[1], cfg),
+                         kernel_model(*p[2], cfg)};
+    int b[3];
+    for (b[0] = 1; b[0] <= p[0]->max_wg_per_cu; ++b[0])
+        for (b[1] = 1; b[1] <= p[1]->max_wg_per_cu; ++b[1])
+            for (b[2] = 1; b[2] <= p[2]->max_wg_per_cu; ++b[2]) {
+                if (!triple_feasible(p, cfg, b)) continue;
+                int w[3];
+                for (int k = 0; k < 3; ++k) w[k] = b[k] * p[k]->waves_per_simd;
+                double c[3];
+                chain_ipc(km, w, 3, cfg.beta, cfg.beta_lds, c);
+                const double cpv = cp_value(c, solo, 3);
+                double T[3], Ts[3];
+                for (int k = 0; k < 3; ++k) {
+                    const double n = (double)w[k] * p[k]->instr_per_wave;
+                    T[k] = n / c[k];
+                    Ts[k] = n / solo[k];
+                }
+                const double tmax = std::max(std::max(T[0], T[1]), T[2]);
+                const double tmin = std::min(std::min(T[0], T[1]), T[2]);
+                double k0, k1 = 0, val;
+                if (cfg.ratio_mode == KL_MODE_BALANCED) {
+                    k0 = 1.0 - tmax / (Ts[0] + Ts[1] + Ts[2]);
+                    val = k0;
+                } else if (cfg.ratio_mode == KL_MODE_CP) {
+                    k0 = cpv;
+                    val = cpv;
+                } else {
+                    k0 = -(tmax - tmin);
+                    k1 = cpv;
+                    val = cpv;
+                }
+                if (!best.ok || k0 > bkey0 || (k0 == bkey0 && k1 > bkey1)) {
+                    best.ok = true;
+                    for (int k = 0; k < 3; ++k) {
+                        best.b[k] = b[k];
+                        best.cipc[k] = c[k];
+                    }
+                    best.value = val;
+                    bkey0 = k0;
+                    bkey1 = k1;
+                }
+            }
+    return best;
+}
+
 bool pair_pruned(const kl_profile& a, const kl_profile& b, double ap, double am) {
     return std::fabs(a.pur - b.pur) < ap && std::fabs(a.mur - b.mur) < am;
 }
@@ -301,6 +379,7 @@ void Planner::set_types(const std::vector<kl_profile>& t) {
     types_ = t;
     solo_.clear();
     pair_.clear();
+    triple_.clear();
     scored_.clear();
 }
 
@@ -310,6 +389,7 @@ void Planner::set_type(int idx, const kl_profile& p) {
     types_[idx] = p;
     solo_.clear();
     pair_.clear();
+    triple_.clear();
     scored_.clear();
 }
 
@@ -343,6 +423,60 @@ Ratio Planner::pair(int t1, int t2) {
                     std::chrono::steady_clock::now() - t0).count();
     pair_[key] = r;
     return r;
+}
+
+Triple Planner::triple(int t1, int t2, int t3) {
+    int ts[3] = {t1, t2, t3};
+    int key[3] = {t1, t2, t3};
+    std::sort(key, key + 3);
+    auto k = std::make_tuple(key[0], key[1], key[2]);
+    auto it = triple_.find(k);
+    Triple r;
+    if (it != triple_.end()) {
+        ++cache_hits;
+        r = it->second;
+    } else {
+        const kl_profile* p[3] = {&types_[key[0]], &types_[key[1]], &types_[key[2]]};
+        double s[3] = {solo(key[0]), solo(key[1]), solo(key[2])};
+        auto t0 = std::chrono::steady_clock::now();
+        r = best_triple(p, s, cfg_);
+        model_us += std::chrono::duration<double, std::micro>(
+                        std::chrono::steady_clock::now() - t0).count();
+        triple_[k] = r;
+    }
+    Triple out = r;
+    for (int i = 0; i < 3; ++i) {
+        const int pos = (int)(std::find(key, key + 3, ts[i]) - key);
+        out.b[i] = r.b[pos];
+        out.cipc[i] = r.cipc[pos];
+    }
+    return out;
+}
+
+Decision Planner::extend(const Decision& pair, const std::vector<PendingJob>& order) {
+    if (cfg_.group_max < 3 || pair.j2 < 0) return pair;
+    int ta = -1, tb = -1;
+    for (const auto& j : order) {
+        if (j.id == pair.j1) ta = j.type;
+        if (j.id == pair.j2) tb = j.type;
+    }
+    if (ta < 0 || tb < 0 || ta == tb) return pair;
+    Decision best = pair;
+    for (const auto& c : order) {
+        if (c.type == ta || c.type == tb) continue;
+        Triple r = triple(ta, tb, c.type);
+        if (!r.ok || !(r.value > best.value)) continue;
+        best = pair;
+        best.b1 = r.b[0];
+        best.b2 = r.b[1];
+        best.b3 = r.b[2];
+        best.j3 = c.id;
+        best.value = r.value;
+        best.cipc1 = r.cipc[0];
+        best.cipc2 = r.cipc[1];
+        best.cipc3 = r.cipc[2];
+    }
+    return best;
 }
 
 Decision Planner::find(const std::vector<PendingJob>& pending,
@@ -588,7 +722,8 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
         }
     }
     if (!have || best.value <= cfg_.cp_min) return solo_d;
-    return best;
+    // the surrogate's policy ranks pairs only
+    return score ? best : extend(best, order);
 }
 
 }  // namespace kl

@@ -38,7 +38,8 @@ struct KernelModel {
 // class 1 the compute stall when r_comp > 0.
 KernelModel kernel_model(const kl_profile& p, const kl_config& cfg);
 
-// Per-kernel IPCs of up to two co-resident kernels with w[k] waves each.
+// Per-kernel IPCs of one to three co-resident kernels (nk), kernel k with
+// w[k] >= 1 waves per SIMD.
 void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
                double beta_lds, double* ipc_out);
 
@@ -53,6 +54,24 @@ struct Ratio {
 double solo_ipc(const kl_profile& p, const kl_config& cfg);
 Ratio best_ratio(const kl_profile& p1, const kl_profile& p2,
                  const kl_config& cfg);
+
+// A slice ratio of three kernels (workgroups per CU of each), the objective
+// of cfg.ratio_mode carried to three kernels, and the co-run IPCs.
+struct Triple {
+    bool ok = false;
+    int b[3] = {0, 0, 0};
+    double value = 0, cipc[3] = {0, 0, 0};
+};
+
+// Whether b[k] workgroups per CU of the three kernels fit on one CU
+// together: wave slots per SIMD, VGPR file and LDS.
+bool triple_feasible(const kl_profile* const p[3], const kl_config& cfg, const int* b);
+
+// Best feasible (b1, b2, b3) of three kernels given their solo IPCs, in
+// lexicographic order (the first maximum wins): mode CP maximises Eq. (1)
+// over the three; BALANCED 1 - max_k T_k / sum_k T_k,solo; LITERAL the
+// smallest spread max_k T_k - min_k T_k, ties to the larger CP.
+Triple best_triple(const kl_profile* const p[3], const double* solo, const kl_config& cfg);
 
 bool pair_pruned(const kl_profile& a, const kl_profile& b, double ap,
                  double am);
@@ -86,6 +105,9 @@ struct Decision {
     int64_t j1 = -1, j2 = -1;  // j2 = -1: solo
     int b1 = 0, b2 = 0;
     double value = 0, cipc1 = 0, cipc2 = 0;
+    int64_t j3 = -1;  // a third kernel (cfg.group_max 3); -1: none
+    int b3 = 0;
+    double cipc3 = 0;
 };
 
 // Caches solo IPCs and per-type-pair ratio searches; thread-safe.
@@ -97,6 +119,9 @@ class Planner {
     const kl_config& cfg() const { return cfg_; }
     double solo(int t);
     Ratio pair(int t1, int t2);
+    // best_triple of three distinct types, searched once per set of types
+    // (in ascending type order) and returned in the order asked.
+    Triple triple(int t1, int t2, int t3);
     // FindCoSchedule over pending jobs (any order); `only_pairs` (optional)
     // restricts the search to the listed type pairs.
     Decision find(const std::vector<PendingJob>& pending,
@@ -142,6 +167,10 @@ class Planner {
     // false when fewer than two such types are pending.
     bool candidates(const std::vector<PendingJob>& pending, std::vector<PendingJob>* order,
                     Decision* solo_d);
+    // cfg.group_max 3: the pair of two different types joined by the
+    // candidate of a third type whose best triple ratio has the largest
+    // objective, if above the pair's (submission order breaks ties).
+    Decision extend(const Decision& pair, const std::vector<PendingJob>& order);
     Decision search(const std::vector<PendingJob>& pending,
                     const std::vector<std::pair<int, int>>* only_pairs, int k,
                     const Scorer* score);
@@ -149,6 +178,7 @@ class Planner {
     std::vector<kl_profile> types_;
     std::map<int, double> solo_;
     std::map<std::pair<int, int>, Ratio> pair_;
+    std::map<std::tuple<int, int, int>, Triple> triple_;
     // surrogate score and best ratio per ordered type pair
     std::map<std::pair<int, int>, std::pair<double, std::pair<int, int>>> scored_;
     std::map<std::pair<int, int>, std::vector<Measure>> meas_;

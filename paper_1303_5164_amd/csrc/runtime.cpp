@@ -174,7 +174,7 @@ struct kl_runtime {
     int64_t t0_dec = 0;
     // co-schedule currently issued
     bool cs_active = false;
-    kl_job cs_job[2] = {KL_NO_JOB, KL_NO_JOB};
+    kl_job cs_job[3] = {KL_NO_JOB, KL_NO_JOB, KL_NO_JOB};
     // launch timing
     std::deque<kl::TimedLaunch> timed;
     std::vector<hipEvent_t> tev_free;
@@ -206,6 +206,7 @@ static kl_config defaults() {
     c.ratio_mode = KL_MODE_CP;
     c.cp_min = -1.0;
     c.pair_same_type = 1;
+    c.group_max = 2;
     c.mem_latency = 400.0;
     c.beta = 0.0;
     c.lanes = 2;
@@ -223,7 +224,7 @@ static kl_status check_cfg(const kl_config& c) {
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
         c.solo_overlap < 0 || c.solo_overlap > 1 || c.pair_same_type < 0 ||
-        c.pair_same_type > 1 ||
+        c.pair_same_type > 1 || c.group_max < 2 || c.group_max > 3 ||
         c.hbm_budget < 0) {
         set_error("invalid kl_config field");
         return KL_EINVAL;
@@ -337,20 +338,21 @@ static void poll_lanes(kl_runtime* rt) {
 static const int64_t kLdsPerWg = 65536;
 
 // Dynamic LDS for kernel `kt` in a co-schedule where it runs at b_self
-// workgroups per CU beside a partner at b_other (static LDS other_lds).
-static uint32_t dyn_lds_for(kl_runtime* rt, const KernelType& kt, int b_self, int b_other,
-                            const KernelType* other, bool capped) {
+// workgroups per CU beside partners at b_others workgroups per CU in all,
+// whose workgroups hold others_lds bytes of static LDS per CU in all.
+static uint32_t dyn_lds_for(kl_runtime* rt, const KernelType& kt, int b_self, int b_others,
+                            int64_t others_lds, bool capped) {
     const int64_t lds = rt->cfg.lds_cu;
     int64_t per = 0;
     if (rt->cfg.lds_reserve == 1) {
-        if (b_self + b_other <= 0) return 0;
-        per = lds / (b_self + b_other) - kt.static_lds;
+        if (b_self + b_others <= 0) return 0;
+        per = lds / (b_self + b_others) - kt.static_lds;
     } else if (rt->cfg.lds_reserve == 2) {
         if (!capped || b_self < 1) return 0;
         // (b_self + 1) workgroups must not fit, b_self must leave room for the
-        // partner's static LDS
+        // partners' static LDS
         int64_t total = lds / (b_self + 1) + 256;
-        int64_t room = lds - (other ? (int64_t)b_other * other->static_lds : 0);
+        int64_t room = lds - others_lds;
         if ((int64_t)b_self * total > room || total > kLdsPerWg) return 0;  // cannot cap
         per = total - kt.static_lds;
     } else {
@@ -453,18 +455,21 @@ static bool runnable(const Job& j) {
     return j.admitted && j.st == J_PENDING && j.next < j.total;
 }
 
-static void log_decision(kl_runtime* rt, const Decision& d, uint32_t s1, uint32_t s2,
-                         double us) {
+static void log_decision(kl_runtime* rt, const Decision& d, const uint32_t* sl, double us) {
     kl_decision x{};
     x.j1 = d.j1;
     x.j2 = d.j2;
+    x.j3 = d.j3;
     x.b1 = d.b1;
     x.b2 = d.b2;
-    x.slice1 = s1;
-    x.slice2 = s2;
+    x.b3 = d.b3;
+    x.slice1 = sl[0];
+    x.slice2 = sl[1];
+    x.slice3 = sl[2];
     x.value = d.value;
     x.cipc1 = d.cipc1;
     x.cipc2 = d.cipc2;
+    x.cipc3 = d.cipc3;
     if (rt->declog.empty() && rt->t0_dec == 0) rt->t0_dec = now_ns();
     x.t_us = (now_ns() - rt->t0_dec) / 1e3;
     rt->declog.push_back(x);
@@ -613,7 +618,7 @@ static void decide(kl_runtime* rt, kl_policy policy) {
         if (runnable(j)) pend.push_back({id, j.type, (double)(j.total - j.next)});
     }
     rt->cs_active = false;
-    rt->cs_job[0] = rt->cs_job[1] = KL_NO_JOB;
+    rt->cs_job[0] = rt->cs_job[1] = rt->cs_job[2] = KL_NO_JOB;
     if (pend.empty()) {
         for (auto& ln : rt->lanes) ln.job = KL_NO_JOB;
         return;
@@ -659,65 +664,76 @@ static void decide(kl_runtime* rt, kl_policy policy) {
     rt->stats.model_us_total = rt->planner->model_us;
     rt->stats.cache_hits = rt->planner->cache_hits;
 
-    kl_job want[2] = {d.j1, d.j2};
-    int lane_of[2] = {-1, -1};
-    const int nl = std::min<int>((int)rt->lanes.size(), 2);
-    for (int k = 0; k < 2; ++k)
+    // one lane per kernel of the co-schedule; a kernel keeps the lane it
+    // already runs on
+    const int ng = d.j2 == KL_NO_JOB ? 1 : (d.j3 == KL_NO_JOB ? 2 : 3);
+    const kl_job want[3] = {d.j1, ng > 1 ? d.j2 : KL_NO_JOB, ng > 2 ? d.j3 : KL_NO_JOB};
+    const int bw[3] = {d.b1, d.b2, d.b3};
+    int lane_of[3] = {-1, -1, -1};
+    const int nl = std::min<int>((int)rt->lanes.size(), 3);
+    auto taken = [&](int li) {
+        return li == lane_of[0] || li == lane_of[1] || li == lane_of[2];
+    };
+    for (int k = 0; k < ng; ++k)
         for (int li = 0; li < nl; ++li)
-            if (want[k] != KL_NO_JOB && rt->lanes[li].job == want[k]) lane_of[k] = li;
-    for (int k = 0; k < 2; ++k) {
-        if (want[k] == KL_NO_JOB || lane_of[k] >= 0) continue;
+            if (rt->lanes[li].job == want[k]) lane_of[k] = li;
+    for (int k = 0; k < ng; ++k) {
+        if (lane_of[k] >= 0) continue;
         int best = -1;
         for (int li = 0; li < nl; ++li) {
-            if (li == lane_of[0] || li == lane_of[1]) continue;
+            if (taken(li)) continue;
             if (best < 0 || rt->lanes[li].inflight.size() < rt->lanes[best].inflight.size())
                 best = li;
         }
         lane_of[k] = best;
     }
     for (int li = 0; li < (int)rt->lanes.size(); ++li)
-        if (li != lane_of[0] && li != lane_of[1]) rt->lanes[li].job = KL_NO_JOB;
+        if (!taken(li)) rt->lanes[li].job = KL_NO_JOB;
 
-    uint32_t sl[2] = {0, 0};
-    const bool solo = d.j2 == KL_NO_JOB || lane_of[1] < 0;
-    // the kernel capped by LDS reservation (mode 2): the larger register
-    // footprint at its target occupancy
+    uint32_t sl[3] = {0, 0, 0};
+    const bool solo = ng == 1 || lane_of[1] < 0;
+    const KernelType* kts[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < ng; ++k) kts[k] = &rt->kernels[rt->jobs.at(want[k]).type];
+    // the kernel capped by LDS reservation (mode 2): the largest register
+    // footprint at its target occupancy (the first on ties)
     int capped = -1;
-    const KernelType* kts[2] = {nullptr, nullptr};
-    for (int k = 0; k < 2; ++k)
-        if (want[k] != KL_NO_JOB) kts[k] = &rt->kernels[rt->jobs.at(want[k]).type];
     if (!solo) {
-        auto foot = [&](int k) {
-            const KernelType* t = kts[k];
-            int v = t->has_prof ? t->prof.vgpr : 0;
-            return (int64_t)(k == 0 ? d.b1 : d.b2) * v;
-        };
-        capped = foot(0) >= foot(1) ? 0 : 1;
+        int64_t top = -1;
+        for (int k = 0; k < ng; ++k) {
+            const int64_t f = (int64_t)bw[k] * (kts[k]->has_prof ? kts[k]->prof.vgpr : 0);
+            if (f > top) top = f, capped = k;
+        }
     }
-    for (int k = 0; k < 2; ++k) {
-        if (want[k] == KL_NO_JOB || lane_of[k] < 0) continue;
+    for (int k = 0; k < ng; ++k) {
+        if (lane_of[k] < 0) continue;
         Job& j = rt->jobs.at(want[k]);
         Lane& ln = rt->lanes[lane_of[k]];
         ln.job = want[k];
-        const KernelType& kt = rt->kernels[j.type];
+        const KernelType& kt = *kts[k];
         if (solo) {
             // a co-schedule of one kernel: its residual in one launch at full
             // occupancy; the other lanes wait for it before their next launch
             sl[k] = j.fixed_slice ? j.fixed_slice : j.total - j.next;
             // a requested occupancy below the kernel's own is held by LDS
             ln.dyn_lds = j.occ > 0 && rt->cfg.lds_reserve == 2
-                             ? dyn_lds_for(rt, kt, j.occ, 0, nullptr, true)
+                             ? dyn_lds_for(rt, kt, j.occ, 0, 0, true)
                              : 0;
         } else {
-            const int bs = k == 0 ? d.b1 : d.b2, bo = k == 0 ? d.b2 : d.b1;
-            sl[k] = slice_size(rt, j, bs);
-            ln.dyn_lds = dyn_lds_for(rt, kt, bs, bo, kts[1 - k], capped == k);
+            int b_others = 0;
+            int64_t others_lds = 0;
+            for (int o = 0; o < ng; ++o) {
+                if (o == k) continue;
+                b_others += bw[o];
+                others_lds += (int64_t)bw[o] * kts[o]->static_lds;
+            }
+            sl[k] = slice_size(rt, j, bw[k]);
+            ln.dyn_lds = dyn_lds_for(rt, kt, bw[k], b_others, others_lds, capped == k);
         }
         ln.slice = sl[k];
         rt->cs_job[k] = want[k];
     }
     rt->cs_active = true;
-    log_decision(rt, d, sl[0], sl[1], us);
+    log_decision(rt, d, sl, us);
 }
 
 // Whether job j would finish alone within the pairing threshold (such a
@@ -733,7 +749,7 @@ static bool too_short_to_pair(kl_runtime* rt, const Job& j) {
 // One step of Algorithm 1: decide if needed, then fill the lanes' queues.
 static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed) {
     bool ended = !rt->cs_active;
-    for (int k = 0; k < 2 && !ended; ++k) {
+    for (int k = 0; k < 3 && !ended; ++k) {
         kl_job id = rt->cs_job[k];
         if (id == KL_NO_JOB) continue;
         auto it = rt->jobs.find(id);
@@ -952,6 +968,10 @@ kl_status kernelet_init(kl_runtime** out, int hip_device, const kl_config* cfg) 
     *out = nullptr;
     kl_config c = cfg ? *cfg : defaults();
     if (kl_status s = check_cfg(c)) return s;
+    if (c.group_max == 3 && c.lanes < 3) {
+        set_error("kernelet_init: group_max 3 needs lanes >= 3 (one stream per kernel)");
+        return KL_EINVAL;
+    }
     int ndev = 0;
     KL_HIP(hipGetDeviceCount(&ndev));
     if (hip_device < 0 || hip_device >= ndev) {
@@ -1665,6 +1685,44 @@ kl_status kernelet_predict(const kl_config* cfg, const kl_profile* p1, const kl_
     return KL_OK;
 }
 
+kl_status kernelet_predict_group(const kl_config* cfg, const kl_profile* profiles,
+                                 const int32_t* waves, int32_t n, double* ipc, double* cp) {
+    if (!profiles || !waves || !ipc || n < 1 || n > 3) {
+        set_error("kernelet_predict_group: null argument or n outside 1..3");
+        return KL_EINVAL;
+    }
+    int total = 0;
+    for (int k = 0; k < n; ++k) {
+        if (waves[k] < 1 || waves[k] > 16) {
+            set_error("kernelet_predict_group: wave count outside 1..16");
+            return KL_EINVAL;
+        }
+        total += waves[k];
+    }
+    if (total > 24) {
+        set_error("kernelet_predict_group: more than 24 waves in all");
+        return KL_EINVAL;
+    }
+    kl_config c = cfg ? *cfg : defaults();
+    if (kl_status s = check_cfg(c)) return s;
+    KernelModel km[3];
+    int w[3];
+    double solo[3];
+    for (int k = 0; k < n; ++k) {
+        if (kl_status s = check_profile(profiles[k])) return s;
+        km[k] = kernel_model(profiles[k], c);
+        w[k] = waves[k];
+    }
+    double out[3];
+    chain_ipc(km, w, n, c.beta, c.beta_lds, out);
+    for (int k = 0; k < n; ++k) ipc[k] = out[k];
+    if (cp) {
+        for (int k = 0; k < n; ++k) solo[k] = solo_ipc(profiles[k], c);
+        *cp = cp_value(out, solo, n);
+    }
+    return KL_OK;
+}
+
 kl_status kernelet_best_ratio(const kl_config* cfg, const kl_profile* p1, const kl_profile* p2,
                               int32_t* b1, int32_t* b2, double* value, double* c1,
                               double* c2) {
@@ -1771,11 +1829,14 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
             x = kl_decision{};
             x.j1 = d.j1;
             x.j2 = d.j2;
+            x.j3 = d.j3;
             x.b1 = d.b1;
             x.b2 = d.b2;
+            x.b3 = d.b3;
             x.value = d.value;
             x.cipc1 = d.cipc1;
             x.cipc2 = d.cipc2;
+            x.cipc3 = d.cipc3;
             x.t_us = t;
         }
         ++nd;
@@ -1789,36 +1850,30 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
             ++ndone;
             continue;
         }
-        int b = (int)d.j2;
-        const kl_profile& pb = types[job_profile[b]];
-        double r1 = wg_rate(pa, d.cipc1, c.n_cu), r2 = wg_rate(pb, d.cipc2, c.n_cu);
-        double t1 = rem[a] / r1, t2 = rem[b] / r2;
-        double dt = std::min(t1, t2);
+        // the co-schedule runs until the first of its kernels runs out
+        const int ng = d.j3 < 0 ? 2 : 3;
+        const int g[3] = {a, (int)d.j2, (int)d.j3};
+        const double cg[3] = {d.cipc1, d.cipc2, d.cipc3};
+        double rate[3], tl[3];
+        for (int k = 0; k < ng; ++k) {
+            rate[k] = wg_rate(types[job_profile[g[k]]], cg[k], c.n_cu);
+            tl[k] = rem[g[k]] / rate[k];
+        }
+        int first = 0;
+        for (int k = 1; k < ng; ++k)
+            if (tl[k] < tl[first]) first = k;
+        const double dt = tl[first];
         t += dt;
-        if (t1 <= t2) {
-            rem[b] -= dt * r2;
-            rem[a] = 0;
-            fin[a] = 1;
-            done[a] = t;
-            ++ndone;
-            if (rem[b] <= kEps) {
-                rem[b] = 0;
-                fin[b] = 1;
-                done[b] = t;
-                ++ndone;
+        for (int k = 0; k < ng; ++k) {
+            const int i = g[k];
+            if (k != first) {
+                rem[i] -= dt * rate[k];
+                if (!(rem[i] <= kEps)) continue;
             }
-        } else {
-            rem[a] -= dt * r1;
-            rem[b] = 0;
-            fin[b] = 1;
-            done[b] = t;
+            rem[i] = 0;
+            fin[i] = 1;
+            done[i] = t;
             ++ndone;
-            if (rem[a] <= kEps) {
-                rem[a] = 0;
-                fin[a] = 1;
-                done[a] = t;
-                ++ndone;
-            }
         }
     }
     *makespan = t;

@@ -61,6 +61,18 @@ def predict(p1, p2=None, w1=1, w2=0, cfg: Config | None = None):
     return tuple(x.value for x in o)
 
 
+def predict_group(profiles, waves, cfg: Config | None = None):
+    """(per-kernel IPCs, cp) of one to three co-resident kernels; no GPU
+    needed."""
+    n = len(profiles)
+    P = (Profile * n)(*[make_profile(p) for p in profiles])
+    w = (C.c_int32 * n)(*waves)
+    ipc = (C.c_double * n)()
+    cp = C.c_double()
+    call("kernelet_predict_group", C.byref(cfg) if cfg else None, P, w, n, ipc, C.byref(cp))
+    return list(ipc), cp.value
+
+
 def best_ratio(p1, p2, cfg: Config | None = None):
     a, b = make_profile(p1), make_profile(p2)
     b1, b2 = C.c_int32(), C.c_int32()

@@ -2,7 +2,8 @@
 configuration the bench times: two instances of every kernel submitted
 together and co-scheduled by the Markov policy with the measured profiles
 (contention slopes, pairing threshold, LDS-capped slices), then by the
-surrogate policy, OPT on the measured co-run table, a Monte Carlo sample
+surrogate policy, OPT on the measured co-run table, a Monte Carlo sample,
+the Markov policy with co-schedules of up to three kernels on three streams,
 and plain concurrent execution of whole launches over two and three
 streams.  Outputs are checked
 against the oracle in full where that is cheap (polynomial, gather, SpMV,
@@ -56,9 +57,10 @@ def mix():
 
 def _run(insts, policy):
     prof = profiles.load()
-    lanes = 3 if policy == "concurrent3" else 2
-    policy = "concurrent" if policy == "concurrent3" else policy
-    with K.Runtime(0, surrogate_topk=0, random_seed=11, lanes=lanes,
+    lanes = 3 if policy in ("concurrent3", "markov3") else 2
+    group_max = 3 if policy == "markov3" else 2
+    policy = {"concurrent3": "concurrent", "markov3": "markov"}.get(policy, policy)
+    with K.Runtime(0, surrogate_topk=0, random_seed=11, lanes=lanes, group_max=group_max,
                    **profiles.model_config()) as rt:
         kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
         if policy == "surrogate":
@@ -83,12 +85,14 @@ def _out(inst, name=None):
 
 
 @pytest.mark.parametrize("policy", ["markov", "surrogate", "opt", "random", "fixed",
-                                    "concurrent", "concurrent3"])
+                                    "markov3", "concurrent", "concurrent3"])
 def test_full_mix_matches_oracle(mix, policy):
     hosts, insts = mix
     dec = _run(insts, policy)
     if not policy.startswith("concurrent"):
         assert any(d["j2"] >= 0 for d in dec), "nothing was co-scheduled"
+    if policy == "markov3":
+        assert any(d["j3"] >= 0 for d in dec), "no co-schedule of three kernels"
     rng = np.random.default_rng(7)
     by = {}
     for inst in insts:

@@ -503,3 +503,49 @@ def test_concurrent_policy_runs_jobs_whole_on_every_lane(L, lanes):
     overlap = any(sp[i + 1][0] < sp[i][1] for i in range(len(sp) - 1))
     assert overlap == (lanes > 1)
     h.close()
+
+
+# a pair of memory-bound kernels held to two workgroups per CU each (LDS),
+# and a compute-bound kernel that fills the wave slots they leave
+TRIPLE_PROF = [dict(r_mem=0.3, mem_req=1, lat_mem=400, instr_per_wave=100, max_wg_per_cu=2,
+                    waves_per_simd=1, vgpr=32, lds_bytes=64 * 1024, pur=0.1, mur=0.8),
+               dict(r_mem=0.2, mem_req=1, lat_mem=400, instr_per_wave=150, max_wg_per_cu=2,
+                    waves_per_simd=1, vgpr=32, lds_bytes=16 * 1024, pur=0.15, mur=0.7),
+               dict(r_mem=0.002, mem_req=1, lat_mem=300, instr_per_wave=4000, max_wg_per_cu=8,
+                    waves_per_simd=1, vgpr=32, pur=0.95, mur=0.01)]
+
+
+def test_groups_of_three_run_side_by_side_on_three_lanes(L):
+    """cfg.group_max 3: the chosen pair joined by a third kernel runs on
+    three lanes at once; every workgroup once; the decision log carries the
+    third kernel, its ratio and slice; a runtime with fewer than three
+    lanes refuses group_max 3."""
+    with pytest.raises(K.KerneletError):
+        K.Runtime(0, lib_handle=L, n_cu=4, group_max=3, lanes=2)
+    h = Harness(L, lanes=3, group_max=3, use_prune=0)
+    kids = []
+    for i, p in enumerate(TRIPLE_PROF):
+        d = _lib.KernelDesc(f"tri{i}".encode(), C.addressof(L._keys[0]), 256,
+                            C.sizeof(VisitArgs), 0, None)
+        kids.append(h.rt.register(d, p))
+    h.kids = kids
+    jobs = [h.job(160, 10 + k, kind=k, us=60) for k in range(3)]
+    _run_with_deadline(lambda: h.rt.schedule("markov", blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    dec = h.rt.decisions()
+    first = dec[0]
+    assert first["j3"] >= 0
+    assert {first["j1"], first["j2"], first["j3"]} == {j[0] for j in jobs}
+    assert first["b3"] >= 1 and first["slice3"] == first["b3"] * 4
+    assert first["b1"] + first["b2"] + first["b3"] <= 8
+    # the three ran side by side: each one's first slice started before
+    # every other one's last slice ended
+    span = lambda j: (j[2][: j[3][0], 3].min(), j[2][: j[3][0], 4].max())
+    sp = [span(j) for j in jobs]
+    for a in range(3):
+        for b in range(3):
+            if a != b:
+                assert sp[a][0] < sp[b][1]
+    h.close()

@@ -132,6 +132,23 @@ typedef struct {
     uint32_t spin;
 } kl_probe_args;
 
+/* ceil_fma, ceil_mfma (not workloads: probes of the chip's FP32 compute
+ * ceilings).  ceil_fma: thread t (t < n_wg * 256) keeps 16 chains a_k,
+ * starting at k, of a_k <- fma(a_k, mul, add) for `iters` iterations
+ * (unpacked VALU FMAs) and writes sum_k a_k to out[t].  ceil_mfma: every
+ * wave keeps four 32 x 32 FP32 accumulators, each updated `iters` times by
+ * one v_mfma_f32_32x32x2f32 whose A and B hold `mul` and `add` in every
+ * lane (so every accumulator entry grows by 2 * mul * add), and thread t
+ * writes the sum of its 64 accumulator registers to out[t].  Work:
+ * ceil_fma 32 * iters FLOPs per thread; ceil_mfma 4 * 4096 * iters FLOPs
+ * per wave.  grid = n_wg; iters <= 2^20. */
+typedef struct {
+    float* out;
+    float mul, add;
+    uint32_t n_wg;
+    uint32_t iters;
+} kl_ceiling_args;
+
 /* synthk_v<V>_l<L> (synthetic kernels of known character, the training
  * population of the surrogate model): thread t (t < n_threads) runs `iters`
  * iterations of one load of src[addr] followed by a chain of `alu`

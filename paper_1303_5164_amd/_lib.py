@@ -139,7 +139,12 @@ class ProbeArgs(C.Structure):
     _fields_ = [("visits", P), ("info", P), ("n_wg", C.c_uint32), ("spin", C.c_uint32)]
 
 
-ARGS = {"probe": ProbeArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
+class CeilingArgs(C.Structure):
+    _fields_ = [("out", P), ("mul", C.c_float), ("add", C.c_float), ("n_wg", C.c_uint32),
+                ("iters", C.c_uint32)]
+
+
+ARGS = {"probe": ProbeArgs, "ceil_fma": CeilingArgs, "ceil_mfma": CeilingArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
         "stencil": StencilArgs, "bs": BsArgs, "hist": HistArgs, "lookup": LookupArgs,
         "lookup_index": LookupArgs, **{k: SynthkArgs for k in SYNTHK}}
 

@@ -22,8 +22,12 @@ pruning features PUR / MUR from solo runs (Section 4.3).  Two steps:
         and the memory latency of each kernel is fitted so that the model's
         solo IPC at the kernel's occupancy equals the measured PUR.
 
+  ceilings: the chip's measured copy bandwidth and FP32 FMA / matrix
+        rates beside the published peaks (the roofs the kernels are held to).
+
 Usage:
   python -m paper_1303_5164_amd.calibrate run --out gpurun_out/calib_times.json
+  python -m paper_1303_5164_amd.calibrate ceilings --out gpurun_out/ceilings.json
   python -m paper_1303_5164_amd.calibrate fit --times T.json --counters A.csv B.csv ...
 """
 from __future__ import annotations
@@ -128,6 +132,101 @@ def run(out_path: str, reps: int = 3, scale: int = 1) -> dict:
         del inst, d_in
         torch.cuda.empty_cache()
     rt.close()
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
+def ceiling_expected(kind: str, iters: int, mul: float = 1.0, add: float = 1.0) -> float:
+    """What every thread of a ceiling probe writes (exact in FP32 for the
+    sizes used here with mul = add = 1): ceil_fma sums 16 chains that start
+    at k and grow by `add` per step; ceil_mfma sums 64 accumulator entries
+    that grow by 2 * mul * add per step."""
+    if kind == "ceil_fma":
+        return float(sum(k + iters * add for k in range(16)))
+    return 64.0 * 2.0 * mul * add * iters
+
+
+def ceiling_flops(kind: str, n_wg: int, iters: int) -> float:
+    if kind == "ceil_fma":
+        return n_wg * 256.0 * iters * 16 * 2
+    return n_wg * 4.0 * iters * 4 * 32 * 32 * 2 * 2
+
+
+def ceilings(out_path: str, reps: int = 5) -> dict:
+    """The chip's measured ceilings beside its published peaks: a 1 GiB
+    device copy (read + write bandwidth; far larger than the 256 MB MALL, so
+    every repetition streams from HBM), a loop of unpacked FP32 FMAs and a
+    loop of FP32 matrix instructions (v_mfma_f32_32x32x2f32), each launched
+    whole through the runtime and timed by HIP events on its lane; the GPU
+    clocks as reported by amd-smi (or rocm-smi) before and after."""
+    import subprocess
+
+    import torch
+
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import _lib
+
+    def smi():
+        for cmd in (["amd-smi", "metric", "-g", "0", "--clock"], ["rocm-smi", "--showclocks"]):
+            try:
+                r = subprocess.run(cmd, capture_output=True, text=True, timeout=30)
+            except (OSError, subprocess.TimeoutExpired):
+                continue
+            if r.returncode == 0 and r.stdout.strip():
+                return {"cmd": " ".join(cmd), "out": r.stdout.strip()[-3000:]}
+        return None
+
+    dev = torch.device("cuda:0")
+    out = {"clocks_before": smi()}
+    copy_bytes = 1 << 30
+    src = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    copy_ms = ev[0].elapsed_time(ev[1]) / reps
+    out["copy"] = {"bytes": copy_bytes, "ms": copy_ms, "gbps": 2 * copy_bytes / copy_ms / 1e6,
+                   "frac_of_8TBs": 2 * copy_bytes / copy_ms / 1e9 / 8.0}
+    print(f"# copy {out['copy']['gbps']:.0f} GB/s", file=sys.stderr, flush=True)
+    del src, dst
+    torch.cuda.empty_cache()
+    rt = K.Runtime(0)
+    n_cu = rt.cfg.n_cu
+    plan = {"ceil_fma": (n_cu * 32, 16384, 78.6e12), "ceil_mfma": (n_cu * 12, 8192, 157.3e12)}
+    for kind, (n_wg, iters, peak) in plan.items():
+        k = rt.register_builtin(kind)
+        buf = torch.empty(n_wg * 256, dtype=torch.float32, device=dev)
+        args = _lib.CeilingArgs(buf.data_ptr(), 1.0, 1.0, n_wg, iters)
+        info = rt.kernel_info(k)
+        for rep in range(reps + 1):
+            buf.fill_(-1.0)
+            torch.cuda.synchronize()
+            if rep == 1:
+                rt.time_kernel(k, True)   # (re)starts the timing: warm-up untimed
+            j = rt.submit(k, (n_wg, 1, 1), args)
+            rt.schedule("fifo", blocking=True, wait_done=True)
+            rt.wait(j, 60_000_000_000)
+            rt.synchronize()
+            rt.reap()
+        ms, n, _ = rt.kernel_time(k)
+        ms /= max(n, 1)
+        want = ceiling_expected(kind, iters)
+        ok = bool(torch.all(buf == want).item())
+        fl = ceiling_flops(kind, n_wg, iters)
+        out[kind] = {"n_wg": n_wg, "iters": iters, "ms": ms, "flops": fl,
+                     "tflops": fl / ms / 1e9, "published_peak_tflops": peak / 1e12,
+                     "frac_of_published": fl / ms / 1e3 / peak, "outputs_exact": ok, **info}
+        print(f"# {kind} {fl / ms / 1e9:.1f} TFLOP/s ({fl / ms / 1e3 / peak:.3f} of "
+              f"{peak / 1e12} published), outputs exact: {ok}", file=sys.stderr, flush=True)
+        del buf
+    rt.close()
+    out["clocks_after"] = smi()
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     return out
@@ -444,6 +543,9 @@ def main():
     s = sub.add_parser("slices")
     s.add_argument("--out", required=True)
     s.add_argument("--reps", type=int, default=5)
+    c = sub.add_parser("ceilings")
+    c.add_argument("--out", required=True)
+    c.add_argument("--reps", type=int, default=5)
     f = sub.add_parser("fit")
     f.add_argument("--times", required=True)
     f.add_argument("--counters", nargs="+", required=True)
@@ -459,6 +561,8 @@ def main():
         print(f"# calibration run {time.time() - t0:.1f} s", file=sys.stderr)
     elif a.cmd == "slices":
         run_slices(a.out, a.reps)
+    elif a.cmd == "ceilings":
+        ceilings(a.out, a.reps)
     else:
         if a.occupancy:
             prof = fit_pools(a.times, a.counters, a.occupancy, a.out, a.slices)

@@ -505,6 +505,46 @@ __global__ __launch_bounds__(KL_WG) void kl_probe(kl_probe_args a, kl_slice s) {
     }
 }
 
+// ------------------------------------------------------------- ceilings
+// FP32 compute ceilings of the chip, for the roofs kernels are measured
+// against: 16 independent FMA chains per thread (unpacked VALU), and four
+// independent MFMA accumulators per wave (the SGEMM's instruction).
+__global__ __launch_bounds__(KL_WG) void kl_ceil_fma(kl_ceiling_args a, kl_slice s) {
+    const uint32_t lin = kl_wg_linear(s);
+    if (lin >= a.n_wg) return;
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = (float)k;
+    for (uint32_t i = 0; i < a.iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = __builtin_fmaf(v[k], a.mul, a.add);
+    }
+    float sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += v[k];
+    a.out[(uint64_t)lin * KL_WG + threadIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(KL_WG) void kl_ceil_mfma(kl_ceiling_args a, kl_slice s) {
+    const uint32_t lin = kl_wg_linear(s);
+    if (lin >= a.n_wg) return;
+    kl_f32x16 acc[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = kl_f32x16{};
+    const float av = a.mul, bv = a.add;
+    for (uint32_t i = 0; i < a.iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            acc[k] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[k], 0, 0, 0);
+    }
+    float sum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) sum += acc[k][e];
+    a.out[(uint64_t)lin * KL_WG + threadIdx.x] = sum;
+}
+
 // ===================================================== host-side registry
 namespace {
 
@@ -579,6 +619,11 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         if (!a.visits || !a.info || a.n_wg == 0) return "null pointer or n_wg == 0";
         if (a.spin > (1u << 24)) return "spin above 2^24";
         g->x = a.n_wg;
+    } else if (n == "ceil_fma" || n == "ceil_mfma") {
+        KL_ARGS(kl_ceiling_args);
+        if (!a.out || a.n_wg == 0) return "null out or n_wg == 0";
+        if (a.iters > (1u << 20)) return "iters above 2^20";
+        g->x = a.n_wg;
     } else if (n == "lookup" || n == "lookup_index") {
         KL_ARGS(kl_lookup_args);
         if (!a.keys || !a.index || a.nkeys == 0 || a.nkeys > 0x7fffffffu)
@@ -619,6 +664,8 @@ const BuiltinEntry kBuiltins[] = {
     {"lookup", (const void*)kl_lookup, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
     {"lookup_index", (const void*)kl_lookup_index, sizeof(kl_lookup_args), KL_KF_IDEMPOTENT},
     {"probe", (const void*)kl_probe, sizeof(kl_probe_args), 0u},
+    {"ceil_fma", (const void*)kl_ceil_fma, sizeof(kl_ceiling_args), KL_KF_IDEMPOTENT},
+    {"ceil_mfma", (const void*)kl_ceil_mfma, sizeof(kl_ceiling_args), KL_KF_IDEMPOTENT},
 #define KL_SYNTHK_ENTRY(V, L)                                                 \
     {"synthk_v" #V "_l" #L, (const void*)kl_synthk_v##V##_l##L, sizeof(kl_synthk_args), \
      KL_KF_IDEMPOTENT},

@@ -254,3 +254,16 @@ def test_empty_and_degenerate_inputs_are_refused():
     assert K.builtin_grid("poly", _lib.PolyArgs(p, p, p, 1, 1)) == (1, 1, 1)
     assert K.builtin_grid("stencil", _lib.StencilArgs(p, p + 16, 1, 4, 0.5, 0.125)) == (1, 1, 1)
     assert K.builtin_grid("lookup", _lib.LookupArgs(p, p, p, p, 1, 4)) == (1, 1, 1)
+
+
+def test_ceiling_probe_grids_and_refusals():
+    out = 256
+    a = _lib.CeilingArgs(out, 1.0, 1.0, 37, 1000)
+    for name in ("ceil_fma", "ceil_mfma"):
+        d = K.builtin_desc(name)
+        assert d.args_bytes == ctypes.sizeof(_lib.CeilingArgs) == 24
+        assert K.builtin_grid(name, a) == (37, 1, 1)
+        for bad in (_lib.CeilingArgs(out, 1.0, 1.0, 37, (1 << 20) + 1),
+                    _lib.CeilingArgs(0, 1.0, 1.0, 37, 10), _lib.CeilingArgs(out, 1.0, 1.0, 0, 10)):
+            with pytest.raises(K.KerneletError):
+                K.builtin_grid(name, bad)

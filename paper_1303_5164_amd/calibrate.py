@@ -159,8 +159,10 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
     every repetition streams from HBM), a loop of unpacked FP32 FMAs and a
     loop of FP32 matrix instructions (v_mfma_f32_32x32x2f32), each launched
     whole through the runtime and timed by HIP events on its lane; the GPU
-    clocks as reported by amd-smi (or rocm-smi) before and after."""
+    clocks as reported by amd-smi (or rocm-smi) idle and while the matrix
+    loop runs."""
     import subprocess
+    import threading
 
     import torch
 
@@ -178,7 +180,7 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
         return None
 
     dev = torch.device("cuda:0")
-    out = {"clocks_before": smi()}
+    out = {"clocks_idle": smi()}
     copy_bytes = 1 << 30
     src = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -219,14 +221,44 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
         want = ceiling_expected(kind, iters)
         ok = bool(torch.all(buf == want).item())
         fl = ceiling_flops(kind, n_wg, iters)
+        rate = fl / (ms / 1e3)
+        # the clock at which the chip would issue this rate with every SIMD
+        # busy every cycle (16 FMA lanes per SIMD, or 256 matrix FLOPs per
+        # CU per cycle)
+        per_cycle = n_cu * (4 * 16 * 2 if kind == "ceil_fma" else 256)
         out[kind] = {"n_wg": n_wg, "iters": iters, "ms": ms, "flops": fl,
-                     "tflops": fl / ms / 1e9, "published_peak_tflops": peak / 1e12,
-                     "frac_of_published": fl / ms / 1e3 / peak, "outputs_exact": ok, **info}
-        print(f"# {kind} {fl / ms / 1e9:.1f} TFLOP/s ({fl / ms / 1e3 / peak:.3f} of "
+                     "tflops": rate / 1e12, "published_peak_tflops": peak / 1e12,
+                     "frac_of_published": rate / peak,
+                     "issue_clock_ghz": rate / per_cycle / 1e9, "outputs_exact": ok, **info}
+        print(f"# {kind} {rate / 1e12:.1f} TFLOP/s ({rate / peak:.3f} of "
               f"{peak / 1e12} published), outputs exact: {ok}", file=sys.stderr, flush=True)
+        if kind == "ceil_mfma":
+            # the clocks amd-smi reports while the matrix loop runs (about six
+            # seconds of back-to-back launches, sampled until they end)
+            seen, busy = [], threading.Event()
+            busy.set()
+
+            def sample():
+                while busy.is_set():
+                    seen.append(smi())
+
+            jobs = [rt.submit(k, (n_wg, 1, 1), args) for _ in range(600)]
+            th = threading.Thread(target=sample)
+            th.start()
+            rt.schedule("fifo", blocking=True, wait_done=True)
+            busy.clear()
+            th.join()
+            rt.synchronize()
+            rt.reap()
+            # amd-smi refreshes about once a second: keep each reading once
+            uniq = []
+            for x in seen:
+                if x and x not in uniq:
+                    uniq.append(x)
+            out["clocks_under_mfma_load"] = uniq
+            del jobs
         del buf
     rt.close()
-    out["clocks_after"] = smi()
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
     return out

@@ -183,6 +183,20 @@ def _traffic(kernel):
     return (float(k["bytes"]), float(k["grid_threads"]) / 256.0) if k else None
 
 
+def _ceiling(bound):
+    """The chip's measured ceiling for a roofline bound, in the roofline's
+    unit (a 1 GiB device copy in GB/s; the FP32 FMA or matrix loop in
+    TFLOP/s; mean of the runs under profiles/), or None."""
+    path = os.path.join(ROOT, "profiles", "ceilings_mi355x.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        runs = json.load(f).get("runs", [])
+    key = {"hbm": "copy_gbps", "mfma": "mfma_tflops", "alu": "fma_tflops"}[bound]
+    vals = [r[key] for r in runs if key in r]
+    return sum(vals) / len(vals) if vals else None
+
+
 def nearest_rank(v, q):
     v = sorted(v)
     return v[max(1, math.ceil(q * len(v))) - 1]
@@ -406,6 +420,10 @@ def main():
         ach = per_wg_b * wg / (ms / 1e3)
         roof = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    ceil = _ceiling(roof["bound"])
+    if ceil:
+        roof["measured_ceiling"] = round(ceil, 2)
+        roof["frac_of_measured_ceiling"] = round(roof["achieved"] / ceil, 4)
     roof["achieved"] = round(roof["achieved"], 3)
     roof["frac"] = round(roof["frac"], 4)
     roof["traffic"] = None

@@ -159,8 +159,8 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
     every repetition streams from HBM), a loop of unpacked FP32 FMAs and a
     loop of FP32 matrix instructions (v_mfma_f32_32x32x2f32), each launched
     whole through the runtime and timed by HIP events on its lane; the GPU
-    clocks as reported by amd-smi (or rocm-smi) idle and while the matrix
-    loop runs."""
+    clocks as reported by amd-smi (or rocm-smi) idle, while the matrix loop
+    runs and while the mix's SGEMM runs back to back."""
     import subprocess
     import threading
 
@@ -258,6 +258,42 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
             out["clocks_under_mfma_load"] = uniq
             del jobs
         del buf
+    # the clocks while the mix's SGEMM (4096^3) runs back to back, sampled
+    # the same way
+    import synth
+    from paper_1303_5164_amd import workloads as W
+    h = synth.sgemm(0, **synth.FULL["sgemm"])
+    inst = W.build("sgemm", W.device_inputs("sgemm", h, dev), {}, dev)
+    kids = {"sgemm": rt.register_builtin("sgemm")}
+    rt.time_kernel(kids["sgemm"], True)
+    seen, busy = [], threading.Event()
+    busy.set()
+
+    def sample():
+        while busy.is_set():
+            seen.append(smi())
+
+    for _ in range(5000):
+        W.submit(rt, kids, inst)
+    th = threading.Thread(target=sample)
+    th.start()
+    rt.schedule("fifo", blocking=True, wait_done=True)
+    busy.clear()
+    th.join()
+    rt.synchronize()
+    rt.reap()
+    ms, n, _ = rt.kernel_time(kids["sgemm"])
+    fl = 2.0 * 4096 ** 3
+    out["sgemm_back_to_back"] = {"launches": n, "avg_ms": ms / max(n, 1),
+                                 "tflops": fl * n / (ms / 1e3) / 1e12}
+    uniq = []
+    for x in seen:
+        if x and x not in uniq:
+            uniq.append(x)
+    out["clocks_under_sgemm_load"] = uniq
+    print(f"# sgemm back to back {out['sgemm_back_to_back']['tflops']:.1f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    del inst
     rt.close()
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1)

@@ -202,15 +202,25 @@ def main():
         rt.reap()
         return wall, busy
 
-    # solo: one launch time per kind (unsliced), median of 5
-    solo = {}
+    # solo: time per launch (unsliced) over a window of back-to-back launches,
+    # median of 3 windows after an untimed one, so that the clock runs as in
+    # the co-run windows below (single launches after an idle GPU run with the
+    # clock still ramping: kept as solo_cold_ms)
+    solo, solo_cold = {}, {}
     for kind in kinds:
         ts = []
         for _ in range(6):
             _, busy = run([(kind, 1, 0, 0)])
             ts.append(busy[kind][0])
+        solo_cold[kind] = float(np.median(ts[1:]))
+        n = max(1, round(a.window_ms / solo_cold[kind]))
+        ts = []
+        for _ in range(4):
+            _, busy = run([(kind, n, 0, 0)])
+            ts.append(busy[kind][0] / n)
         solo[kind] = float(np.median(ts[1:]))
-        print(f"# solo {kind}: {solo[kind]:.4f} ms", file=sys.stderr, flush=True)
+        print(f"# solo {kind}: {solo[kind]:.4f} ms per launch over {n} launches "
+              f"({solo_cold[kind]:.4f} alone after idle)", file=sys.stderr, flush=True)
 
     solo_occ = {}
     if a.solo_occupancy:
@@ -282,7 +292,8 @@ def main():
                   file=sys.stderr, flush=True)
     rt.close()
     with open(a.out, "w") as f:
-        json.dump({"n_cu": n_cu, "solo_ms": solo, "window_ms": a.window_ms,
+        json.dump({"n_cu": n_cu, "solo_ms": solo, "solo_cold_ms": solo_cold,
+                   "window_ms": a.window_ms,
                    "slicing": a.slicing, "lds_reserve": a.lds_reserve, "balance": a.balance,
                    "solo_occupancy_ms": solo_occ, "rows": rows}, f, indent=1)
     if a.compact:

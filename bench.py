@@ -23,7 +23,10 @@ import argparse
 import json
 import math
 import os
+import re
+import subprocess
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -197,6 +200,21 @@ def _ceiling(bound):
     return sum(vals) / len(vals) if vals else None
 
 
+def _smi_sample():
+    """GFX clock of each XCD (MHz) and socket power (W) as amd-smi reports
+    them, or None where it is not available."""
+    try:
+        r = subprocess.run(["amd-smi", "metric", "-g", "0", "--clock", "--power"],
+                           capture_output=True, text=True, timeout=30)
+    except (OSError, subprocess.TimeoutExpired):
+        return None
+    if r.returncode != 0:
+        return None
+    gfx = [int(x) for x in re.findall(r"GFX_\d+:\s*\n\s*CLK: (\d+) MHz", r.stdout)]
+    pw = re.findall(r"SOCKET_POWER: ([\d.]+) W", r.stdout)
+    return {"gfx": gfx, "power": float(pw[0]) if pw else None} if gfx else None
+
+
 def nearest_rank(v, q):
     v = sorted(v)
     return v[max(1, math.ceil(q * len(v))) - 1]
@@ -298,8 +316,23 @@ def main():
         runtimes["cke3"] = runtimes["kernelet3"] = (
             r3, {k: r3.register_builtin(k, prof[k]) for k in W.KERNELS})
     triples = 0
+    # GPU clock and power sampled (about once a second) during the timed steps
+    smi, smi_on, smi_end = [], threading.Event(), threading.Event()
+
+    def sampler():
+        smi_on.wait()
+        while not smi_end.is_set():
+            x = _smi_sample()
+            if x is None:
+                return
+            smi.append(x)
+
+    smi_thread = threading.Thread(target=sampler, daemon=True)
+    smi_thread.start()
     for step in range(args.warmup + args.steps):
         timed_step = step >= args.warmup
+        if timed_step:
+            smi_on.set()
         for leg in legs:
             rt, kids = runtimes.get(leg, (rt_main, kids_main))
             for inst in insts:
@@ -342,6 +375,9 @@ def main():
             print(f"# step {step} {leg}: {(t1 - t0) / 1e6:.2f} ms", file=sys.stderr,
                   flush=True)
 
+    smi_end.set()
+    smi_on.set()
+    smi_thread.join(timeout=60)
     rt, kids = rt_main, kids_main
     model_ms3 = None
     if "kernelet3" in legs:
@@ -450,6 +486,19 @@ def main():
     out["mix_bound_ms"] = {"compute": round(comp * 1e3, 4), "hbm": round(mem * 1e3, 4)}
     out["kernel_ms_per_step"] = {k: round(ktime[k][0] / max(1, args.steps), 3) for k in W.KERNELS}
     out["setup_s"] = round(setup_s, 1)
+    # clocks and power while the timed steps ran; the MALL holds whatever the
+    # previous leg left (no flush between legs or steps)
+    busy = [x for x in smi if x["gfx"] and min(x["gfx"]) > 1000]
+    out["gpu_state"] = {
+        "samples": len(smi), "busy_samples": len(busy),
+        "gfx_clock_mhz_mean": (round(sum(sum(x["gfx"]) / len(x["gfx"]) for x in busy)
+                                     / len(busy), 1) if busy else None),
+        "socket_power_w_mean": (round(sum(x["power"] for x in busy if x["power"] is not None)
+                                      / max(1, sum(x["power"] is not None for x in busy)), 1)
+                                if busy else None),
+        "socket_power_w_max": (max((x["power"] for x in busy if x["power"] is not None),
+                                   default=None) if busy else None),
+        "mall": "warm: inputs and outputs as the previous leg left them, no flush"}
     st = rt.stats()
     out["decision_us_mean"] = round(st["decision_us_total"] / max(1, st["decisions"]), 2)
     rt.close()

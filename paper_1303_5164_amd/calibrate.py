@@ -180,7 +180,8 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
     from paper_1303_5164_amd import _lib
 
     def smi():
-        for cmd in (["amd-smi", "metric", "-g", "0", "--clock"], ["rocm-smi", "--showclocks"]):
+        for cmd in (["amd-smi", "metric", "-g", "0", "--clock", "--power"],
+                    ["amd-smi", "metric", "-g", "0", "--clock"], ["rocm-smi", "--showclocks"]):
             try:
                 r = subprocess.run(cmd, capture_output=True, text=True, timeout=30)
             except (OSError, subprocess.TimeoutExpired):

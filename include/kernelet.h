@@ -342,7 +342,14 @@ kl_status kernelet_job_occupancy(kl_runtime* rt, kl_job j, int32_t wg_per_cu);
  * the call returns once every pending job (including dependants released
  * meanwhile) has been launched; otherwise a scheduler thread keeps serving
  * submissions until kernelet_shutdown.  Launches are asynchronous: use
- * kernelet_wait for completion. */
+ * kernelet_wait for completion.  The model's policies (MARKOV, SURROGATE,
+ * OPT, RANDOM) need a profile for every pending job's kernel (profiles are
+ * measured offline, Section 4.4, and given at registration or by
+ * kernelet_set_profile; nothing is profiled on submission); FIFO, FIXED and
+ * CONCURRENT need none.  KL_ESTATE: a pending kernel without a profile
+ * under a model policy, SURROGATE without kernelet_set_surrogate, OPT
+ * without kernelet_set_pair_measures, or a scheduler already running;
+ * KL_EINVAL: an unknown policy. */
 kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags);
 
 /* Block until job j has finished on the GPU, or `timeout_ns` (< 0:

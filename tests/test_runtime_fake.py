@@ -549,3 +549,22 @@ def test_groups_of_three_run_side_by_side_on_three_lanes(L):
             if a != b:
                 assert sp[a][0] < sp[b][1]
     h.close()
+
+
+def test_model_policies_refuse_a_kernel_without_profile(L):
+    """Profiles are measured offline: under a model policy a pending job of a
+    kernel registered without one is refused (KL_ESTATE) before anything is
+    launched, while FIFO runs it."""
+    h = Harness(L)
+    d = _lib.KernelDesc(b"noprof", C.addressof(L._keys[0]), 256, C.sizeof(VisitArgs), 0, None)
+    h.kids.append(h.rt.register(d))
+    j = h.job(16, 1, kind=2)
+    for pol in ("markov", "random"):
+        with pytest.raises(K.KerneletError) as e:
+            h.rt.schedule(pol, blocking=True, wait_done=True)
+        assert e.value.code == -5 and "no profile" in str(e.value)
+    assert h.rt.stats()["slices_launched"] == 0
+    _run_with_deadline(lambda: h.rt.schedule("fifo", blocking=True, wait_done=True))
+    h.rt.wait(j[0], 5_000_000_000)
+    assert np.all(j[1] == 1)
+    h.close()

@@ -497,7 +497,7 @@ def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict
 
 def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str,
               slices_path=None, betas=(0.0, 2.0, 4.0, 8.0), betas_lds=(0.0, 4.0, 16.0, 64.0),
-              min_pair_us: float = 50.0) -> dict:
+              min_pair_us: float = 50.0, corun_path=None) -> dict:
     """Profiles for the model with contention pools.
 
     Instructions are counted by the issue slots they hold (an FP32 32x32x2
@@ -600,6 +600,41 @@ def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str
                   flush=True)
             results.append((err, bh, bl, fitted))
     err, bh, bl, prof = min(results, key=lambda r: r[0])
+    corun = None
+    if corun_path:
+        # choose the slopes by the measured co-runs instead: each grid point's
+        # fitted table predicts every (pair, ratio) point of a balanced sweep
+        # (S = sum of the predicted per-kernel slowdowns); the slopes of least
+        # mean absolute relative error are taken, and the error of slopes
+        # chosen without each pair, on that pair, is reported beside it
+        rows = json.load(open(corun_path))["rows"]
+        meas = np.array([r["speedup"] for r in rows])
+        key = [(r["a"], r["b"]) for r in rows]
+        ape = []
+        for _, gh, gl, fitted in results:
+            cfg = K.default_config(beta=gh, beta_lds=gl)
+            full = {k: dict(profiles._COMMON, **v) for k, v in fitted.items()}
+            pred = []
+            for r in rows:
+                pa, pb = full[r["a"]], full[r["b"]]
+                i1, i2, _ = K.predict(pa, pb, r["b1"], r["b2"], cfg)
+                s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0, cfg)[0]
+                s2 = K.predict(pb, None, pb["max_wg_per_cu"], 0, cfg)[0]
+                pred.append(i1 / s1 + i2 / s2)
+            ape.append(np.abs(np.array(pred) - meas) / meas)
+        pick = int(np.argmin([a.mean() for a in ape]))
+        held = []
+        for pair in sorted(set(key)):
+            other = np.array([k != pair for k in key])
+            g = int(np.argmin([a[other].mean() for a in ape]))
+            held.extend(ape[g][~other].tolist())
+        err, bh, bl, prof = results[pick]
+        corun = {"sweep": os.path.basename(corun_path), "points": len(rows),
+                 "mape": float(ape[pick].mean()),
+                 "leave_one_pair_out_mape": float(np.mean(held)),
+                 "grid": [[r[1], r[2], float(a.mean())] for r, a in zip(results, ape)]}
+        print(f"# slopes by co-runs: beta {bh} beta_lds {bl}, MAPE {corun['mape']:.3f}, "
+              f"leave one pair out {corun['leave_one_pair_out_mape']:.3f}", file=sys.stderr)
     meta = {"source": "calibrate.py fit_pools over solo runs at every occupancy on MI355X",
             "times": os.path.basename(times_path), "occupancy": os.path.basename(occupancy_path),
             "counters": [os.path.basename(x) for x in counter_paths], "freq_hz": FREQ,
@@ -607,7 +642,8 @@ def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str
             "model": {"beta": bh, "beta_lds": bl,
                       "min_pair_slots": min_pair_us * 1e-6 * FREQ / 4.0,
                       "occupancy_fit_error": err,
-                      "grid": [[r[1], r[2], r[0]] for r in results]}}
+                      "grid": [[r[1], r[2], r[0]] for r in results],
+                      "corun_fit": corun}}
     with open(out_path, "w") as f:
         json.dump({"meta": meta, "profiles": prof}, f, indent=1, sort_keys=True)
     return prof
@@ -630,6 +666,9 @@ def main():
     f.add_argument("--counters", nargs="+", required=True)
     f.add_argument("--slices", default=None)
     f.add_argument("--out", default=os.path.join(HERE, "profiles_mi355x.json"))
+    f.add_argument("--corun", default=None,
+                   help="balanced co-run sweep JSON: choose the contention slopes by its "
+                        "measured speedups (with --occupancy)")
     f.add_argument("--occupancy", default=None,
                    help="sweep JSON with solo_occupancy_ms: fit the model with contention "
                         "pools to every kernel's IPC-vs-occupancy curve")
@@ -644,7 +683,8 @@ def main():
         ceilings(a.out, a.reps)
     else:
         if a.occupancy:
-            prof = fit_pools(a.times, a.counters, a.occupancy, a.out, a.slices)
+            prof = fit_pools(a.times, a.counters, a.occupancy, a.out, a.slices,
+                             corun_path=a.corun)
         else:
             prof = fit(a.times, a.counters, a.out, a.slices)
         for k, v in prof.items():

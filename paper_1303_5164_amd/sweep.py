@@ -37,19 +37,36 @@ RATIOS = [(1, 7), (2, 6), (3, 5), (4, 4), (5, 3), (6, 2), (7, 1)]
 
 
 def report(sweep_path: str, occupancy_path: str | None = None) -> str:
-    """Markdown summary of a balanced sweep: the model's error over every
-    (pair, ratio) point (predicted S = sum of the predicted per-kernel
-    slowdowns), with and without the polynomial's pairs; the rank
+    """Markdown summary of a balanced sweep: the installed profile table's
+    error over every (pair, ratio) point (predicted S = sum of the predicted
+    per-kernel slowdowns), with and without the polynomial's pairs; the rank
     correlation of the pairs' best S; per pair the measured best, the
     model's best and the measured S at the model's choice; and the solo
     occupancy curves of `occupancy_path` if given."""
     import numpy as np
     from scipy import stats as st
 
+    import paper_1303_5164_amd as K
+    from paper_1303_5164_amd import profiles
+
     d = json.load(open(sweep_path))
-    rows = [r for r in d["rows"] if r["pred_rel_a"] == r["pred_rel_a"]]
+    # predictions of the profile table installed now (the sweep's own
+    # columns hold those of the table it ran with)
+    prof = profiles.load()
+    cfg = K.default_config(**profiles.model_config())
+    rows, pred = [], []
+    for r in d["rows"]:
+        pa, pb = prof[r["a"]], prof[r["b"]]
+        try:
+            i1, i2, _ = K.predict(pa, pb, r["b1"], r["b2"], cfg)
+        except K.KerneletError:
+            continue
+        s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0, cfg)[0]
+        s2 = K.predict(pb, None, pb["max_wg_per_cu"], 0, cfg)[0]
+        rows.append(r)
+        pred.append(i1 / s1 + i2 / s2)
     meas = np.array([r["speedup"] for r in rows])
-    pred = np.array([r["pred_rel_a"] + r["pred_rel_b"] for r in rows])
+    pred = np.array(pred)
     nopoly = np.array(["poly" not in (r["a"], r["b"]) for r in rows])
 
     def err(m, p):

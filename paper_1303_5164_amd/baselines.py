@@ -11,7 +11,7 @@ compared bit for bit with the FIFO run's.  Reported: kernels/s of FIFO,
 Kernelet and OPT (median of --reps), the distribution of the MC samples
 (min, deciles, max), and how many samples beat Kernelet and OPT.
 
-Usage: python -m paper_1303_5164_amd.baselines --samples 1000 --out gpurun_out/baselines.json
+Usage: python -m paper_1303_5164_amd.baselines --samples 1000 --out results/baselines.json
 """
 from __future__ import annotations
 

@@ -26,8 +26,8 @@ pruning features PUR / MUR from solo runs (Section 4.3).  Two steps:
         rates beside the published peaks (the roofs the kernels are held to).
 
 Usage:
-  python -m paper_1303_5164_amd.calibrate run --out gpurun_out/calib_times.json
-  python -m paper_1303_5164_amd.calibrate ceilings --out gpurun_out/ceilings.json
+  python -m paper_1303_5164_amd.calibrate run --out results/calib_times.json
+  python -m paper_1303_5164_amd.calibrate ceilings --out results/ceilings.json
   python -m paper_1303_5164_amd.calibrate fit --times T.json --counters A.csv B.csv ...
 """
 from __future__ import annotations

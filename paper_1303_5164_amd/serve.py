@@ -18,7 +18,7 @@ arrival order, records its turnaround (completion - submission) and frees
 it; a sample of the instances is compared bit for bit with the output of
 the same instance run alone.
 
-Usage: python -m paper_1303_5164_amd.serve --out gpurun_out/serve.json
+Usage: python -m paper_1303_5164_amd.serve --out results/serve.json
 """
 from __future__ import annotations
 

@@ -16,8 +16,8 @@ most of the run.  Reported per pair and ratio:
 The stencil runs single sweeps and the lookup its query kernel over an index
 built beforehand, so every job is one launch.
 
-Usage: python -m paper_1303_5164_amd.sweep --out gpurun_out/sweep.json
-       python -m paper_1303_5164_amd.sweep report gpurun_out/sweep.json [--occupancy OCC.json]
+Usage: python -m paper_1303_5164_amd.sweep --out results/sweep.json
+       python -m paper_1303_5164_amd.sweep report results/sweep.json [--occupancy OCC.json]
 """
 from __future__ import annotations
 

@@ -14,8 +14,8 @@ pairs:  `--pairs` random pairs of the population run alone and together
         jobs) / (co-run time) is set beside the Markov model's and the
         surrogate's predictions.
 
-Usage: python -m paper_1303_5164_amd.synthmix decide --out gpurun_out/synth_decide.json
-       python -m paper_1303_5164_amd.synthmix pairs --out gpurun_out/synth_pairs.json
+Usage: python -m paper_1303_5164_amd.synthmix decide --out results/synth_decide.json
+       python -m paper_1303_5164_amd.synthmix pairs --out results/synth_pairs.json
 """
 from __future__ import annotations
 

@@ -442,7 +442,7 @@ kl_status kernelet_simulate(const kl_config* cfg, const kl_profile* profiles,
  * survives pruning in one batched inference on the device (its own
  * stream), keeps the cfg.surrogate_topk pairs of highest predicted weighted
  * speedup and lets the Markov model choose among them (Kernelet, Section
- * 4.3 with the model of Section 4.4 as the judge).  Errors: KL_EINVAL,
+ * 4.3, the model of Section 4.4 deciding among the ranked pairs).  Errors: KL_EINVAL,
  * KL_EHIP. */
 kl_status kernelet_set_surrogate(kl_runtime* rt, const float* params, uint32_t n_params);
 

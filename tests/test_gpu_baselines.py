@@ -1,7 +1,8 @@
 """GPU runs of the evaluation baselines (Section 5) through the C ABI: OPT
 (the greedy algorithm on the measured co-run table) and Monte Carlo samples
 (random pairs and slice ratios) run a mix of the eight kernels to the same
-bits as FIFO, whose outputs are checked against the oracle."""
+bits as FIFO, whose outputs are checked against the oracle; and so do the
+Markov policy's co-schedules of three kernels."""
 import json
 
 import numpy as np
@@ -67,3 +68,38 @@ def test_opt_and_random_same_bits_as_fifo():
     h_hist = insts[[i.kind for i in insts].index("hist")]
     assert np.array_equal(outs["random2"][insts.index(h_hist)]["bins"].astype(np.uint64),
                           oracle.histogram(hh["data"]))
+
+
+def test_groups_of_three_same_bits_as_fifo():
+    """The Markov policy with co-schedules of up to three kernels (three
+    lanes) on the small mix: FIFO's bits, and some decision joins a third
+    kernel (no pairing threshold at these sizes)."""
+    dev = torch.device("cuda:0")
+    prof = profiles.load()
+    insts = small_mix(dev)
+    cfg = dict(profiles.model_config(), min_pair_slots=0.0)
+    with K.Runtime(0, lanes=3, group_max=3, **cfg) as rt:
+        kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
+        outs, dec = {}, {}
+        for pol in ["fifo", "markov"]:
+            for inst in insts:
+                inst.reset()
+            torch.cuda.synchronize()
+            jobs = [W.submit(rt, kids, inst) for inst in insts]
+            print(f"schedule {pol} (groups of three)", flush=True)
+            rt.schedule(pol, blocking=True, wait_done=True)
+            for js in jobs:
+                rt.wait(js[-1], 60_000_000_000)
+            torch.cuda.synchronize()
+            outs[pol] = _outputs(insts)
+            dec[pol] = rt.decisions()
+            rt.reap()
+    bad = [i.kind for i, a, b in zip(insts, outs["fifo"], outs["markov"])
+           if any(not np.array_equal(a[n], b[n]) for n in a)]
+    assert not bad, f"outputs differ from FIFO: {bad}"
+    assert any(d["j3"] >= 0 for d in dec["markov"]), "no co-schedule of three kernels"
+    # three distinct kernels in every triple, at most eight waves per SIMD
+    for d in dec["markov"]:
+        if d["j3"] >= 0:
+            assert len({d["j1"], d["j2"], d["j3"]}) == 3
+            assert d["b1"] + d["b2"] + d["b3"] <= 8

@@ -22,13 +22,19 @@ KernelModel kernel_model(const kl_profile& p, const kl_config& cfg) {
 
 namespace {
 
-const double kFact[] = {1, 1, 2, 6, 24, 120, 720, 5040, 40320, 362880,
-                        3628800, 39916800, 479001600};
+// Binomial coefficient by the multiplicative formula (exact in double for
+// every count a chain here can hold).
+double choose(int n, int k) {
+    if (k < 0 || k > n) return 0.0;
+    if (k > n - k) k = n - k;
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * (double)(n - k + i) / (double)i;
+    return std::round(c);
+}
 
 double binom(int n, int k, double p) {
     if (k < 0 || k > n) return 0.0;
-    double c = kFact[n] / (kFact[k] * kFact[n - k]);
-    return c * std::pow(p, k) * std::pow(1.0 - p, n - k);
+    return choose(n, k) * std::pow(p, k) * std::pow(1.0 - p, n - k);
 }
 
 // Stalled-count tuples of one kernel: (n0) or (n0, n1), sum <= w.
@@ -101,8 +107,25 @@ void stationary(const std::vector<double>& P, int N, std::vector<double>& pi) {
 
 }  // namespace
 
+int64_t chain_states(const KernelModel* km, const int* w, int nk) {
+    int64_t n = 1;
+    for (int k = 0; k < nk; ++k) {
+        if (w[k] < 0) return -1;
+        const int64_t s = km[k].nclass == 1 ? (int64_t)w[k] + 1
+                                             : ((int64_t)w[k] + 1) * ((int64_t)w[k] + 2) / 2;
+        n *= s;
+        if (n > (int64_t)1 << 40) return n;
+    }
+    return n;
+}
+
 void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
                double beta_lds, double* ipc_out) {
+    if (chain_states(km, w, nk) > kMaxChainStates) {
+        // the dense chain would not fit: no prediction (callers check first)
+        for (int k = 0; k < nk; ++k) ipc_out[k] = std::nan("");
+        return;
+    }
     const double beta[2] = {beta_hbm, beta_lds};
     // kernels beyond nk have one state (no waves) and move with probability 1
     KStates ks[3];
@@ -162,7 +185,7 @@ void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
                         for (int a0 = 0; a0 <= r; ++a0) {
                             for (int a1 = 0; a0 + a1 <= r; ++a1) {
                                 int rest = r - a0 - a1;
-                                double c = kFact[r] / (kFact[a0] * kFact[a1] * kFact[rest]);
+                                double c = choose(r, a0) * choose(r - a0, a1);
                                 double pn = c * std::pow(pr, rest) * std::pow(p0, a0) *
                                             std::pow(p1, a1);
                                 if (pn == 0.0) continue;

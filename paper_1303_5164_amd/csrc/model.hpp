@@ -38,8 +38,17 @@ struct KernelModel {
 // class 1 the compute stall when r_comp > 0.
 KernelModel kernel_model(const kl_profile& p, const kl_config& cfg);
 
+// Joint states of the chain of nk kernels at w[k] waves per SIMD: the
+// product over kernels of their stalled-count tuples.
+int64_t chain_states(const KernelModel* km, const int* w, int nk);
+
+// Largest chain solved (its dense transition matrix holds the square of
+// this many doubles, 128 MiB).
+constexpr int64_t kMaxChainStates = 4096;
+
 // Per-kernel IPCs of one to three co-resident kernels (nk), kernel k with
-// w[k] >= 1 waves per SIMD.
+// w[k] >= 1 waves per SIMD.  A chain above kMaxChainStates is not solved:
+// the outputs are NaN.
 void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
                double beta_lds, double* ipc_out);
 

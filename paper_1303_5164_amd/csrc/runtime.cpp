@@ -219,7 +219,7 @@ static kl_config defaults() {
 }
 
 static kl_status check_cfg(const kl_config& c) {
-    if (c.wmax < 1 || c.wmax > 64 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
+    if (c.wmax < 1 || c.wmax > 16 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
@@ -235,7 +235,9 @@ static kl_status check_cfg(const kl_config& c) {
 static kl_status check_profile(const kl_profile& p) {
     if (!(p.r_mem >= 0 && p.r_comp >= 0 && p.r_mem + p.r_comp <= 1.0) || p.mem_req < 0 ||
         p.lat_mem < 0 || (p.r_comp > 0 && !(p.lat_comp >= 1.0)) || !(p.instr_per_wave > 0) ||
-        p.max_wg_per_cu < 1 || p.waves_per_simd < 1 || p.vgpr < 0 || p.lds_bytes < 0 ||
+        p.max_wg_per_cu < 1 || p.waves_per_simd < 1 || p.max_wg_per_cu > 64 ||
+        p.waves_per_simd > 64 || p.max_wg_per_cu * p.waves_per_simd > 64 || p.vgpr < 0 ||
+        p.lds_bytes < 0 ||
         p.access < 0 || p.access > 2 || p.comp_pool < 0 || p.comp_pool > 1) {
         set_error("invalid kl_profile field");
         return KL_EINVAL;
@@ -1659,6 +1661,16 @@ kl_status kernelet_predict(const kl_config* cfg, const kl_profile* p1, const kl_
     if (kl_status s = check_profile(*p1)) return s;
     if (p2)
         if (kl_status s = check_profile(*p2)) return s;
+    {
+        KernelModel km[2] = {kernel_model(*p1, c), p2 ? kernel_model(*p2, c) : KernelModel{}};
+        int w[2] = {w1, w2};
+        const int n = w2 > 0 ? 2 : 1;
+        if (w1 == 0) km[0] = km[1], w[0] = w2;
+        if (chain_states(km, w, n) > kMaxChainStates) {
+            set_error("kernelet_predict: the chain of these wave counts is too large");
+            return KL_EINVAL;
+        }
+    }
     double out[2] = {0, 0};
     if (w2 == 0 || w1 == 0) {
         const kl_profile& p = w1 ? *p1 : *p2;
@@ -1712,6 +1724,10 @@ kl_status kernelet_predict_group(const kl_config* cfg, const kl_profile* profile
         if (kl_status s = check_profile(profiles[k])) return s;
         km[k] = kernel_model(profiles[k], c);
         w[k] = waves[k];
+    }
+    if (chain_states(km, w, n) > kMaxChainStates) {
+        set_error("kernelet_predict_group: the chain of these wave counts is too large");
+        return KL_EINVAL;
     }
     double out[3];
     chain_ipc(km, w, n, c.beta, c.beta_lds, out);

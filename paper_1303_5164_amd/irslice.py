@@ -142,6 +142,11 @@ def rewrite(ir: str, kernel: str) -> str:
     body = lines[k0 + 1:k1]
     if any("llvm.amdgcn.dispatch.ptr" in ln for ln in body):
         raise SliceError(f"@{kernel} reads the dispatch packet (grid size in work-items)")
+    # slices are launched as 1-D workgroups of block_threads work-items, so a
+    # kernel indexing its workgroup in y or z would see 0 there
+    if any(re.search(r"@llvm\.amdgcn\.workitem\.id\.[yz]\(", ln) for ln in body):
+        raise SliceError(f"@{kernel} uses a 2-D or 3-D workgroup (work-item id y or z); "
+                         "slices run 1-D workgroups")
 
     # signature: exactly one by-value argument block, then the slice
     d = lines[k0]
@@ -173,6 +178,22 @@ def rewrite(ir: str, kernel: str) -> str:
         if m and m.group(3) in base and base[m.group(3)] in (0, 4, 8):
             dim = "xyz"[base[m.group(3)] // 4]
             lines[i] = f"{m.group(1)}{m.group(2)} = add i32 %kl.g{dim}, 0"
+
+    # every read of the grid's workgroup counts (the first 12 bytes of the
+    # implicit arguments) must have become one of the rebuilt counts: a
+    # vector, wider or unaligned read of them, or the pointer escaping,
+    # would still see the 1-D slice launch
+    for i in range(k0 + 1, k1):
+        ln = lines[i]
+        if _IMPL.match(ln):
+            continue
+        g = _GEP.match(ln)
+        if g and g.group(2) in base:
+            continue
+        for v, off in base.items():
+            if off < 12 and re.search(re.escape(v) + r"(?![\w.$])", ln):
+                raise SliceError(f"@{kernel} reads the grid's workgroup counts in a form "
+                                 f"the rewrite does not replace: {ln.strip()}")
 
     pre = ["  %kl.off = load i32, ptr addrspace(4) %kl.s, align 4",
            "  %kl.gxp = getelementptr inbounds i8, ptr addrspace(4) %kl.s, i64 8",

@@ -102,6 +102,50 @@ extern "C" __global__ void k(A a) {
         I.rewrite(I.device_ir(B.PLAIN_SOURCE), "no_such_kernel")
 
 
+def test_refuses_two_dimensional_workgroups(tmp_path):
+    """The paper's matrix addition with 16 x 16 workgroups reads threadIdx.y;
+    slices run 1-D workgroups, so the rewrite refuses it."""
+    src = """
+extern "C" __global__ void k(A a) {
+    uint32_t x = blockIdx.x * 16 + threadIdx.x, y = blockIdx.y * 16 + threadIdx.y;
+    if (x < a.n && y < a.n) a.o[y * a.n + x] = 1;
+}
+"""
+    with pytest.raises(I.SliceError, match="work-item id"):
+        I.rewrite(I.device_ir(_write(tmp_path, src)), "k")
+
+
+# A kernel whose two workgroup counts are read by one <2 x i32> load of the
+# implicit arguments (hand-written IR: the vectoriser may or may not merge
+# such reads in compiled code).
+_VEC_GRID_IR = """
+%struct.A = type { ptr, i32 }
+
+define amdgpu_kernel void @k(ptr addrspace(4) noundef readonly byref(%struct.A) align 8 %0) {
+  %impl = tail call ptr addrspace(4) @llvm.amdgcn.implicitarg.ptr()
+  %g = load <2 x i32>, ptr addrspace(4) %impl, align 4
+  %gx = extractelement <2 x i32> %g, i64 0
+  %op = load ptr, ptr addrspace(4) %0, align 8
+  store i32 %gx, ptr %op, align 4
+  ret void
+}
+
+declare ptr addrspace(4) @llvm.amdgcn.implicitarg.ptr()
+"""
+
+
+def test_refuses_merged_grid_reads():
+    with pytest.raises(I.SliceError, match="workgroup counts"):
+        I.rewrite(_VEC_GRID_IR, "k")
+    # the same read as one i32 per count is rewritten
+    ok = _VEC_GRID_IR.replace(
+        "%g = load <2 x i32>, ptr addrspace(4) %impl, align 4\n"
+        "  %gx = extractelement <2 x i32> %g, i64 0",
+        "%gx = load i32, ptr addrspace(4) %impl, align 4")
+    out = I.rewrite(ok, "k")
+    assert "%gx = add i32 %kl.gx, 0" in out
+
+
 def test_built_image_exists():
     """build() leaves the sliceable code object beside the library."""
     assert os.path.exists(B.PLAIN_IMAGE) and os.path.getsize(B.PLAIN_IMAGE) > 1000

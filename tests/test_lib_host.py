@@ -67,6 +67,38 @@ def test_predict_matches_oracle(seed):
     assert abs(cp - M.cp(o, s)) <= 1e-9 * max(1.0, abs(cp))
 
 
+@pytest.mark.parametrize("w1,w2,two_class", [(13, 0, False), (14, 2, False), (16, 16, False),
+                                               (15, 0, True), (13, 3, True)])
+def test_predict_many_waves_matches_oracle(w1, w2, two_class):
+    """Wave counts above 12, where binomial coefficients outgrow 12!: the
+    library's chain still equals the oracle's."""
+    rng = np.random.default_rng(w1 * 100 + w2)
+    p1 = rand_profile(rng, two_class)
+    p2 = rand_profile(rng, False)
+    p1["max_wg_per_cu"] = p2["max_wg_per_cu"] = 1
+    i1, i2, _ = K.predict(p1, p2 if w2 else None, w1, w2)
+    if w2:
+        o = M.ipc_pair(oracle_kernel(p1), w1, oracle_kernel(p2), w2)
+    else:
+        o = (M.ipc_homogeneous(oracle_kernel(p1), w1), 0.0)
+    assert abs(i1 - o[0]) <= 1e-9 * abs(o[0])
+    assert abs(i2 - o[1]) <= 1e-9 * max(abs(o[1]), 1e-300)
+
+
+def test_predict_rejects_oversized_chains():
+    """A two-class kernel pair at 16 waves each has 153^2 joint states, above
+    the dense solver's bound: refused, not allocated."""
+    rng = np.random.default_rng(5)
+    p1, p2 = rand_profile(rng, True), rand_profile(rng, True)
+    with pytest.raises(K.KerneletError):
+        K.predict(p1, p2, 16, 16)
+    bad = dict(p1, max_wg_per_cu=32, waves_per_simd=4)
+    with pytest.raises(K.KerneletError):
+        K.predict(bad, None, 1, 0)
+    with pytest.raises(K.KerneletError):
+        K.predict(p1, None, 1, 0, K.default_config(wmax=32))
+
+
 def test_one_wave_closed_form_through_abi():
     p = dict(r_mem=0.1, mem_req=1, lat_mem=400, instr_per_wave=100, max_wg_per_cu=1,
              waves_per_simd=1)

@@ -90,6 +90,30 @@ typedef struct {
     int32_t reserved;
 } kl_profile;
 
+/* Hardware-counter readings of one launch of a kernel run alone, with its
+ * duration: the raw material of the model inputs (Section 4.3 defines PUR
+ * and MUR from instructions, DRAM traffic and time; Section 4.4 takes the
+ * memory-instruction ratio from profiling the kernel).  Counts are totals
+ * over the launch (rocprofv3 --pmc SQ_WAVES SQ_INSTS_* FETCH_SIZE
+ * WRITE_SIZE on gfx950; FETCH_SIZE and WRITE_SIZE scaled to bytes). */
+typedef struct {
+    double waves;          /* waves launched (SQ_WAVES)                       */
+    double valu, salu, vmem, smem, lds, branch; /* instructions issued by kind,
+                              SQ_INSTS_VALU (matrix and transcendental
+                              instructions included), _SALU, _VMEM, _SMEM,
+                              _LDS, _BRANCH                                  */
+    double mfma;           /* matrix instructions (SQ_INSTS_MFMA), of valu    */
+    double trans;          /* FP32 transcendentals (SQ_INSTS_VALU_TRANS_F32),
+                              of valu                                        */
+    double dram_read;      /* bytes read from HBM                             */
+    double dram_write;     /* bytes written to HBM                            */
+    double time_s;         /* duration of the launch, seconds                 */
+    double freq_hz;        /* shader clock                                    */
+    double peak_bw;        /* HBM bandwidth of the roof, bytes/s              */
+    int32_t n_cu;          /* compute units the launch ran on                 */
+    int32_t reserved;
+} kl_counters;
+
 #define KL_KF_IDEMPOTENT 1u /* re-running a slice gives the same result */
 
 typedef struct {
@@ -287,6 +311,23 @@ kl_status kernelet_builtin_grid(const char* name, const void* args,
  * workgroup.  Any output may be NULL. */
 kl_status kernelet_kernel_info(kl_runtime* rt, kl_kernel k, int32_t* max_wg_per_cu,
                                int32_t* vgpr, int32_t* lds_bytes);
+
+/* Model inputs of a kernel from the counters of a launch run alone (host;
+ * no GPU).  Instructions are counted by the issue slots they hold (an FP32
+ * 32x32x2 matrix instruction 16, a transcendental 4, any other 1): with S
+ * slots over the launch, instr_per_wave = S / waves (I_K of Section 4.4);
+ * r_mem = vmem / S, the memory-instruction ratio of Section 4.4; an LDS
+ * instruction is the compute stall, r_comp = lds / S in the CU's LDS pool
+ * (comp_pool 1; 0 when below 1e-4); mem_req = max(1, DRAM bytes / 64 /
+ * vmem), the 64-byte requests one memory instruction holds; PUR (Section
+ * 4.3) = S / (time * freq * n_cu), issue slots used over the chip's (one per
+ * SIMD every four cycles), capped at 1; MUR (Section 4.3) = DRAM bytes /
+ * (time * peak_bw); solo_ipc = the uncapped PUR.  The latencies
+ * (lat_mem, lat_comp = 1) are left to a fit against measured occupancy
+ * curves and occupancy and resource fields to the code object: out's other
+ * fields are untouched.  KL_EINVAL for a count that is negative, no waves
+ * or instructions, or a time, clock, bandwidth or CU count not positive. */
+kl_status kernelet_profile_from_counters(const kl_counters* c, kl_profile* out);
 
 kl_status kernelet_set_profile(kl_runtime* rt, kl_kernel k, const kl_profile* p);
 kl_status kernelet_get_profile(kl_runtime* rt, kl_kernel k, kl_profile* p);

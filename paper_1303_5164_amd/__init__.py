@@ -5,4 +5,5 @@ hand-written HIP workload kernels.  This package is the thin Python face of
 that library (see include/kernelet.h)."""
 from ._lib import KerneletError, lib  # noqa: F401
 from .runtime import (Runtime, best_ratio, builtin_desc, builtin_grid,  # noqa: F401
-                      default_config, make_profile, predict, predict_group, simulate)
+                      default_config, make_profile, predict, predict_group,
+                      profile_from_counters, simulate)

@@ -38,6 +38,15 @@ class Profile(C.Structure):
                 ("comp_pool", C.c_int32), ("reserved", C.c_int32)]
 
 
+class Counters(C.Structure):
+    _fields_ = [("waves", C.c_double), ("valu", C.c_double), ("salu", C.c_double),
+                ("vmem", C.c_double), ("smem", C.c_double), ("lds", C.c_double),
+                ("branch", C.c_double), ("mfma", C.c_double), ("trans", C.c_double),
+                ("dram_read", C.c_double), ("dram_write", C.c_double),
+                ("time_s", C.c_double), ("freq_hz", C.c_double), ("peak_bw", C.c_double),
+                ("n_cu", C.c_int32), ("reserved", C.c_int32)]
+
+
 class KernelDesc(C.Structure):
     _fields_ = [("name", C.c_char_p), ("host_fn", C.c_void_p),
                 ("block_threads", C.c_uint32), ("args_bytes", C.c_uint32),
@@ -161,6 +170,7 @@ SYMBOLS = [
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
     "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
     "kernelet_set_pair_measures", "kernelet_register_image", "kernelet_stream_barrier",
+    "kernelet_profile_from_counters",
 ]
 
 _lib = None
@@ -199,6 +209,7 @@ def configure(L):
         "kernelet_builtin": [C.c_char_p, C.POINTER(KernelDesc)],
         "kernelet_builtin_grid": [C.c_char_p, C.c_void_p, u32, C.POINTER(Dim3)],
         "kernelet_set_profile": [C.c_void_p, i32, C.POINTER(Profile)],
+        "kernelet_profile_from_counters": [C.POINTER(Counters), C.POINTER(Profile)],
         "kernelet_get_profile": [C.c_void_p, i32, C.POINTER(Profile)],
         "kernelet_submit": [C.c_void_p, i32, Dim3, C.c_void_p, u32, i64, u32, u64,
                             C.POINTER(i64)],

@@ -406,6 +406,19 @@ def read_counters(paths) -> dict:
     return out
 
 
+def counters_of(c: dict, dram_read: float, dram_write: float, time_s: float,
+                n_cu: int) -> dict:
+    """kl_counters fields of one kernel from its per-dispatch counter means
+    (read_counters) and its scaled DRAM bytes and solo time."""
+    g = lambda k: float(c.get(k, 0.0))  # noqa: E731
+    return dict(waves=g("SQ_WAVES"), valu=g("SQ_INSTS_VALU"), salu=g("SQ_INSTS_SALU"),
+                vmem=g("SQ_INSTS_VMEM"), smem=g("SQ_INSTS_SMEM"), lds=g("SQ_INSTS_LDS"),
+                branch=g("SQ_INSTS_BRANCH"), mfma=g("SQ_INSTS_MFMA"),
+                trans=g("SQ_INSTS_VALU_TRANS_F32"), dram_read=dram_read,
+                dram_write=dram_write, time_s=time_s, freq_hz=FREQ, peak_bw=PEAK_HBM,
+                n_cu=int(n_cu))
+
+
 def fit(times_path: str, counter_paths, out_path: str, slices_path=None) -> dict:
     import paper_1303_5164_amd as K
     from paper_1303_5164_amd import profiles
@@ -533,29 +546,19 @@ def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str
         c = cnt.get(name)
         if not c or "SQ_WAVES" not in c:
             continue
-        waves = c["SQ_WAVES"]
-        tot = sum(c.get(k, 0.0) for k in ["SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM",
-                                           "SQ_INSTS_SMEM", "SQ_INSTS_LDS", "SQ_INSTS_BRANCH"])
-        mf = c.get("SQ_INSTS_MFMA", 0.0)
-        tr = c.get("SQ_INSTS_VALU_TRANS_F32", 0.0)
-        slots = tot - mf - tr + MFMA_SLOTS * mf + 4.0 * tr
-        I = slots / waves
-        T = t["avg_launch_ms"] / 1e3
-        pur = waves * I / (T * FREQ * n_cu)
-        vm = c.get("SQ_INSTS_VMEM", 0.0)
-        lds = c.get("SQ_INSTS_LDS", 0.0)
-        dram = 1024.0 * (c.get("FETCH_SIZE", 0.0) * f_fetch + c.get("WRITE_SIZE", 0.0) * f_write)
-        r_lds = lds / slots
+        # PUR, MUR, R_m, the LDS stall ratio and I_K come from the library
+        # (kernelet_profile_from_counters)
+        rd = 1024.0 * c.get("FETCH_SIZE", 0.0) * f_fetch
+        wr = 1024.0 * c.get("WRITE_SIZE", 0.0) * f_write
+        m = K.profile_from_counters(**counters_of(c, rd, wr, t["avg_launch_ms"] / 1e3, n_cu))
+        pur = m["solo_ipc"]
         p = dict(est.get(name, {}))
-        p.update(r_mem=vm / slots, mem_req=max(1.0, dram / 64.0 / vm) if vm else 1.0,
-                 r_comp=r_lds if r_lds > 1e-4 else 0.0, comp_pool=1 if r_lds > 1e-4 else 0,
-                 lat_comp=1.0, instr_per_wave=I, pur=min(pur, 1.0), mur=dram / T / PEAK_HBM,
-                 solo_ipc=pur, max_wg_per_cu=min(max(1, int(t["max_wg_per_cu"])), 8),
+        p.update({k: m[k] for k in ("r_mem", "mem_req", "r_comp", "comp_pool", "lat_comp",
+                                    "instr_per_wave", "pur", "mur", "solo_ipc")})
+        p.update(max_wg_per_cu=min(max(1, int(t["max_wg_per_cu"])), 8),
                  waves_per_simd=1, vgpr=int(t["vgpr"]), lds_bytes=int(t["lds_bytes"]),
-                 solo_ms=t["avg_launch_ms"], fetch_bytes_per_launch=dram - 1024.0 *
-                 c.get("WRITE_SIZE", 0.0) * f_write,
-                 write_bytes_per_launch=1024.0 * c.get("WRITE_SIZE", 0.0) * f_write,
-                 wgs_per_launch=t["wgs_per_launch"])
+                 solo_ms=t["avg_launch_ms"], fetch_bytes_per_launch=rd,
+                 write_bytes_per_launch=wr, wgs_per_launch=t["wgs_per_launch"])
         kind = "lookup" if name.startswith("lookup") else name
         if kind in slices:
             p["min_slice_wgs"] = int(slices[kind]["min_slice_wgs"]) or 2147483647

@@ -235,6 +235,34 @@ void chain_ipc(const KernelModel* km, const int* w, int nk, double beta_hbm,
     for (int k = 0; k < nk; ++k) ipc_out[k] = num[k] / den;
 }
 
+bool profile_from_counters(const kl_counters& c, kl_profile* out) {
+    const double counts[] = {c.waves, c.valu, c.salu, c.vmem, c.smem, c.lds, c.branch,
+                             c.mfma, c.trans, c.dram_read, c.dram_write};
+    for (double v : counts)
+        if (!(v >= 0.0)) return false;
+    if (!(c.waves > 0.0) || !(c.time_s > 0.0) || !(c.freq_hz > 0.0) || !(c.peak_bw > 0.0) ||
+        c.n_cu < 1 || c.mfma + c.trans > c.valu)
+        return false;
+    // issue slots: a matrix instruction holds its SIMD for 16, a
+    // transcendental for 4, anything else for 1
+    const double slots = (c.valu - c.mfma - c.trans) + 16.0 * c.mfma + 4.0 * c.trans + c.salu +
+                         c.vmem + c.smem + c.lds + c.branch;
+    if (!(slots > 0.0)) return false;
+    const double dram = c.dram_read + c.dram_write;
+    const double r_lds = c.lds / slots;
+    const double pur = slots / (c.time_s * c.freq_hz * (double)c.n_cu);
+    out->r_mem = c.vmem / slots;
+    out->mem_req = c.vmem > 0.0 ? std::max(1.0, dram / 64.0 / c.vmem) : 1.0;
+    out->r_comp = r_lds > 1e-4 ? r_lds : 0.0;
+    out->comp_pool = r_lds > 1e-4 ? 1 : 0;
+    out->lat_comp = 1.0;
+    out->instr_per_wave = slots / c.waves;
+    out->pur = std::min(pur, 1.0);
+    out->mur = dram / (c.time_s * c.peak_bw);
+    out->solo_ipc = pur;
+    return true;
+}
+
 double cp_value(const double* cipc, const double* solo, int n) {
     double s = 0.0;
     for (int i = 0; i < n; ++i) s += cipc[i] / solo[i];

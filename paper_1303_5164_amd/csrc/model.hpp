@@ -195,6 +195,10 @@ class Planner {
 };
 
 // Workgroups per issue slot that a kernel finishes chip-wide at IPC `ipc`.
+// Model inputs from the counters of a solo launch (see
+// kernelet_profile_from_counters); false for invalid counts.
+bool profile_from_counters(const kl_counters& c, kl_profile* out);
+
 double wg_rate(const kl_profile& p, double ipc, int n_cu);
 
 }  // namespace kl

@@ -1163,6 +1163,19 @@ kl_status kernelet_kernel_info(kl_runtime* rt, kl_kernel k, int32_t* max_wg_per_
     return KL_OK;
 }
 
+kl_status kernelet_profile_from_counters(const kl_counters* c, kl_profile* out) {
+    if (!c || !out) {
+        set_error("kernelet_profile_from_counters: null argument");
+        return KL_EINVAL;
+    }
+    if (!profile_from_counters(*c, out)) {
+        set_error("kernelet_profile_from_counters: invalid counts, time, clock, bandwidth or "
+                  "CU count");
+        return KL_EINVAL;
+    }
+    return KL_OK;
+}
+
 kl_status kernelet_set_profile(kl_runtime* rt, kl_kernel k, const kl_profile* p) {
     if (!rt || !p) {
         set_error("kernelet_set_profile: null argument");

@@ -13,13 +13,10 @@
 #include <string>
 
 #include "kernelet.h"
+#include "kernelet_device.h"
 #include "kernelet_workloads.h"
 
 #define KL_WG 256
-
-__device__ __forceinline__ uint32_t kl_wg_linear(const kl_slice& s) {
-    return s.offset + blockIdx.x;
-}
 
 // ------------------------------------------------------------------ poly
 // Horner's rule, one fma per coefficient from the highest degree down; the
@@ -177,8 +174,8 @@ __device__ __forceinline__ float st_cell(float c0, float c1, float mid, float n,
 // west / east halo lines are fetched once per 1024 columns and its north /
 // south halo rows once per 32 rows.
 __global__ __launch_bounds__(KL_WG) void kl_stencil(kl_stencil_args a, kl_slice s) {
-    const uint32_t lin = kl_wg_linear(s);
-    const uint32_t bx = lin % s.gx, by = lin / s.gx;
+    const uint3 wg = kl_wg_id3(s);
+    const uint32_t bx = wg.x, by = wg.y;
     const int lane = threadIdx.x & 63;
     const uint32_t nx = a.nx, ny = a.ny;
     const uint32_t x0 = bx * 1024 + (threadIdx.x >> 6) * 256 + lane * 4;

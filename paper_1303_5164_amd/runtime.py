@@ -39,6 +39,20 @@ def profile_dict(p: Profile) -> dict:
     return {f: getattr(p, f) for f in PROFILE_FIELDS}
 
 
+def profile_from_counters(**counts) -> dict:
+    """Model inputs (kernelet_profile_from_counters) of a solo launch from its
+    counter totals: waves, valu, salu, vmem, smem, lds, branch, mfma, trans,
+    dram_read, dram_write, time_s, freq_hz, peak_bw, n_cu."""
+    c = _lib.Counters()
+    for k, v in counts.items():
+        if not hasattr(c, k) or k == "reserved":
+            raise KeyError(k)
+        setattr(c, k, v)
+    p = Profile()
+    call("kernelet_profile_from_counters", C.byref(c), C.byref(p))
+    return profile_dict(p)
+
+
 def builtin_desc(name: str) -> KernelDesc:
     d = KernelDesc()
     call("kernelet_builtin", name.encode(), C.byref(d))

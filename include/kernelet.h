@@ -525,6 +525,23 @@ kl_status kernelet_mlp_train_step(float* params, float* m, float* v, const float
                                   uint32_t step, float lr, float* grad_out, float* workspace,
                                   void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * step as kernelet_mlp_train_step, same kernels and results, with its
+ * workspace in a static device array of the library instead of a caller
+ * buffer.  batch <= kernelet_mlp_noalloc_max_batch() (4096 samples, a
+ * 4.2 MB array each GPU the library runs on holds until the process
+ * ends); a larger batch returns KL_EINVAL with a message.  No device
+ * memory is allocated or freed.  The array is shared by every call on one
+ * GPU: calls that overlap on the same GPU (on different streams or host
+ * threads without ordering) race and give undefined results.  The
+ * caller's stream orders the step as for the workspace variant. */
+uint32_t kernelet_mlp_noalloc_max_batch(void);
+kl_status kernelet_mlp_train_step_noalloc(float* params, float* m, float* v, const float* x,
+                                          const float* t, const int32_t* idx, uint32_t batch,
+                                          uint32_t step, float lr, float* grad_out,
+                                          void* stream);
+
 /* --------------------------------------------------------------- logging */
 
 /* Time every launch of kernel k (enable != 0) with a pair of HIP events

@@ -170,7 +170,8 @@ SYMBOLS = [
     "kernelet_kernel_info", "kernelet_mlp_workspace_floats", "kernelet_mlp_forward",
     "kernelet_mlp_train_step", "kernelet_set_surrogate", "kernelet_surrogate_features",
     "kernelet_set_pair_measures", "kernelet_register_image", "kernelet_stream_barrier",
-    "kernelet_profile_from_counters",
+    "kernelet_profile_from_counters", "kernelet_mlp_noalloc_max_batch",
+    "kernelet_mlp_train_step_noalloc",
 ]
 
 _lib = None
@@ -256,7 +257,10 @@ def configure(L):
     opt = {"kernelet_mlp_workspace_floats": ([u32], u64),
            "kernelet_mlp_forward": ([f32p, f32p, u32, f32p, C.c_void_p], i32),
            "kernelet_mlp_train_step": ([f32p, f32p, f32p, f32p, f32p, f32p, u32, u32,
-                                        C.c_float, f32p, f32p, C.c_void_p], i32)}
+                                        C.c_float, f32p, f32p, C.c_void_p], i32),
+           "kernelet_mlp_noalloc_max_batch": ([], u32),
+           "kernelet_mlp_train_step_noalloc": ([f32p, f32p, f32p, f32p, f32p, f32p, u32, u32,
+                                                C.c_float, f32p, C.c_void_p], i32)}
     for name, (args, res) in opt.items():
         if hasattr(L, name):
             getattr(L, name).argtypes = args

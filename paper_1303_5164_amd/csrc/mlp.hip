@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 
 #include "kernelet.h"
@@ -198,4 +199,66 @@ extern "C" kl_status kernelet_mlp_train_step(float* params, float* m, float* v,
                                                      z2, dy, dz1, dz2, lr, b1, b2, eps, c1, c2);
     KL_HIPC(hipGetLastError());
     return KL_OK;
+}
+
+// ------------------------------------------------- training without allocation
+// The training step's workspace held in a file-scope device array, for
+// callers that cannot allocate device memory.  Each device the library runs
+// on holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device.
+namespace {
+
+constexpr uint32_t kNoAllocMaxBatch = 4096;
+constexpr size_t kScratchFloats = (size_t)kNoAllocMaxBatch * (4 * kH + 2);
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (looked up once per device, with
+// that device current).  Null, with the error set, on failure.
+float* scratch_for_current_device() {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        kl::set_error(std::string("kernelet_mlp_train_step_noalloc: hipGetDevice: ") +
+                      (e != hipSuccess ? hipGetErrorString(e) : "device index out of range"));
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            kl::set_error(std::string("kernelet_mlp_train_step_noalloc: hipGetSymbolAddress: ") +
+                          hipGetErrorString(e));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (float*)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" uint32_t kernelet_mlp_noalloc_max_batch(void) { return kNoAllocMaxBatch; }
+
+extern "C" kl_status kernelet_mlp_train_step_noalloc(float* params, float* m, float* v,
+                                                     const float* x, const float* t,
+                                                     const int32_t* idx, uint32_t batch,
+                                                     uint32_t step, float lr, float* grad_out,
+                                                     void* stream) {
+    if (batch > kNoAllocMaxBatch) {
+        kl::set_error("kernelet_mlp_train_step_noalloc: batch " + std::to_string(batch) +
+                      " exceeds the maximum of " + std::to_string(kNoAllocMaxBatch) +
+                      " samples its static workspace holds");
+        return KL_EINVAL;
+    }
+    float* ws = scratch_for_current_device();
+    if (!ws) return KL_EHIP;
+    // every workspace value the step reads is written by the same step
+    // before it is read, so the previous call's contents need no clearing
+    return kernelet_mlp_train_step(params, m, v, x, t, idx, batch, step, lr, grad_out, ws,
+                                   stream);
 }

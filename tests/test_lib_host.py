@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "kernelet.h")).read()
-    declared = set(re.findall(r"^\s*(?:kl_status|const char\*|uint64_t)\s+(kernelet_\w+)\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:kl_status|const char\*|uint64_t|uint32_t)\s+(kernelet_\w+)\(", hdr, re.M))
     assert declared == set(_lib.SYMBOLS)
     L = _lib.lib()
     for s in declared:

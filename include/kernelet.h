@@ -545,8 +545,9 @@ kl_status kernelet_mlp_train_step_noalloc(float* params, float* m, float* v, con
 /* --------------------------------------------------------------- logging */
 
 /* Time every launch of kernel k (enable != 0) with a pair of HIP events
- * recorded around it on the stream it is launched on.  Enabling resets the
- * kernel's counters. */
+ * carried by the launch itself (hipExtLaunchKernel's start and stop
+ * events: the dispatch's own begin and end, no extra packets on the
+ * stream).  Enabling resets the kernel's counters. */
 kl_status kernelet_time_kernel(kl_runtime* rt, kl_kernel k, int32_t enable);
 
 /* Launch timing of kernel k since it was enabled: summed GPU time of its

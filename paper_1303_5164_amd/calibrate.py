@@ -311,32 +311,38 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
     return out
 
 
-def run_slices(out_path: str, reps: int = 5, p: float = 0.02) -> dict:
+def slice_candidates(n_cu: int, largest: int, b_max_step: int = 8) -> list:
+    """Slice sizes b * n_cu tried for a kernel whose largest launch has
+    `largest` workgroups: b = 1, 2, 3, ... up to b_max_step, then doubling,
+    while the slice is smaller than the launch."""
+    out, b = [], 1
+    while b * n_cu < largest:
+        out.append(b)
+        b = b + 1 if b < b_max_step else 2 * b
+    return out
+
+
+def min_slice(unsliced_s: float, sliced: list, p: float = 0.02) -> int:
+    """The minimum slice (Section 4.1): the smallest slice size whose sliced
+    execution takes at most (1 + p) times the unsliced one, from
+    `sliced` = [(slice_wgs, seconds), ...]; 0 when none qualifies."""
+    ok = [w for w, t in sliced if t <= (1.0 + p) * unsliced_s]
+    return min(ok) if ok else 0
+
+
+def run_slices(out_path: str, reps: int = 7, p: float = 0.02) -> dict:
     """Minimum slice of each kernel (Section 4.1): the smallest slice of
-    b * n_cu workgroups (b = 1, 2, 4, ...) whose sliced execution takes at
-    most (1 + p) times the unsliced one; 0 when no slice size qualifies."""
+    b * n_cu workgroups (b = 1, 2, 3, ...; slice_candidates) whose sliced
+    execution takes at most (1 + p) times the unsliced one; 0 when no slice
+    size qualifies.  The search stops at the first size that qualifies."""
     import numpy as np
     import torch
 
-    import synth
     import paper_1303_5164_amd as K
     from paper_1303_5164_amd import workloads as W
 
     dev = torch.device("cuda:0")
-    F = synth.FULL
-    hosts = {
-        "poly": lambda: synth.poly(0, **F["poly"]),
-        "gather": lambda: synth.gather(0, **F["gather"]),
-        "sgemm": lambda: synth.sgemm(0, **F["sgemm"]),
-        "spmv": lambda: synth.spmv(0, **F["spmv"]),
-        "stencil": lambda: synth.stencil(0, F["stencil"]["ny"], F["stencil"]["nx"]),
-        "bs": lambda: synth.bs(0, F["bs"]["n"]),
-        "hist": lambda: synth.hist(0, F["hist"]["n"]),
-        "lookup": lambda: synth.lookup(0, **F["lookup"]),
-    }
-    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
-                              c1=F["stencil"]["c1"]),
-              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+    params = W.full_params()
     rt = K.Runtime(0)
     kids = {k: rt.register_builtin(k) for k in W.KERNELS}
     n_cu = rt.cfg.n_cu
@@ -360,19 +366,18 @@ def run_slices(out_path: str, reps: int = 5, p: float = 0.02) -> dict:
 
     out = {"n_cu": n_cu, "p": p, "kernels": {}}
     for kind in W.TYPES:
-        d_in = W.device_inputs(kind, hosts[kind](), dev)
+        d_in = W.device_inputs(kind, W.host_inputs(kind, 0), dev)
         inst = W.build(kind, d_in, params.get(kind, {}), dev)
         most = max(ln.grid[0] * ln.grid[1] * ln.grid[2] for ln in inst.launches)
         t_ns = wall(inst, 0)
-        rows, best = [], 0
-        b = 1
-        while b * n_cu < most and b <= 1024:
+        rows = []
+        for b in slice_candidates(n_cu, most):
             t_s = wall(inst, b * n_cu)
-            ov = t_s / t_ns - 1.0
-            rows.append({"b": b, "slice_wgs": b * n_cu, "ms": t_s * 1e3, "overhead": ov})
-            if ov <= p and best == 0:
-                best = b * n_cu
-            b *= 2
+            rows.append({"b": b, "slice_wgs": b * n_cu, "ms": t_s * 1e3,
+                         "overhead": t_s / t_ns - 1.0})
+            if min_slice(t_ns, [(b * n_cu, t_s)], p):
+                break
+        best = min_slice(t_ns, [(r["slice_wgs"], r["ms"] / 1e3) for r in rows], p)
         out["kernels"][kind] = {"unsliced_ms": t_ns * 1e3, "largest_launch_wgs": most,
                                 "min_slice_wgs": best, "sweep": rows}
         print(f"# {kind}: unsliced {t_ns * 1e3:.3f} ms; " + ", ".join(

@@ -7,13 +7,19 @@
 // co-schedule <K1, K2, b1, b2> puts K1 on one lane and K2 on the other and
 // launches their slices (b_i workgroups per CU, i.e. b_i * n_cu workgroups
 // per slice) back to back, keeping at most `inflight` slices queued per
-// lane.  Consecutive slices of a lane are ordered by the stream; a job that
-// changes lanes, or depends on a job last launched on another lane, first
-// makes the new lane wait on that job's last event.  When one kernel of the
+// lane.  Each slice's completion event is attached to its dispatch
+// (hipExtLaunchKernel's stop event), not recorded behind it: a recorded
+// event is a packet of its own that holds the queue until the slice has
+// drained (about 3.5 us of idle GPU per slice on MI355X), while an event
+// carried by the dispatch costs the GPU nothing.  Consecutive slices of a
+// lane are ordered by the stream; a job that changes lanes, or depends on a
+// job last launched on another lane, first makes the new lane wait on that
+// job's last event.  When one kernel of the
 // pair has launched all its workgroups the co-schedule ends and
 // FindCoSchedule runs again on the pending set, which holds the other
 // kernel's residual (Section 2.2: residuals and new arrivals are
 // re-optimised together).
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -67,7 +73,9 @@ struct EvPool {
     int get() {
         if (free_.empty()) {
             hipEvent_t e;
-            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return -1;
+            // timing enabled: a timed slice measures from its start event
+            // to this, its completion event
+            if (hipEventCreate(&e) != hipSuccess) return -1;
             ev.push_back(e);
             refs.push_back(0);
             free_.push_back((int)ev.size() - 1);
@@ -109,9 +117,12 @@ struct KernelType {
     int64_t time_launches = 0, time_wgs = 0;
 };
 
-// A timed launch waiting for its end event: (start, end, kernel, wgs).
-struct TimedLaunch {
-    hipEvent_t a, b;
+// A slice in flight on a lane: its completion event (pool index), its job,
+// and for a timed kernel the event its dispatch started.
+struct Inflight {
+    int ev;
+    kl_job job;
+    hipEvent_t start;
     int type;
     uint32_t wgs;
 };
@@ -140,7 +151,7 @@ struct Job {
 
 struct Lane {
     hipStream_t s = nullptr;
-    std::deque<std::pair<int, kl_job>> inflight;  // (event, job)
+    std::deque<Inflight> inflight;
     kl_job job = KL_NO_JOB;
     uint32_t slice = 0;
     uint32_t dyn_lds = 0;
@@ -156,6 +167,12 @@ struct kl_runtime {
     std::vector<kl::KernelType> kernels;
     std::map<kl_job, kl::Job> jobs;
     std::set<kl_job> live;  // jobs neither finished nor cancelled, in submission order
+    // live jobs with workgroups still to launch (waiting on a predecessor or
+    // pending), all and per kernel type, and live jobs not yet admitted by
+    // the memory budget: the dispatcher's scans visit these, not every job
+    std::set<kl_job> unlaunched;
+    std::vector<std::set<kl_job>> unlaunched_by_type;
+    std::set<kl_job> unadmitted;
     kl_job next_id = 0;
     std::vector<kl::Lane> lanes;
     kl::EvPool pool;
@@ -175,8 +192,7 @@ struct kl_runtime {
     // co-schedule currently issued
     bool cs_active = false;
     kl_job cs_job[3] = {KL_NO_JOB, KL_NO_JOB, KL_NO_JOB};
-    // launch timing
-    std::deque<kl::TimedLaunch> timed;
+    // start events of timed launches
     std::vector<hipEvent_t> tev_free;
     // surrogate network (kernelet_set_surrogate): parameters and batch
     // buffers on the device, staging in pinned host memory, its own stream
@@ -255,10 +271,24 @@ static void release_dependents(kl_runtime* rt, Job& j) {
     }
 }
 
+// The job has no workgroups left to launch (or will never launch them).
+static void leave_unlaunched(kl_runtime* rt, const Job& j) {
+    rt->unlaunched.erase(j.id);
+    if (j.type >= 0 && j.type < (int)rt->unlaunched_by_type.size())
+        rt->unlaunched_by_type[j.type].erase(j.id);
+}
+
+// The job leaves every scan set (finished or cancelled).
+static void forget_job(kl_runtime* rt, const Job& j) {
+    rt->live.erase(j.id);
+    rt->unadmitted.erase(j.id);
+    leave_unlaunched(rt, j);
+}
+
 static void mark_done(kl_runtime* rt, Job& j, bool error) {
     if (j.st == J_DONE) return;
     j.st = J_DONE;
-    rt->live.erase(j.id);
+    forget_job(rt, j);
     j.error = error;
     j.t_done = now_ns();
     int64_t rel = j.carry + (j.admitted ? (int64_t)j.footprint : 0);
@@ -289,34 +319,29 @@ static hipEvent_t timing_event(kl_runtime* rt) {
     return e;
 }
 
-// Accumulate the durations of timed launches that have finished.
-static void poll_timed(kl_runtime* rt) {
-    while (!rt->timed.empty()) {
-        TimedLaunch& t = rt->timed.front();
-        if (hipEventQuery(t.b) == hipErrorNotReady) break;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
-            KernelType& kt = rt->kernels[t.type];
-            kt.time_ms += ms;
-            kt.time_launches++;
-            kt.time_wgs += t.wgs;
-        }
-        rt->tev_free.push_back(t.a);
-        rt->tev_free.push_back(t.b);
-        rt->timed.pop_front();
-    }
-}
-
-// Retire finished slices on every lane and finished jobs.
+// Retire finished slices on every lane and finished jobs; a timed slice
+// adds its dispatch's duration (start event to completion event) to its
+// kernel's counters.
 static void poll_lanes(kl_runtime* rt) {
-    poll_timed(rt);
     for (auto& ln : rt->lanes) {
         while (!ln.inflight.empty()) {
-            int e = ln.inflight.front().first;
+            const Inflight f = ln.inflight.front();
+            const int e = f.ev;
             hipError_t q = hipEventQuery(rt->pool.ev[e]);
             if (q == hipErrorNotReady) break;
-            kl_job jid = ln.inflight.front().second;
+            const kl_job jid = f.job;
             ln.inflight.pop_front();
+            if (f.start) {
+                float ms = 0.f;
+                if (q == hipSuccess &&
+                    hipEventElapsedTime(&ms, f.start, rt->pool.ev[e]) == hipSuccess) {
+                    KernelType& kt = rt->kernels[f.type];
+                    kt.time_ms += ms;
+                    kt.time_launches++;
+                    kt.time_wgs += f.wgs;
+                }
+                rt->tev_free.push_back(f.start);
+            }
             auto it = rt->jobs.find(jid);
             if (it != rt->jobs.end()) {
                 Job& j = it->second;
@@ -394,45 +419,50 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
     s.gz = j.grid.z;
     s.reserved = 0;
     void* params[2] = {j.args.data(), &s};
-    hipEvent_t ta = nullptr, tb = nullptr;
+    hipEvent_t ta = nullptr;
     if (kt.timed) {
         ta = timing_event(rt);
-        tb = timing_event(rt);
-        if (!ta || !tb) {
+        if (!ta) {
             set_error("hipEventCreate failed");
             return KL_EHIP;
         }
-        KL_HIP(hipEventRecord(ta, ln.s));
     }
-    hipError_t e = kt.mfn ? hipModuleLaunchKernel(kt.mfn, count, 1, 1, kt.block, 1, 1,
-                                                  (unsigned)ln.dyn_lds, ln.s, params, nullptr)
-                          : hipLaunchKernel(kt.fn, dim3(count), dim3(kt.block), params,
-                                            ln.dyn_lds, ln.s);
-    if (e != hipSuccess) {
-        set_error(std::string("hipLaunchKernel(") + kt.name + "): " + hipGetErrorString(e));
-        j.error = true;
-        return KL_EHIP;
-    }
-    if (kt.timed) {
-        KL_HIP(hipEventRecord(tb, ln.s));
-        rt->timed.push_back({ta, tb, j.type, count});
+    if (kt.mfn && (uint64_t)count * kt.block > 0xffffffffull) {
+        if (ta) rt->tev_free.push_back(ta);
+        set_error("launch of " + kt.name + ": more than 2^32 work-items in one slice");
+        return KL_EINVAL;
     }
     int ev = rt->pool.get();
     if (ev < 0) {
+        if (ta) rt->tev_free.push_back(ta);
         set_error("hipEventCreate failed");
         return KL_EHIP;
     }
-    KL_HIP(hipEventRecord(rt->pool.ev[ev], ln.s));
+    // the completion event (and the start event of a timed kernel) travel
+    // with the dispatch itself
+    hipError_t e = kt.mfn ? hipExtModuleLaunchKernel(kt.mfn, count * kt.block, 1, 1, kt.block,
+                                                     1, 1, ln.dyn_lds, ln.s, params, nullptr,
+                                                     ta, rt->pool.ev[ev], 0)
+                          : hipExtLaunchKernel(kt.fn, dim3(count), dim3(kt.block), params,
+                                               ln.dyn_lds, ln.s, ta, rt->pool.ev[ev], 0);
+    if (e != hipSuccess) {
+        rt->pool.unref(ev);
+        if (ta) rt->tev_free.push_back(ta);
+        set_error(std::string("hipExtLaunchKernel(") + kt.name + "): " + hipGetErrorString(e));
+        j.error = true;
+        return KL_EHIP;
+    }
     if (j.next == 0) j.t_start = now_ns();
     j.next += count;
     rt->stats.slices_launched++;
-    ln.inflight.emplace_back(ev, jid);
+    ln.inflight.push_back(Inflight{ev, jid, ta, j.type, count});
     rt->pool.ref(ev);  // the job's reference
     rt->pool.unref(j.last_ev);
     j.last_ev = ev;
     j.last_lane = li;
     if (j.next >= j.total) {
         j.st = J_LAUNCHED;
+        leave_unlaunched(rt, j);
         release_dependents(rt, j);
     }
     return KL_OK;
@@ -441,15 +471,15 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
 // Admission by the memory budget: jobs in submission order while the
 // admitted footprint fits.
 static void admit(kl_runtime* rt) {
-    for (kl_job id : rt->live) {
-        Job& j = rt->jobs.at(id);
-        if (j.admitted) continue;
+    while (!rt->unadmitted.empty()) {
+        Job& j = rt->jobs.at(*rt->unadmitted.begin());
         if (rt->cfg.hbm_budget > 0 &&
             rt->resident + (int64_t)j.footprint > rt->cfg.hbm_budget)
             break;  // keep submission order: nothing later overtakes
         j.admitted = true;
         rt->resident += (int64_t)j.footprint;
         rt->resident_peak = std::max(rt->resident_peak, rt->resident);
+        rt->unadmitted.erase(rt->unadmitted.begin());
     }
 }
 
@@ -497,9 +527,9 @@ static uint32_t slice_size(kl_runtime* rt, const Job& j, int b) {
 static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
     Lane& ln = rt->lanes[0];
     ln.dyn_lds = 0;
-    for (kl_job id : rt->live) {
-        Job& j = rt->jobs.at(id);
-        if (j.st == J_LAUNCHED) continue;
+    for (auto it = rt->unlaunched.begin(); it != rt->unlaunched.end();) {
+        Job& j = rt->jobs.at(*it);
+        ++it;  // launching the job takes it out of the set
         if (!runnable(j)) break;
         kl_status s = launch_slice(rt, 0, j.id, j.total - j.next);
         if (s) return s;
@@ -519,7 +549,7 @@ static kl_status concurrent_step(kl_runtime* rt, bool* progressed) {
         ln.job = KL_NO_JOB;
         while ((int)ln.inflight.size() < rt->cfg.inflight) {
             Job* next = nullptr;
-            for (kl_job id : rt->live) {
+            for (kl_job id : rt->unlaunched) {
                 Job& j = rt->jobs.at(id);
                 if (runnable(j) && j.next == 0) {
                     next = &j;
@@ -614,10 +644,18 @@ static uint64_t splitmix64(uint64_t seed, uint64_t i) {
 }
 
 static void decide(kl_runtime* rt, kl_policy policy) {
+    // FindCoSchedule's candidates are the earliest runnable jobs of each
+    // kernel type (two per type when two instances of a kernel may pair):
+    // collect those, not every pending job
     std::vector<PendingJob> pend;
-    for (kl_job id : rt->live) {
-        const Job& j = rt->jobs.at(id);
-        if (runnable(j)) pend.push_back({id, j.type, (double)(j.total - j.next)});
+    for (const auto& ids : rt->unlaunched_by_type) {
+        int got = 0;
+        for (kl_job id : ids) {
+            const Job& j = rt->jobs.at(id);
+            if (!runnable(j)) continue;
+            pend.push_back({id, j.type, (double)(j.total - j.next)});
+            if (++got == 2) break;
+        }
     }
     rt->cs_active = false;
     rt->cs_job[0] = rt->cs_job[1] = rt->cs_job[2] = KL_NO_JOB;
@@ -793,13 +831,7 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
     return KL_OK;
 }
 
-static bool all_launched(kl_runtime* rt) {
-    for (kl_job id : rt->live) {
-        const Job& j = rt->jobs.at(id);
-        if (j.st == J_WAIT_DEP || j.st == J_PENDING) return false;
-    }
-    return true;
-}
+static bool all_launched(kl_runtime* rt) { return rt->unlaunched.empty(); }
 
 static bool any_inflight(kl_runtime* rt) {
     for (auto& ln : rt->lanes)
@@ -842,14 +874,12 @@ static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
             continue;
         }
         if (blocking && all_launched(rt) && (!wait_done || !any_inflight(rt))) break;
-        bool waiting_budget = false;
-        for (kl_job id : rt->live)
-            if (!rt->jobs.at(id).admitted) waiting_budget = true;
+        const bool waiting_budget = !rt->unadmitted.empty();
         if (blocking && !any_inflight(rt) && !waiting_budget) {
             // nothing in flight and nothing runnable: jobs wait on deps that
             // can never be released (e.g. a cancelled predecessor)
             bool runnable_any = false;
-            for (kl_job id : rt->live) runnable_any |= runnable(rt->jobs.at(id));
+            for (kl_job id : rt->unlaunched) runnable_any |= runnable(rt->jobs.at(id));
             if (!runnable_any) {
                 set_error("kernelet_schedule: jobs wait on dependencies that cannot finish");
                 st = KL_ESTATE;
@@ -939,6 +969,10 @@ static kl_job add_job(kl_runtime* rt, kl_kernel k, kl_dim3 grid, const void* arg
     }
     const kl_job id = j.id;
     rt->live.insert(id);
+    rt->unlaunched.insert(id);
+    if ((int)rt->unlaunched_by_type.size() <= k) rt->unlaunched_by_type.resize(k + 1);
+    rt->unlaunched_by_type[k].insert(id);
+    rt->unadmitted.insert(id);
     rt->jobs.emplace(id, std::move(j));
     rt->stats.jobs_submitted++;
     return id;
@@ -1018,11 +1052,10 @@ kl_status kernelet_shutdown(kl_runtime* rt) {
     }
     for (auto& ln : rt->lanes)
         if (ln.s) (void)hipStreamDestroy(ln.s);
+    for (auto& ln : rt->lanes)
+        for (auto& f : ln.inflight)
+            if (f.start) (void)hipEventDestroy(f.start);
     rt->pool.destroy();
-    for (auto& t : rt->timed) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
-    }
     for (auto e : rt->tev_free) (void)hipEventDestroy(e);
     if (rt->sur_stream) (void)hipStreamDestroy(rt->sur_stream);
     for (auto& k : rt->kernels)
@@ -1466,7 +1499,7 @@ kl_status kernelet_cancel(kl_runtime* rt, kl_job jid) {
     j.carry = 0;
     j.admitted = false;
     j.st = J_CANCELED;
-    rt->live.erase(j.id);
+    forget_job(rt, j);
     // dependants can never run: cancel them too
     std::vector<kl_job> todo = j.dependents;
     while (!todo.empty()) {
@@ -1479,7 +1512,7 @@ kl_status kernelet_cancel(kl_runtime* rt, kl_job jid) {
         dt->second.carry = 0;
         dt->second.admitted = false;
         dt->second.st = J_CANCELED;
-        rt->live.erase(d);
+        forget_job(rt, dt->second);
         for (kl_job x : dt->second.dependents) todo.push_back(x);
     }
     rt->cv.notify_all();
@@ -1554,7 +1587,7 @@ kl_status kernelet_kernel_time(kl_runtime* rt, kl_kernel k, double* total_ms,
         return KL_ENOTFOUND;
     }
     (void)hipSetDevice(rt->device);
-    poll_timed(rt);
+    poll_lanes(rt);
     const KernelType& kt = rt->kernels[k];
     if (total_ms) *total_ms = kt.time_ms;
     if (launches) *launches = kt.time_launches;

@@ -149,35 +149,85 @@ def submit(rt, kernel_ids: dict, inst: Instance, client: int = 0, after: int = -
                            footprint=inst.footprint)
 
 
-def full_hosts(seed: int = 0) -> tuple:
-    """Seeded host inputs of the eight kernels at their full sizes and the
-    per-kind parameters (stencil sweeps and coefficients, Black-Scholes rate
-    and volatility)."""
+def host_inputs(kind: str, seed: int) -> dict:
+    """Seeded host inputs of one kernel type at its full size."""
     import synth
     F = synth.FULL
-    hosts = {
-        "poly": synth.poly(seed, **F["poly"]),
-        "gather": synth.gather(seed, **F["gather"]),
-        "sgemm": synth.sgemm(seed, **F["sgemm"]),
-        "spmv": synth.spmv(seed, **F["spmv"]),
-        "stencil": synth.stencil(seed, F["stencil"]["ny"], F["stencil"]["nx"]),
-        "bs": synth.bs(seed, F["bs"]["n"]),
-        "hist": synth.hist(seed, F["hist"]["n"]),
-        "lookup": synth.lookup(seed, **F["lookup"]),
-    }
-    params = {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
-                              c1=F["stencil"]["c1"]),
-              "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
-    return hosts, params
+    if kind == "poly":
+        return synth.poly(seed, **F["poly"])
+    if kind == "gather":
+        return synth.gather(seed, **F["gather"])
+    if kind == "sgemm":
+        return synth.sgemm(seed, **F["sgemm"])
+    if kind == "spmv":
+        return synth.spmv(seed, **F["spmv"])
+    if kind == "stencil":
+        return synth.stencil(seed, F["stencil"]["ny"], F["stencil"]["nx"])
+    if kind == "bs":
+        return synth.bs(seed, F["bs"]["n"])
+    if kind == "hist":
+        return synth.hist(seed, F["hist"]["n"])
+    if kind == "lookup":
+        return synth.lookup(seed, **F["lookup"])
+    raise KeyError(kind)
 
 
-def mix(hosts: dict, params: dict, per_type: int, seed: int, device) -> list:
-    """The eight-kernel mix: `per_type` instances of every kind over shared
-    device inputs (each instance has its own outputs and scratch), in a
-    seeded random submission order."""
+def full_params() -> dict:
+    """Per-kind parameters: stencil sweeps and coefficients, Black-Scholes
+    rate and volatility."""
+    import synth
+    F = synth.FULL
+    return {"stencil": dict(iters=F["stencil"]["iters"], c0=F["stencil"]["c0"],
+                            c1=F["stencil"]["c1"]),
+            "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
+
+
+def full_hosts(seed: int = 0) -> tuple:
+    """Seeded host inputs of the eight kernels at their full sizes and the
+    per-kind parameters."""
+    return {k: host_inputs(k, seed) for k in TYPES}, full_params()
+
+
+def mix(hosts: dict, params: dict, per_type: int, seed: int, device,
+        distinct: bool = False) -> list:
+    """The eight-kernel mix: `per_type` instances of every kind in a seeded
+    random submission order, each with its own outputs and scratch.  With
+    `distinct`, instance i of a kind reads inputs of seed `seed + i` (the
+    host inputs given are seed `seed`'s, used by instance 0); otherwise all
+    instances of a kind share the given inputs read-only."""
     import numpy as np
+    insts = []
     dev_in = {k: device_inputs(k, h, device) for k, h in hosts.items()}
-    insts = [build(k, dev_in[k], params.get(k, {}), device)
-             for _ in range(per_type) for k in TYPES]
+    for i in range(per_type):
+        for k in TYPES:
+            d = dev_in[k]
+            if distinct and i > 0:
+                d = device_inputs(k, host_inputs(k, seed + i), device)
+            insts.append(build(k, d, params.get(k, {}), device))
     order = np.random.default_rng(seed).permutation(len(insts))
     return [insts[i] for i in order]
+
+
+def pair_mix(n_each: int, seed: int, device, table_pool: int = 16) -> list:
+    """The two-kernel mix: `n_each` polynomial and `n_each` gather
+    instances, arriving interleaved (polynomial i, then gather i).  Instance
+    i reads inputs of seed `seed + i` (its own x and coefficients, its own
+    indices); the gathers' 64 MiB tables come from a pool of `table_pool`
+    seeds, instance i using table i mod table_pool."""
+    import synth
+    F = synth.FULL
+    tables = {}
+    insts = []
+    for i in range(n_each):
+        hp = synth.poly(seed + i, **F["poly"])
+        insts.append(build("poly", device_inputs("poly", hp, device), {}, device))
+        ts = seed + i % table_pool
+        if ts not in tables:
+            tables[ts] = device_inputs(
+                "gather", {"table": synth.gather(ts, n=1, table=F["gather"]["table"])["table"]},
+                device)["table"]
+        hg = synth.gather(seed + i, **F["gather"], with_table=False)
+        dg = device_inputs("gather", hg, device)
+        dg["table"] = tables[ts]
+        insts.append(build("gather", dg, {}, device))
+    return insts

@@ -135,11 +135,15 @@ def poly(seed=0, n=1 << 20, ncoef=257):
                 coef=uniform_f32(seed, STREAM["poly_coef"], ncoef, -1.0, 1.0))
 
 
-def gather(seed=0, n=1 << 22, table=1 << 24):
-    """Random gather: idx ~ U{0..table-1}, table of random int32."""
-    t = raw_u64(seed, STREAM["gather_table"], table)
-    return dict(idx=below_u32(seed, STREAM["gather_idx"], n, table).view(np.int32),
-                table=(t >> np.uint64(32)).astype(np.uint32).view(np.int32))
+def gather(seed=0, n=1 << 22, table=1 << 24, with_table=True):
+    """Random gather: idx ~ U{0..table-1}, table of random int32 (left out
+    when with_table is false, for instances that share another seed's
+    table)."""
+    d = dict(idx=below_u32(seed, STREAM["gather_idx"], n, table).view(np.int32))
+    if with_table:
+        t = raw_u64(seed, STREAM["gather_table"], table)
+        d["table"] = (t >> np.uint64(32)).astype(np.uint32).view(np.int32)
+    return d
 
 
 def sgemm(seed=0, m=4096, n=4096, k=4096):
@@ -181,8 +185,9 @@ def hist(seed=0, n=1 << 28):
 
 def lookup(seed=0, nkeys=1 << 26, nq=1 << 26, gap_max=63):
     """Strictly increasing uint32 keys (gaps ~ U{1..gap_max}) and uint32
-    queries ~ U{0..2^32-1}."""
+    queries ~ U{0..last key}, so that every query's answer lies inside the
+    key array."""
     keys = np.empty(nkeys, dtype=np.uint32)
     assert nkeys * gap_max < 2**32
     lib().synth_sorted_keys(seed, STREAM["lookup_gap"], nkeys, gap_max, _ptr(keys))
-    return dict(keys=keys, q=below_u32(seed, STREAM["lookup_q"], nq, 2**32))
+    return dict(keys=keys, q=below_u32(seed, STREAM["lookup_q"], nq, int(keys[-1]) + 1))

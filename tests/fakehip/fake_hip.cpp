@@ -1,5 +1,6 @@
 // TEST DOUBLE: host-thread implementation of hip_runtime.h (see there).
 #include "hip/hip_runtime.h"
+#include "hip/hip_ext.h"
 
 #include <chrono>
 #include <condition_variable>
@@ -233,6 +234,27 @@ hipError_t hipModuleLaunchKernel(hipFunction_t f, unsigned gx, unsigned, unsigne
     s->q.push_back(std::move(op));
     g_cv.notify_all();
     return hipSuccess;
+}
+// The start event completes when the stream reaches the launch, the stop
+// event when the launch has run (both recorded around it on its stream).
+hipError_t hipExtLaunchKernel(const void* fn, dim3 grid, dim3 block, void** args,
+                              size_t shmem, hipStream_t s, hipEvent_t start, hipEvent_t stop,
+                              int) {
+    if (start && hipEventRecord(start, s) != hipSuccess) return hipErrorInvalidValue;
+    hipError_t e = hipLaunchKernel(fn, grid, block, args, shmem, s);
+    if (e != hipSuccess) return e;
+    return stop ? hipEventRecord(stop, s) : hipSuccess;
+}
+hipError_t hipExtModuleLaunchKernel(hipFunction_t f, uint32_t gwx, uint32_t gwy, uint32_t gwz,
+                                    uint32_t lx, uint32_t ly, uint32_t lz, size_t shmem,
+                                    hipStream_t s, void** params, void** extra,
+                                    hipEvent_t start, hipEvent_t stop, uint32_t) {
+    if (lx == 0 || gwx % lx) return hipErrorInvalidValue;
+    if (start && hipEventRecord(start, s) != hipSuccess) return hipErrorInvalidValue;
+    hipError_t e = hipModuleLaunchKernel(f, gwx / lx, gwy, gwz, lx, ly, lz, (unsigned)shmem, s,
+                                         params, extra);
+    if (e != hipSuccess) return e;
+    return stop ? hipEventRecord(stop, s) : hipSuccess;
 }
 hipError_t hipFuncGetAttribute(int* v, hipFunction_attribute a, hipFunction_t) {
     *v = a == HIP_FUNC_ATTRIBUTE_NUM_REGS ? 32 : 0;

@@ -49,6 +49,10 @@ def test_sorted_keys_strictly_increasing():
     k = d["keys"].astype(np.int64)
     g = np.diff(k)
     assert g.min() >= 1 and g.max() <= 63 and k[0] >= 1
+    # every query's lower bound lies inside the key array
+    q = d["q"].astype(np.int64)
+    assert q.min() >= 0 and q.max() <= k[-1]
+    assert np.searchsorted(k, q, side="left").max() < k.size
 
 
 def test_fnv1a_known_answer():

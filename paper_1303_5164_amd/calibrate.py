@@ -665,7 +665,7 @@ def main():
     r.add_argument("--reps", type=int, default=3)
     s = sub.add_parser("slices")
     s.add_argument("--out", required=True)
-    s.add_argument("--reps", type=int, default=5)
+    s.add_argument("--reps", type=int, default=7)
     c = sub.add_parser("ceilings")
     c.add_argument("--out", required=True)
     c.add_argument("--reps", type=int, default=5)

@@ -56,6 +56,21 @@ static int64_t now_ns() {
         .count();
 }
 
+// A short timed wait on the runtime's condition variable.  Thread-sanitizer
+// builds wait on the system clock (pthread_cond_timedwait, which their
+// runtime intercepts; a steady-clock wait goes through
+// pthread_cond_clockwait, which older ones do not see, and they then report
+// lock errors that are not there); other builds wait on the steady clock,
+// immune to clock steps.
+template <class Lock>
+static void wait_us(std::condition_variable& cv, Lock& lk, int64_t us) {
+#if defined(__SANITIZE_THREAD__)
+    cv.wait_until(lk, std::chrono::system_clock::now() + std::chrono::microseconds(us));
+#else
+    cv.wait_for(lk, std::chrono::microseconds(us));
+#endif
+}
+
 #define KL_HIP(call)                                                              \
     do {                                                                          \
         hipError_t e_ = (call);                                                   \
@@ -887,7 +902,7 @@ static kl_status dispatch(kl_runtime* rt, kl_policy policy, bool blocking,
             }
         }
         // nothing to do now: wait for a slice to finish or a submission
-        rt->cv.wait_for(lk, std::chrono::microseconds(any_inflight(rt) ? 5 : 200));
+        wait_us(rt->cv, lk, any_inflight(rt) ? 5 : 200);
     }
     poll_lanes(rt);
     rt->scheduling = false;
@@ -1429,7 +1444,7 @@ kl_status kernelet_wait(kl_runtime* rt, kl_job jid, int64_t timeout_ns) {
             set_error("kernelet_wait: timed out");
             return KL_ETIMEOUT;
         }
-        rt->cv.wait_for(lk, std::chrono::microseconds(20));
+        wait_us(rt->cv, lk, 20);
     }
 }
 

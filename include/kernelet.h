@@ -205,7 +205,13 @@ typedef struct {
                               three-kernel model (Section 4.4) predicts a
                               larger objective for the best ratio of all
                               three than for the pair; needs lanes >= 3 (2) */
-    int32_t reserved[3];
+    int32_t inflight_us;   /* besides `inflight` slices, a lane keeps launching
+                              while less than this many microseconds of
+                              predicted work (the profile's solo rate) are
+                              queued on it, up to 64 slices, so that slices
+                              shorter than a launch call do not starve the
+                              GPU (50; 0: the slice count alone)          */
+    int32_t reserved[2];
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this

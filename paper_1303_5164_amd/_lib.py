@@ -63,7 +63,7 @@ class Config(C.Structure):
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
                 ("random_seed", C.c_uint32), ("solo_overlap", C.c_int32),
                 ("pair_same_type", C.c_int32), ("group_max", C.c_int32),
-                ("reserved", C.c_int32 * 3),
+                ("inflight_us", C.c_int32), ("reserved", C.c_int32 * 2),
                 ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 

@@ -341,10 +341,17 @@ def run_slices(out_path: str, reps: int = 7, p: float = 0.02) -> dict:
     import paper_1303_5164_amd as K
     from paper_1303_5164_amd import workloads as W
 
+    from paper_1303_5164_amd import profiles
     dev = torch.device("cuda:0")
     params = W.full_params()
-    rt = K.Runtime(0)
-    kids = {k: rt.register_builtin(k) for k in W.KERNELS}
+    # with the profile table, the lanes keep `inflight_us` of predicted work
+    # queued; without it (the first calibration) a deep slice window
+    try:
+        prof = profiles.load()
+    except (OSError, KeyError, ValueError):
+        prof = None
+    rt = K.Runtime(0) if prof else K.Runtime(0, inflight=16)
+    kids = {k: rt.register_builtin(k, prof[k] if prof else None) for k in W.KERNELS}
     n_cu = rt.cfg.n_cu
     assert n_cu > 0
 

@@ -140,6 +140,7 @@ struct Inflight {
     hipEvent_t start;
     int type;
     uint32_t wgs;
+    double pred_us;  // predicted duration (0: unknown)
 };
 
 enum JobState { J_WAIT_DEP = 0, J_PENDING, J_LAUNCHED, J_DONE, J_CANCELED };
@@ -167,6 +168,8 @@ struct Job {
 struct Lane {
     hipStream_t s = nullptr;
     std::deque<Inflight> inflight;
+    double queued_us = 0;  // predicted work of the slices in flight
+    int unpredicted = 0;   // slices in flight without a prediction
     kl_job job = KL_NO_JOB;
     uint32_t slice = 0;
     uint32_t dyn_lds = 0;
@@ -242,6 +245,7 @@ static kl_config defaults() {
     c.beta = 0.0;
     c.lanes = 2;
     c.inflight = 2;
+    c.inflight_us = 50;
     c.lds_reserve = 2;
     c.max_slices = 0;
     c.hbm_budget = 0;
@@ -253,7 +257,8 @@ static kl_status check_cfg(const kl_config& c) {
     if (c.wmax < 1 || c.wmax > 16 || c.vgpr_file < 1 || c.lds_cu < 0 || c.lanes < 1 ||
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
-        c.lds_reserve < 0 || c.lds_reserve > 2 || c.surrogate_topk < 0 || c.max_slices < 0 ||
+        c.lds_reserve < 0 || c.lds_reserve > 2 || c.inflight_us < 0 ||
+        c.inflight_us > 100000 || c.surrogate_topk < 0 || c.max_slices < 0 ||
         c.solo_overlap < 0 || c.solo_overlap > 1 || c.pair_same_type < 0 ||
         c.pair_same_type > 1 || c.group_max < 2 || c.group_max > 3 ||
         c.hbm_budget < 0) {
@@ -346,6 +351,8 @@ static void poll_lanes(kl_runtime* rt) {
             if (q == hipErrorNotReady) break;
             const kl_job jid = f.job;
             ln.inflight.pop_front();
+            ln.queued_us = ln.inflight.empty() ? 0.0 : std::max(0.0, ln.queued_us - f.pred_us);
+            if (f.pred_us <= 0) --ln.unpredicted;
             if (f.start) {
                 float ms = 0.f;
                 if (q == hipSuccess &&
@@ -403,6 +410,26 @@ static uint32_t dyn_lds_for(kl_runtime* rt, const KernelType& kt, int b_self, in
     int64_t cap = kLdsPerWg - kt.static_lds;
     if (per > cap) per = cap;
     return per > 0 ? (uint32_t)((per + 255) & ~255ll) : 0u;
+}
+
+// Predicted duration of `count` workgroups of kernel kt run alone, in
+// microseconds (its profile's solo rate; an issue slot is 4 cycles at
+// 2.4 GHz); 0 when the kernel has no profile.
+static double predict_us(kl_runtime* rt, const KernelType& kt, int type, uint32_t count) {
+    if (!kt.has_prof) return 0.0;
+    const double ipc = kt.prof.solo_ipc > 0 ? kt.prof.solo_ipc : rt->planner->solo(type);
+    const double rate = wg_rate(kt.prof, ipc, rt->cfg.n_cu);  // workgroups per slot
+    return rate > 0 ? (double)count / rate * (4.0 / 2400.0) : 0.0;
+}
+
+// Whether lane ln may queue another slice of a co-schedule: fewer than
+// `inflight` slices, or less than `inflight_us` of predicted work when every
+// slice in flight has a prediction (at most 64 slices).
+static bool lane_has_room(kl_runtime* rt, const Lane& ln) {
+    const size_t n = ln.inflight.size();
+    if ((int)n < rt->cfg.inflight) return true;
+    if (rt->cfg.inflight_us <= 0 || n >= 64 || ln.unpredicted > 0) return false;
+    return ln.queued_us < (double)rt->cfg.inflight_us;
 }
 
 // Launch the next slice of job `jid` on lane `li`, `count` workgroups.
@@ -470,7 +497,10 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
     if (j.next == 0) j.t_start = now_ns();
     j.next += count;
     rt->stats.slices_launched++;
-    ln.inflight.push_back(Inflight{ev, jid, ta, j.type, count});
+    const double pred = predict_us(rt, kt, j.type, count);
+    ln.inflight.push_back(Inflight{ev, jid, ta, j.type, count, pred});
+    ln.queued_us += pred;
+    if (pred <= 0) ++ln.unpredicted;
     rt->pool.ref(ev);  // the job's reference
     rt->pool.unref(j.last_ev);
     j.last_ev = ev;
@@ -824,7 +854,7 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
         Job& j = rt->jobs.at(ln.job);
         const bool hold_others = solo && !rt->cfg.solo_overlap &&
                                  !(j.next == 0 && too_short_to_pair(rt, j));
-        while ((int)ln.inflight.size() < rt->cfg.inflight && j.next < j.total) {
+        while (lane_has_room(rt, ln) && j.next < j.total) {
             kl_status s = launch_slice(rt, li, j.id, ln.slice);
             if (s) return s;
             *progressed = true;

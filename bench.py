@@ -123,8 +123,9 @@ def algorithmic(kind, inst_args):
     if kind == "lookup":
         return 0.0, 8.0 * a.nq + 4.0 * a.nkeys, PEAK_VALU_F32
     if kind == "lookup_index":
+        # reads the keys once, writes the index
         ent = float(_index_entries(a.nkeys))
-        return 0.0, 8.0 * ent, PEAK_VALU_F32
+        return 0.0, 4.0 * a.nkeys + 4.0 * ent, PEAK_VALU_F32
     raise KeyError(kind)
 
 

@@ -100,15 +100,22 @@ typedef struct {
 
 /* lookup: out[t] = lower_bound(keys, q[t]) = smallest i with keys[i] >=
  * q[t], or nkeys if none; keys sorted ascending.  The search descends a
- * static 16-ary tree over the keys whose nodes are 64-byte lines: level 1
- * entry i is keys[min(16 i + 15, n - 1)] (the largest key of leaf line i),
- * level k + 1 entry i is level k entry min(16 i + 15, m_k - 1); level sizes
- * m_1 = ceil(n / 16), m_{k+1} = ceil(m_k / 16), stopping at the first level
- * with at most 1024 entries (searched in LDS).  `index` holds the levels
- * back to back (level 1 first), kernelet_lookup_index_entries(n) entries;
- * the "lookup_index" kernel writes it (grid = ceil(entries / 256)) and the
- * "lookup" kernel reads it (four queries per thread, grid = ceil(nq / 1024)).
- * nq a multiple of 4, nkeys >= 1; keys, q, out, index 16-byte aligned. */
+ * static 32-ary tree of 128-byte nodes to a compressed leaf: leaf j holds
+ * keys 64 j .. 64 j + 63 as 16-bit distances below its largest key
+ * keys[min(64 j + 63, n - 1)], two per uint32 word (slot 2w in the low
+ * half), 32 words per leaf, slots past the last key 0; a leaf whose keys
+ * span more than 65534 has 0xffff in slot 0 and is searched in `keys`.
+ * Level 1 entry j is leaf j's largest key, level k + 1 entry i is level k
+ * entry min(32 i + 31, m_k - 1); sizes m_1 = ceil(n / 64), m_{k+1} =
+ * ceil(m_k / 32), stopping at the first level with at most 1024 entries
+ * (searched in LDS); each level padded to 32 entries with 0xffffffff.
+ * `index` holds the levels back to back (level 1 first), then the leaves:
+ * kernelet_lookup_index_entries(n) uint32 words in all.  The
+ * "lookup_index" kernel writes it (one thread per four words, grid =
+ * ceil(words / 1024)) and the "lookup" kernel reads it (four queries per
+ * thread, eight threads searching each query together, grid =
+ * ceil(nq / 1024)).  nq a multiple of 4, nkeys >= 1; keys, q, out, index
+ * 16-byte aligned. */
 typedef struct {
     const uint32_t* keys;
     const uint32_t* q;

@@ -270,24 +270,46 @@ __global__ __launch_bounds__(KL_WG) void kl_hist(kl_hist_args a, kl_slice s) {
 }
 
 // ---------------------------------------------------------------- lookup
-// lower_bound through a static 16-ary tree whose nodes are 64-byte lines:
-// the leaves are the keys themselves (16 per line), level 1 holds the
-// largest key of every leaf line, level k + 1 the largest entry of every
-// 16-entry node of level k, up to a top level of at most 1024 entries that
-// each workgroup keeps in LDS.  A query costs a binary search in LDS and
-// then one line per level.  Levels start on 64-byte boundaries; the tail of
-// each level's last node is padded with 0xffffffff.
+// lower_bound through a static 32-ary tree of 128-byte nodes over
+// compressed leaves.  A leaf is 64 consecutive keys kept as 16-bit
+// distances below the leaf's largest key, one 128-byte line (the L2 line)
+// per leaf, so the searched structure takes 2 bytes per key: for 2^26 keys
+// 128 MiB of leaves and a 4 MiB level 1, which the 256 MiB last-level cache
+// can hold while the 256 MiB key array is not read.  A leaf whose keys span
+// more than 65534 is flagged (its first distance is 0xffff) and searched in
+// the key array instead.  Level 1 holds the largest key of every leaf, level
+// k + 1 the largest entry of every 32-entry node of level k, up to a top
+// level of at most 1024 entries that each workgroup keeps in LDS.  Levels
+// and leaves start on 128-byte boundaries; the tail of each level's last
+// node is padded with 0xffffffff, a leaf's slots past the last key hold 0.
+//
+// Eight lanes search one query together: each reads 16 bytes of the same
+// 128-byte node or leaf and the eight partial counts are summed across the
+// lanes, so a wave's load touches 8 lines, not 64 (the per-CU address
+// path, about one line per clock, bounds a search whose every lane reads
+// its own line).
+constexpr uint32_t kLkLeaf = 64;       // keys per leaf
+constexpr uint32_t kLkLeafWords = 32;  // uint32 words per leaf (two distances each)
+constexpr uint32_t kLkFan = 32;        // entries per node
+constexpr uint32_t kLkEscape = 0xffffu;
+// lanes whose queries a group searches at once: one (74 VGPRs, six waves per
+// SIMD) measured 1.9 ms for 2^26 queries, two (106 VGPRs) 2.5 ms
+constexpr int kLkLanesPerStep = 1;
+
 struct LkLevels {
     uint32_t nlev;
     uint64_t off[8];  // first entry of each level (level 1 first)
     uint64_t m[8];    // entries of each level
-    uint64_t total;   // entries including padding
+    uint64_t leaf_off;  // first word of the leaves
+    uint64_t nleaf;
+    uint64_t total;   // words including padding and leaves
 };
 
 // Fully unrolled so that every array index is a constant: the level
-// tables stay in registers (n < 2^31 needs at most 6 levels).
+// tables stay in registers (n < 2^31 needs at most 4 levels).
 __host__ __device__ inline void lk_levels(uint32_t n, LkLevels* L) {
-    uint64_t m = ((uint64_t)n + 15) / 16, off = 0;
+    const uint64_t nleaf = ((uint64_t)n + kLkLeaf - 1) / kLkLeaf;
+    uint64_t m = nleaf, off = 0;
     bool done = false;
     L->nlev = 0;
 #pragma unroll
@@ -296,60 +318,116 @@ __host__ __device__ inline void lk_levels(uint32_t n, LkLevels* L) {
         L->off[k] = off;
         if (!done) {
             L->nlev = k + 1;
-            off += (m + 15) / 16 * 16;
+            off += (m + kLkFan - 1) / kLkFan * kLkFan;
             if (m <= 1024)
                 done = true;
             else
-                m = (m + 15) / 16;
+                m = (m + kLkFan - 1) / kLkFan;
         }
     }
-    L->total = off;
+    L->leaf_off = off;
+    L->nleaf = nleaf;
+    L->total = off + nleaf * kLkLeafWords;
 }
 
-__device__ __forceinline__ uint32_t kl_highbit(uint32_t v) {
-    return v ? 1u << (31 - __builtin_clz(v)) : 0u;
-}
-
+// One thread per four words of the index (16 bytes): four level entries, or
+// eight leaf distances.
 __global__ __launch_bounds__(KL_WG) void kl_lookup_index(kl_lookup_args a, kl_slice s) {
     LkLevels L;
     lk_levels(a.nkeys, &L);
-    const uint64_t e = (uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x;
+    const uint64_t e = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
     if (e >= L.total) return;
-    // the level holding entry e, by constant-index selects
-    uint32_t k = 0;
-    uint64_t base = L.off[0], mk = L.m[0];
+    const uint32_t n = a.nkeys;
+    uint4 v;
+    if (e >= L.leaf_off) {
+        const uint64_t w = e - L.leaf_off;
+        const uint64_t j = w / kLkLeafWords;
+        const uint64_t k0 = j * kLkLeaf + 2 * (w % kLkLeafWords);  // 8 keys from k0
+        const uint64_t last = j * kLkLeaf + kLkLeaf - 1 < n ? j * kLkLeaf + kLkLeaf - 1 : n - 1;
+        const uint32_t mx = a.keys[last];
+        if (mx - a.keys[j * kLkLeaf] > kLkEscape - 1) {
+            // searched in the keys: the flag in slot 0, nothing else
+            v = make_uint4(w % kLkLeafWords == 0 ? kLkEscape : 0u, 0u, 0u, 0u);
+        } else {
+            uint32_t d[8];
+            if (k0 + 8 <= n) {
+                const uint4* kp = (const uint4*)(a.keys + k0);  // 32-byte aligned
+                const uint4 x = kp[0], y = kp[1];
+                d[0] = mx - x.x; d[1] = mx - x.y; d[2] = mx - x.z; d[3] = mx - x.w;
+                d[4] = mx - y.x; d[5] = mx - y.y; d[6] = mx - y.z; d[7] = mx - y.w;
+            } else {
 #pragma unroll
-    for (int j = 1; j < 8; ++j)
-        if (j < (int)L.nlev && e >= L.off[j]) {
-            k = j;
-            base = L.off[j];
-            mk = L.m[j];
+                for (int i = 0; i < 8; ++i) d[i] = k0 + i < n ? mx - a.keys[k0 + i] : 0u;
+            }
+            v = make_uint4(d[0] | (d[1] << 16), d[2] | (d[3] << 16), d[4] | (d[5] << 16),
+                           d[6] | (d[7] << 16));
         }
-    const uint64_t i = e - base;
-    uint32_t v = 0xffffffffu;
-    if (i < mk) {
-        // entry i of level k + 1 covers keys [16^(k+1) i, 16^(k+1) (i + 1))
-        const uint64_t span = 1ull << (4 * (k + 1));
-        uint64_t last = (i + 1) * span;
-        if (last > a.nkeys) last = a.nkeys;
-        v = a.keys[last - 1];
+    } else {
+        // the level holding entries e .. e + 3 (levels are padded to 32)
+        uint32_t k = 0;
+        uint64_t base = L.off[0], mk = L.m[0];
+#pragma unroll
+        for (int jl = 1; jl < 8; ++jl)
+            if (jl < (int)L.nlev && e >= L.off[jl]) {
+                k = jl;
+                base = L.off[jl];
+                mk = L.m[jl];
+            }
+        // entry i of level k + 1 covers keys [64 32^k i, 64 32^k (i + 1))
+        const uint64_t span = (uint64_t)kLkLeaf << (5 * k);
+        uint32_t x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint64_t i = e + t - base;
+            uint64_t last = (i + 1) * span;
+            if (last > n) last = n;
+            x[t] = i < mk ? a.keys[last - 1] : 0xffffffffu;
+        }
+        v = make_uint4(x[0], x[1], x[2], x[3]);
     }
-    a.index[e] = v;
+    *(uint4*)(a.index + e) = v;
 }
 
 // The queries and results stream through once: nontemporal accesses keep
-// them from displacing the tree's upper levels in the caches.
+// them from displacing the tree and the leaves in the caches.
 typedef uint32_t kl_u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint32_t lk_count16(const uint32_t* p, uint32_t q) {
-    const uint4* v = (const uint4*)p;
-    uint32_t c = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint4 x = v[j];
-        c += (x.x < q) + (x.y < q) + (x.z < q) + (x.w < q);
-    }
-    return c;
+// Sum over the eight lanes of a group (lanes 8g .. 8g + 7 of the wave) by
+// data-parallel-primitive moves: swap neighbours (quad_perm 1,0,3,2), swap
+// pairs (quad_perm 2,3,0,1), then add the other quad of the eight
+// (row_half_mirror: lane i of a half row reads lane 7 - i).
+__device__ __forceinline__ uint32_t lk_sum8(uint32_t v) {
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
+    return (uint32_t)x;
+}
+
+// Entries of the LDS top level (mt of them, sorted, padded with 0xffffffff
+// to the next multiple of 8 as far as 1024) that are < q, found by the
+// eight lanes of a group together in three rounds: pivots 128 apart, then
+// 16 apart, then two entries per lane.
+__device__ __forceinline__ uint32_t lk_top_count(const uint32_t* top, uint32_t mt, uint32_t q,
+                                                 uint32_t r) {
+    uint32_t base = 0;
+    // round 1: lane r tests the last entry of block r of 128
+    uint32_t p = 128 * r + 127;
+    uint32_t c = lk_sum8(p < mt && top[p] < q);
+    base = 128 * c;
+    // round 2: lane r tests the last entry of block r of 16 in that block
+    p = base + 16 * r + 15;
+    c = lk_sum8(p < mt && top[p] < q);
+    base += 16 * c;
+    // round 3: lane r tests two entries of that block of 16
+    p = base + 2 * r;
+    c = lk_sum8((p < mt && top[p] < q) + (p + 1 < mt && top[p + 1] < q));
+    return base + c;
+}
+
+// Distances of a uint32 word (two leaf slots) above t.
+__device__ __forceinline__ uint32_t lk_above2(uint32_t w, uint32_t t) {
+    return ((w & 0xffffu) > t) + ((w >> 16) > t);
 }
 
 __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
@@ -367,45 +445,85 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
         }
     for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[top_off + i];
     __syncthreads();
+    // every lane loads its own four queries; lanes past the end search dummy
+    // queries (the eight lanes of a group work together) and store nothing
     const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
-    if (t0 >= a.nq) return;
-    const kl_u32x4 qv = __builtin_nontemporal_load((const kl_u32x4*)(a.q + t0));
-    const uint32_t q[4] = {qv.x, qv.y, qv.z, qv.w};
-    uint32_t c[4] = {0, 0, 0, 0};
-    for (uint32_t st = kl_highbit(mt); st; st >>= 1)
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (c[i] + st <= mt && top[c[i] + st - 1] < q[i]) c[i] += st;
-    bool past[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) past[i] = c[i] >= mt;  // above every key
-    const uint32_t* __restrict__ idx = a.index;
-#pragma unroll
-    for (int k = 6; k >= 0; --k) {
-        if (k >= (int)T) continue;   // uniform: levels below the top only
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (!past[i]) c[i] = 16 * c[i] + lk_count16(idx + L.off[k] + 16 * (uint64_t)c[i], q[i]);
-    }
+    const bool valid = t0 < a.nq;
+    kl_u32x4 qv = {0u, 0u, 0u, 0u};
+    if (valid) qv = __builtin_nontemporal_load((const kl_u32x4*)(a.q + t0));
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g8 = lane & ~7u;  // first lane of this lane's group
+    const uint32_t r = lane & 7u;    // this lane's 16 bytes of a line
     const uint32_t n = a.nkeys;
-    const uint32_t* __restrict__ keys = a.keys;
-    kl_u32x4 o;
+    const uint32_t* __restrict__ idx = a.index;
+    kl_u32x4 o = {n, n, n, n};
+    // the group searches the four queries of kLkLanesPerStep of its lanes at
+    // a time (their loads in flight together), its eight lanes in turn
+    constexpr int QB = 4 * kLkLanesPerStep;
+    for (uint32_t b = 0; b < 8; b += kLkLanesPerStep) {
+        uint32_t q[QB], c[QB];
+        bool past[QB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        uint32_t r = n;
-        if (!past[i]) {
-            const uint64_t base = 16 * (uint64_t)c[i];
-            if (base + 16 <= n) {
-                r = (uint32_t)base + lk_count16(keys + base, q[i]);
-            } else {
-                uint32_t cnt = 0;
-                for (uint64_t j = base; j < n; ++j) cnt += keys[j] < q[i];
-                r = (uint32_t)base + cnt;
+        for (int l = 0; l < kLkLanesPerStep; ++l) {
+            const int src = (int)(g8 + b + l);
+            q[4 * l + 0] = (uint32_t)__shfl((int)qv.x, src);
+            q[4 * l + 1] = (uint32_t)__shfl((int)qv.y, src);
+            q[4 * l + 2] = (uint32_t)__shfl((int)qv.z, src);
+            q[4 * l + 3] = (uint32_t)__shfl((int)qv.w, src);
+        }
+#pragma unroll
+        for (int i = 0; i < QB; ++i) c[i] = lk_top_count(top, mt, q[i], r);
+#pragma unroll
+        for (int i = 0; i < QB; ++i) {
+            past[i] = c[i] >= mt;  // above every key
+            if (past[i]) c[i] = 0;  // searched as query 0, answer n
+        }
+#pragma unroll
+        for (int k = 6; k >= 0; --k) {
+            if (k >= (int)T) continue;  // uniform: levels below the top only
+            uint4 x[QB];
+#pragma unroll
+            for (int i = 0; i < QB; ++i)
+                x[i] = *(const uint4*)(idx + L.off[k] + kLkFan * (uint64_t)c[i] + 4 * r);
+#pragma unroll
+            for (int i = 0; i < QB; ++i) {
+                const uint32_t cnt = (x[i].x < q[i]) + (x[i].y < q[i]) + (x[i].z < q[i]) +
+                                     (x[i].w < q[i]);
+                c[i] = kLkFan * c[i] + lk_sum8(cnt);
             }
         }
-        o[i] = r;
+        // c[i]: the leaf holding the answer, the first whose largest key
+        // is >= q[i]
+        uint4 w[QB];
+        uint32_t mx[QB];
+#pragma unroll
+        for (int i = 0; i < QB; ++i) {
+            w[i] = *(const uint4*)(idx + L.leaf_off + kLkLeafWords * (uint64_t)c[i] + 4 * r);
+            mx[i] = idx[L.off[0] + c[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < QB; ++i) {
+            // slot 0 (the group's first lane) flags a leaf searched in the keys
+            const bool esc = lk_sum8(r == 0 && (w[i].x & 0xffffu) == kLkEscape) != 0;
+            uint32_t cnt;
+            if (!esc) {
+                // key < q exactly when its distance below the leaf's largest
+                // key exceeds mx - q (q <= mx here)
+                const uint32_t t = mx[i] - q[i];
+                cnt = lk_above2(w[i].x, t) + lk_above2(w[i].y, t) + lk_above2(w[i].z, t) +
+                      lk_above2(w[i].w, t);
+            } else {
+                cnt = 0;
+                const uint64_t k0 = (uint64_t)c[i] * kLkLeaf + 8 * r;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) cnt += k0 + u < n && a.keys[k0 + u] < q[i];
+            }
+            cnt = lk_sum8(cnt);  // the whole group takes the same branch
+            const uint32_t res = past[i] ? n : c[i] * kLkLeaf + cnt;
+            if (lane == g8 + b + (uint32_t)(i / 4)) o[i % 4] = res;
+        }
     }
-    __builtin_nontemporal_store(o, (kl_u32x4*)(a.out + t0));
+    if (valid) __builtin_nontemporal_store(o, (kl_u32x4*)(a.out + t0));
 }
 
 
@@ -629,7 +747,7 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         if (n == "lookup_index") {
             LkLevels L;
             lk_levels(a.nkeys, &L);
-            g->x = cdiv(L.total, KL_WG);
+            g->x = cdiv(L.total / 4, KL_WG);
         } else {
             if (!a.q || !a.out || a.nq == 0 || a.nq % 4)
                 return "null q or out, or nq not a positive multiple of 4";

@@ -99,6 +99,50 @@ def report(sweep_path: str, occupancy_path: str | None = None) -> str:
         m, (r, pv) = best[k]["meas"], best[k]["model"]
         out.append(f"| {k[0]} + {k[1]} | {m['speedup']:.3f} ({m['b1']}, {m['b2']}) | "
                    f"{pv:.3f} ({r['b1']}, {r['b2']}) | {r['speedup']:.3f} |")
+    # per co-run IPC and HBM traffic: each kernel's wave-instructions (issue
+    # slots, from its solo counter profile: instructions per wave times its
+    # waves) over the co-run's issue slots on every SIMD, and its DRAM bytes
+    # per launch (solo FETCH_SIZE + WRITE_SIZE) over the co-run time
+    slot_s = 4.0 / 2.4e9
+    n_cu = d.get("n_cu", 256)
+
+    def ipc_gbps(r):
+        out_ipc, byts = [], 0.0
+        for k, cnt in ((r["a"], r["na"]), (r["b"], r["nb"])):
+            p = prof[k]
+            # four waves per 256-thread workgroup, one per SIMD
+            waves = cnt * p.get("wgs_per_launch", 0) * 4 * p.get("waves_per_simd", 1)
+            out_ipc.append(waves * p["instr_per_wave"] /
+                           (r["co_ms"] * 1e-3 / slot_s * 4 * n_cu))
+            byts += cnt * (p.get("fetch_bytes_per_launch", 0) +
+                           p.get("write_bytes_per_launch", 0))
+        return out_ipc, byts / (r["co_ms"] * 1e-3) / 1e9
+
+    fr = sorted({r.get("frac") or 0 for r in rows})
+    if len(fr) > 1 or fr != [0]:
+        out += ["", "By slice size (fraction of each kernel's grid; all ratios): mean measured "
+                "S, model MAPE, mean co-run IPC of the two kernels (wave-instructions per "
+                "issue slot per SIMD) and mean HBM GB/s (solo counter bytes per launch over "
+                "the co-run time):", "",
+                "| slice | points | mean S | MAPE | IPC a + b | HBM GB/s |",
+                "|---|---:|---:|---:|---:|---:|"]
+        for f in fr:
+            sel = [i for i, r in enumerate(rows) if (r.get("frac") or 0) == f]
+            m, p_ = meas[sel], pred[sel]
+            ig = [ipc_gbps(rows[i]) for i in sel]
+            out.append(f"| {'1/' + str(f) if f else 'min'} | {len(sel)} | {m.mean():.3f} | "
+                       f"{np.mean(np.abs(p_ - m) / m):.3f} | "
+                       f"{np.mean([x[0][0] + x[0][1] for x in ig]):.3f} | "
+                       f"{np.mean([x[1] for x in ig]):.0f} |")
+    out += ["", "Per co-run (pair at its measured best ratio and slice): IPC of each kernel "
+            "and HBM GB/s:", "", "| Pair | S | slice | IPC a | IPC b | HBM GB/s |",
+            "|---|---:|---|---:|---:|---:|"]
+    for k in keys:
+        m = best[k]["meas"]
+        (ia, ib), g = ipc_gbps(m)
+        f = m.get("frac")
+        out.append(f"| {k[0]} + {k[1]} ({m['b1']}, {m['b2']}) | {m['speedup']:.3f} | "
+                   f"{'1/' + str(f) if f else 'min'} | {ia:.3f} | {ib:.3f} | {g:.0f} |")
     if occupancy_path:
         occ = json.load(open(occupancy_path)).get("solo_occupancy_ms", {})
         bs = sorted({int(b) for v in occ.values() for b in v})
@@ -130,6 +174,10 @@ def main():
     ap.add_argument("--slicing", default="exact", choices=["exact", "min", "none"],
                     help="exact: slices of b*n_cu WGs; min: max(b*n_cu, calibrated minimum "
                          "slice); none: whole launches")
+    ap.add_argument("--fractions", default=None,
+                    help="slice sizes as fractions of each kernel's grid, e.g. 64,32,16,8,4 "
+                         "(slices of ceil(grid / f) workgroups); every (pair, ratio) is run "
+                         "at each, in place of --slicing")
     ap.add_argument("--lds-reserve", type=int, default=0)
     ap.add_argument("--solo-occupancy", action="store_true",
                     help="also time every kernel alone at each occupancy b (held by LDS "
@@ -254,8 +302,9 @@ def main():
             print(f"# occupancy {kind}: " + ", ".join(
                 f"{b}:{v:.4f}" for b, v in solo_occ[kind].items()), file=sys.stderr, flush=True)
 
+    fracs = [int(f) for f in a.fractions.split(",")] if a.fractions else [None]
     rows = []
-    for ka, kb in itertools.combinations(kinds, 2):
+    for (ka, kb), frac in itertools.product(itertools.combinations(kinds, 2), fracs):
         pa, pb = prof[launch[ka][0]], prof[launch[kb][0]]
         na = max(1, round(a.window_ms / solo[ka]))
         nb = max(1, round(a.window_ms / solo[kb]))
@@ -269,6 +318,8 @@ def main():
                     b1 * pa["lds_bytes"] + b2 * pb["lds_bytes"] > 160 * 1024:
                 continue
             def sl(b, wg, p):
+                if frac:
+                    return -(-wg // frac)
                 if a.slicing == "none":
                     return 0
                 s = b * n_cu
@@ -299,12 +350,13 @@ def main():
                 pcp = 1.0 - 1.0 / (pr1 + pr2)
             except K.KerneletError:
                 pr1 = pr2 = pcp = float("nan")
-            row = dict(a=ka, b=kb, b1=b1, b2=b2, na=na_r, nb=nb_r, seq_ms=seq, co_ms=co_ms,
+            row = dict(a=ka, b=kb, b1=b1, b2=b2, frac=frac, slice_a=sl(b1, wga, pa),
+                       slice_b=sl(b2, wgb, pb), na=na_r, nb=nb_r, seq_ms=seq, co_ms=co_ms,
                        speedup=S, cp=1.0 - 1.0 / S, rel_a=sa, rel_b=sb,
                        pred_rel_a=pr1, pred_rel_b=pr2, pred_cp=pcp,
                        busy_a_ms=busy[ka][0], busy_b_ms=busy[kb][0])
             rows.append(row)
-            print(f"# {ka}+{kb} ({b1},{b2}): S={S:.3f} rel=({sa:.2f},{sb:.2f}) "
+            print(f"# {ka}+{kb} ({b1},{b2}) 1/{frac or 0}: S={S:.3f} rel=({sa:.2f},{sb:.2f}) "
                   f"pred=({pr1:.2f},{pr2:.2f}) cp={row['cp']:+.3f} pred_cp={pcp:+.3f}",
                   file=sys.stderr, flush=True)
     rt.close()

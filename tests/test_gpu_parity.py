@@ -128,6 +128,52 @@ def test_lookup_queries_within_the_keys(rtk, nkeys, nq, slice_wgs):
     assert np.array_equal(out, oracle.lower_bound(h["keys"], h["q"]))
 
 
+def _keys_from_gaps(gaps):
+    k = np.cumsum(np.asarray(gaps, np.int64))
+    assert k[-1] < 2**32
+    return k.astype(np.uint32)
+
+
+def _probe_queries(keys, extra):
+    """Every key, its neighbours, 0, 2^32 - 1 and `extra` queries drawn over
+    the key range; a multiple of 4."""
+    k = keys.astype(np.int64)
+    q = np.concatenate([k, k - 1, k + 1, [0, 2**32 - 1], extra.astype(np.int64)])
+    q = q[(q >= 0) & (q < 2**32)]
+    q = np.concatenate([q, np.zeros((-q.size) % 4, np.int64)])
+    return q.astype(np.uint32)
+
+
+@pytest.mark.parametrize("nkeys", [63, 64, 65, 64 * 1024, 64 * 1024 + 1, 64 * 1024 + 65,
+                                   64 * 32 * 1024 + 64])
+def test_lookup_leaf_and_level_boundaries(rtk, nkeys):
+    """Key counts at the edges of a 64-key leaf and of the LDS top level
+    (1024 leaves): a partial last leaf, exactly full leaves, one key past,
+    and a tree of three levels below a top of 33 entries."""
+    g = synth.below_u32(3, synth.STREAM["lookup_gap"], nkeys, 63).astype(np.int64) + 1
+    keys = _keys_from_gaps(g)
+    extra = synth.below_u32(4, synth.STREAM["lookup_q"], 4000, int(keys[-1]) + 2)
+    h = dict(keys=keys, q=_probe_queries(keys, extra))
+    out = _both(rtk, _case("lookup", h), 3)
+    assert np.array_equal(out, oracle.lower_bound(h["keys"], h["q"]))
+
+
+def test_lookup_wide_gaps_search_the_keys(rtk):
+    """Leaves whose keys span more than 16 bits are searched in the key
+    array: gaps of up to 2^20 between some keys, all of them for a second
+    key set."""
+    g = synth.below_u32(5, synth.STREAM["lookup_gap"], 5000, 63).astype(np.int64) + 1
+    wide = synth.below_u32(6, synth.STREAM["lookup_gap"], 40, 5000).astype(np.int64)
+    g[wide] = 60000 + synth.below_u32(7, synth.STREAM["lookup_gap"], 40, 1 << 20)
+    for keys in (_keys_from_gaps(g),
+                 _keys_from_gaps(1 + synth.below_u32(8, synth.STREAM["lookup_gap"], 3000,
+                                                     1 << 18).astype(np.int64))):
+        extra = synth.below_u32(9, synth.STREAM["lookup_q"], 4000, int(keys[-1]) + 2)
+        h = dict(keys=keys, q=_probe_queries(keys, extra))
+        out = _both(rtk, _case("lookup", h), 2)
+        assert np.array_equal(out, oracle.lower_bound(h["keys"], h["q"]))
+
+
 def test_lookup_all_queries_above_the_keys(rtk):
     keys = np.arange(1, 1001, dtype=np.uint32) * 3
     h = dict(keys=keys, q=np.full(8192, 10_000, np.uint32))

@@ -248,8 +248,11 @@ def test_builtin_descriptors_and_grids():
         K.builtin_grid("stencil", a)
     a = _lib.LookupArgs(16, 16, 16, 16, 1 << 26, 1 << 26)
     assert K.builtin_grid("lookup", a) == (1 << 16, 1, 1)
-    assert K.builtin_grid("lookup_index", a) == (4473856 // 256, 1, 1)
-    assert _lib.lib().kernelet_lookup_index_entries(1 << 26) == 4473856
+    # 2^20 leaves of 64 keys: levels of 2^20, 2^15 and 2^10 entries, then
+    # 32 words per leaf; one index thread per four words
+    words = (2**20 + 2**15 + 2**10) + 32 * 2**20
+    assert K.builtin_grid("lookup_index", a) == (words // 1024, 1, 1)
+    assert _lib.lib().kernelet_lookup_index_entries(1 << 26) == words
     a = _lib.SgemmArgs(16, 16, 16, 100, 4096, 4096)
     with pytest.raises(K.KerneletError) as e:
         K.builtin_grid("sgemm", a)

@@ -292,9 +292,9 @@ constexpr uint32_t kLkLeaf = 64;       // keys per leaf
 constexpr uint32_t kLkLeafWords = 32;  // uint32 words per leaf (two distances each)
 constexpr uint32_t kLkFan = 32;        // entries per node
 constexpr uint32_t kLkEscape = 0xffffu;
-// lanes whose queries a group searches at once: one (74 VGPRs, six waves per
-// SIMD) measured 1.9 ms for 2^26 queries, two (106 VGPRs) 2.5 ms
-constexpr int kLkLanesPerStep = 1;
+// lanes that search one query together: each reads 128 / kLkGroup bytes of
+// every node and leaf line
+constexpr int kLkGroup = 8;
 
 struct LkLevels {
     uint32_t nlev;
@@ -392,45 +392,56 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup_index(kl_lookup_args a, kl_sl
 // them from displacing the tree and the leaves in the caches.
 typedef uint32_t kl_u32x4 __attribute__((ext_vector_type(4)));
 
-// Sum over the eight lanes of a group (lanes 8g .. 8g + 7 of the wave) by
-// data-parallel-primitive moves: swap neighbours (quad_perm 1,0,3,2), swap
-// pairs (quad_perm 2,3,0,1), then add the other quad of the eight
-// (row_half_mirror: lane i of a half row reads lane 7 - i).
-__device__ __forceinline__ uint32_t lk_sum8(uint32_t v) {
+// Sum over the G lanes of a group (lanes G g .. G g + G - 1 of the wave, G
+// = 4 or 8) by data-parallel-primitive moves: swap neighbours (quad_perm
+// 1,0,3,2), swap pairs (quad_perm 2,3,0,1), and for eight lanes add the
+// other quad (row_half_mirror: lane i of a half row reads lane 7 - i).
+template <int G>
+__device__ __forceinline__ uint32_t lk_sum(uint32_t v) {
+    static_assert(G == 4 || G == 8, "groups of four or eight lanes");
     int x = (int)v;
     x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
     x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
-    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
+    if (G == 8) x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
     return (uint32_t)x;
 }
 
-// Entries of the LDS top level (mt of them, sorted, padded with 0xffffffff
-// to the next multiple of 8 as far as 1024) that are < q, found by the
-// eight lanes of a group together in three rounds: pivots 128 apart, then
-// 16 apart, then two entries per lane.
+// Entries of the LDS top level (mt <= 1024 of them, sorted) that are < q,
+// found by the G lanes of a group together: while the range left is longer
+// than 16 entries it is cut into G blocks and lane r tests the last entry
+// of block r; then each lane tests 16 / G entries of the last 16.
+template <int G>
 __device__ __forceinline__ uint32_t lk_top_count(const uint32_t* top, uint32_t mt, uint32_t q,
                                                  uint32_t r) {
     uint32_t base = 0;
-    // round 1: lane r tests the last entry of block r of 128
-    uint32_t p = 128 * r + 127;
-    uint32_t c = lk_sum8(p < mt && top[p] < q);
-    base = 128 * c;
-    // round 2: lane r tests the last entry of block r of 16 in that block
-    p = base + 16 * r + 15;
-    c = lk_sum8(p < mt && top[p] < q);
-    base += 16 * c;
-    // round 3: lane r tests two entries of that block of 16
-    p = base + 2 * r;
-    c = lk_sum8((p < mt && top[p] < q) + (p + 1 < mt && top[p + 1] < q));
-    return base + c;
+#pragma unroll
+    for (uint32_t R = 1024; R > 16; R /= G) {
+        const uint32_t B = R / G;
+        const uint32_t p = base + B * r + B - 1;
+        base += B * lk_sum<G>(p < mt && top[p] < q);
+    }
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < 16 / G; ++u) {
+        const uint32_t p = base + (16 / G) * r + u;
+        c += p < mt && top[p] < q;
+    }
+    return base + lk_sum<G>(c);
 }
 
-// Distances of a uint32 word (two leaf slots) above t.
-__device__ __forceinline__ uint32_t lk_above2(uint32_t w, uint32_t t) {
-    return ((w & 0xffffu) > t) + ((w >> 16) > t);
+// Leaf distances of a uint32 word (two slots) above tc (tc <= 0xffff),
+// compared as two 16-bit lanes.
+typedef uint16_t kl_u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t lk_above2(uint32_t w, kl_u16x2 tc) {
+    const kl_u16x2 d = __builtin_bit_cast(kl_u16x2, w);
+    typedef short kl_s16x2 __attribute__((ext_vector_type(2)));
+    const kl_s16x2 gt = d > tc;  // lanes -1 where true, 0 where false
+    return (uint32_t)(gt.x & 1) + (uint32_t)(gt.y & 1);
 }
 
-__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
+template <int G>
+__device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_slice& s) {
+    constexpr int W4 = 8 / G;  // 16-byte pieces of a 128-byte line per lane
     __shared__ uint32_t top[1024];
     LkLevels L;
     lk_levels(a.nkeys, &L);
@@ -446,84 +457,96 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s)
     for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[top_off + i];
     __syncthreads();
     // every lane loads its own four queries; lanes past the end search dummy
-    // queries (the eight lanes of a group work together) and store nothing
+    // queries (the lanes of a group work together) and store nothing
     const uint64_t t0 = ((uint64_t)kl_wg_linear(s) * KL_WG + threadIdx.x) * 4;
     const bool valid = t0 < a.nq;
     kl_u32x4 qv = {0u, 0u, 0u, 0u};
     if (valid) qv = __builtin_nontemporal_load((const kl_u32x4*)(a.q + t0));
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t g8 = lane & ~7u;  // first lane of this lane's group
-    const uint32_t r = lane & 7u;    // this lane's 16 bytes of a line
+    const uint32_t g0 = lane & ~(uint32_t)(G - 1);  // first lane of this lane's group
+    const uint32_t r = lane & (uint32_t)(G - 1);    // this lane's part of a line
     const uint32_t n = a.nkeys;
     const uint32_t* __restrict__ idx = a.index;
     kl_u32x4 o = {n, n, n, n};
-    // the group searches the four queries of kLkLanesPerStep of its lanes at
-    // a time (their loads in flight together), its eight lanes in turn
-    constexpr int QB = 4 * kLkLanesPerStep;
-    for (uint32_t b = 0; b < 8; b += kLkLanesPerStep) {
-        uint32_t q[QB], c[QB];
-        bool past[QB];
+    // the group searches the four queries of each of its lanes in turn
+    for (uint32_t b = 0; b < (uint32_t)G; ++b) {
+        const int src = (int)(g0 + b);
+        uint32_t q[4], c[4];
+        bool past[4];
+        q[0] = (uint32_t)__shfl((int)qv.x, src);
+        q[1] = (uint32_t)__shfl((int)qv.y, src);
+        q[2] = (uint32_t)__shfl((int)qv.z, src);
+        q[3] = (uint32_t)__shfl((int)qv.w, src);
 #pragma unroll
-        for (int l = 0; l < kLkLanesPerStep; ++l) {
-            const int src = (int)(g8 + b + l);
-            q[4 * l + 0] = (uint32_t)__shfl((int)qv.x, src);
-            q[4 * l + 1] = (uint32_t)__shfl((int)qv.y, src);
-            q[4 * l + 2] = (uint32_t)__shfl((int)qv.z, src);
-            q[4 * l + 3] = (uint32_t)__shfl((int)qv.w, src);
-        }
+        for (int i = 0; i < 4; ++i) c[i] = lk_top_count<G>(top, mt, q[i], r);
 #pragma unroll
-        for (int i = 0; i < QB; ++i) c[i] = lk_top_count(top, mt, q[i], r);
-#pragma unroll
-        for (int i = 0; i < QB; ++i) {
+        for (int i = 0; i < 4; ++i) {
             past[i] = c[i] >= mt;  // above every key
             if (past[i]) c[i] = 0;  // searched as query 0, answer n
         }
 #pragma unroll
         for (int k = 6; k >= 0; --k) {
             if (k >= (int)T) continue;  // uniform: levels below the top only
-            uint4 x[QB];
+            uint4 x[4][W4];
 #pragma unroll
-            for (int i = 0; i < QB; ++i)
-                x[i] = *(const uint4*)(idx + L.off[k] + kLkFan * (uint64_t)c[i] + 4 * r);
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int i = 0; i < QB; ++i) {
-                const uint32_t cnt = (x[i].x < q[i]) + (x[i].y < q[i]) + (x[i].z < q[i]) +
-                                     (x[i].w < q[i]);
-                c[i] = kLkFan * c[i] + lk_sum8(cnt);
+                for (int v = 0; v < W4; ++v)
+                    x[i][v] = *(const uint4*)(idx + L.off[k] + kLkFan * (uint64_t)c[i] +
+                                              4 * (W4 * r + v));
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                uint32_t cnt = 0;
+#pragma unroll
+                for (int v = 0; v < W4; ++v)
+                    cnt += (x[i][v].x < q[i]) + (x[i][v].y < q[i]) + (x[i][v].z < q[i]) +
+                           (x[i][v].w < q[i]);
+                c[i] = kLkFan * c[i] + lk_sum<G>(cnt);
             }
         }
         // c[i]: the leaf holding the answer, the first whose largest key
         // is >= q[i]
-        uint4 w[QB];
-        uint32_t mx[QB];
+        uint4 w[4][W4];
+        uint32_t mx[4];
 #pragma unroll
-        for (int i = 0; i < QB; ++i) {
-            w[i] = *(const uint4*)(idx + L.leaf_off + kLkLeafWords * (uint64_t)c[i] + 4 * r);
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int v = 0; v < W4; ++v)
+                w[i][v] = *(const uint4*)(idx + L.leaf_off + kLkLeafWords * (uint64_t)c[i] +
+                                          4 * (W4 * r + v));
             mx[i] = idx[L.off[0] + c[i]];
         }
 #pragma unroll
-        for (int i = 0; i < QB; ++i) {
+        for (int i = 0; i < 4; ++i) {
             // slot 0 (the group's first lane) flags a leaf searched in the keys
-            const bool esc = lk_sum8(r == 0 && (w[i].x & 0xffffu) == kLkEscape) != 0;
-            uint32_t cnt;
+            const bool esc = lk_sum<G>(r == 0 && (w[i][0].x & 0xffffu) == kLkEscape) != 0;
+            uint32_t cnt = 0;
             if (!esc) {
                 // key < q exactly when its distance below the leaf's largest
-                // key exceeds mx - q (q <= mx here)
+                // key exceeds mx - q (q <= mx here; distances are < 0xffff)
                 const uint32_t t = mx[i] - q[i];
-                cnt = lk_above2(w[i].x, t) + lk_above2(w[i].y, t) + lk_above2(w[i].z, t) +
-                      lk_above2(w[i].w, t);
-            } else {
-                cnt = 0;
-                const uint64_t k0 = (uint64_t)c[i] * kLkLeaf + 8 * r;
+                const uint16_t t16 = (uint16_t)(t < 0xffffu ? t : 0xffffu);
+                const kl_u16x2 tc = {t16, t16};
 #pragma unroll
-                for (int u = 0; u < 8; ++u) cnt += k0 + u < n && a.keys[k0 + u] < q[i];
+                for (int v = 0; v < W4; ++v)
+                    cnt += lk_above2(w[i][v].x, tc) + lk_above2(w[i][v].y, tc) +
+                           lk_above2(w[i][v].z, tc) + lk_above2(w[i][v].w, tc);
+            } else {
+                const uint64_t k0 = (uint64_t)c[i] * kLkLeaf + (kLkLeaf / G) * r;
+#pragma unroll
+                for (int u = 0; u < (int)(kLkLeaf / G); ++u)
+                    cnt += k0 + u < n && a.keys[k0 + u] < q[i];
             }
-            cnt = lk_sum8(cnt);  // the whole group takes the same branch
+            cnt = lk_sum<G>(cnt);  // the whole group takes the same branch
             const uint32_t res = past[i] ? n : c[i] * kLkLeaf + cnt;
-            if (lane == g8 + b + (uint32_t)(i / 4)) o[i % 4] = res;
+            if (lane == (uint32_t)src) o[i] = res;
         }
     }
     if (valid) __builtin_nontemporal_store(o, (kl_u32x4*)(a.out + t0));
+}
+
+__global__ __launch_bounds__(KL_WG) void kl_lookup(kl_lookup_args a, kl_slice s) {
+    lookup_body<kLkGroup>(a, s);
 }
 
 

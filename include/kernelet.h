@@ -211,7 +211,17 @@ typedef struct {
                               queued on it, up to 64 slices, so that slices
                               shorter than a launch call do not starve the
                               GPU (50; 0: the slice count alone)          */
-    int32_t reserved[2];
+    int32_t auto_profile;  /* 1: a model policy (MARKOV, SURROGATE, OPT, RANDOM)
+                              meeting a pending job of a kernel without a
+                              profile first profiles it by pre-executing
+                              the job's first workgroups alone (timed, at
+                              the kernel's full occupancy and at two
+                              workgroups per CU held by LDS reservation;
+                              they count as the job's progress) and
+                              deriving the model inputs from the timings
+                              and the code object's resources; 0: such a
+                              schedule call fails with KL_ESTATE (1)     */
+    int32_t reserved[1];
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this
@@ -230,6 +240,8 @@ typedef struct {
     double surrogate_us_total;  /* host time of surrogate scoring (SURROGATE) */
     int64_t surrogate_candidates; /* (pair, ratio) candidates scored */
     int64_t surrogate_pairs;    /* pairs ranked by the surrogate */
+    int64_t kernels_profiled;   /* kernel types profiled by pre-execution
+                                   (kl_config.auto_profile) */
 } kl_stats;
 
 /* One measured co-run (KL_POLICY_OPT): kernel a at b1 workgroups per CU

@@ -63,7 +63,8 @@ class Config(C.Structure):
                 ("hbm_budget", C.c_int64), ("surrogate_topk", C.c_int32),
                 ("random_seed", C.c_uint32), ("solo_overlap", C.c_int32),
                 ("pair_same_type", C.c_int32), ("group_max", C.c_int32),
-                ("inflight_us", C.c_int32), ("reserved", C.c_int32 * 2),
+                ("inflight_us", C.c_int32), ("auto_profile", C.c_int32),
+                ("reserved", C.c_int32 * 1),
                 ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 
@@ -74,7 +75,8 @@ class Stats(C.Structure):
                 ("decision_us_total", C.c_double), ("model_us_total", C.c_double),
                 ("cache_hits", C.c_int64), ("resident_bytes", C.c_int64),
                 ("resident_peak", C.c_int64), ("surrogate_us_total", C.c_double),
-                ("surrogate_candidates", C.c_int64), ("surrogate_pairs", C.c_int64)]
+                ("surrogate_candidates", C.c_int64), ("surrogate_pairs", C.c_int64),
+                ("kernels_profiled", C.c_int64)]
 
 
 class PairMeasure(C.Structure):

@@ -664,6 +664,146 @@ def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str
     return prof
 
 
+# ------------------------------------------------------------ joint fit
+# The base latencies fitted to solo occupancy curves alone leave a kernel
+# whose solo rate does not depend on its occupancy (the SGEMM: its matrix
+# pipe is busy at one workgroup per CU) with latencies the curve cannot
+# identify, so the model cannot tell how its co-runners slow it down.  The
+# joint fit adds what the co-run sweep measured: the weighted speedup S of
+# every co-run, so a kernel's two base latencies are the grid point of least
+#   sum over its curve of (log IPC_model - log IPC)^2
+#   + lam * sum over its co-runs of (log S_model - log S)^2 ,
+# its partners' latencies held; a few rounds of this over all kernels.
+# Held-out pairs (folds) are left out of the fit.
+
+def _rel_pred(pa, pb, b1, b2, cfg):
+    """Predicted slowdowns (cIPC / solo IPC) of the two kernels of a co-run."""
+    import paper_1303_5164_amd as K
+    i1, i2, _ = K.predict(pa, pb, b1, b2, cfg)
+    s1 = K.predict(pa, None, pa["max_wg_per_cu"], 0, cfg)[0]
+    s2 = K.predict(pb, None, pb["max_wg_per_cu"], 0, cfg)[0]
+    return i1 / s1, i2 / s2
+
+
+def _kernel_objective(args):
+    """Objective of one (lat_mem, lat_comp) candidate for kernel `name`."""
+    import math
+    import paper_1303_5164_amd as K
+    name, lm, lc, prof, curve, rows, cfgd, lam = args
+    cfg = K.default_config(**cfgd)
+    q = dict(prof[name], lat_mem=float(lm), lat_comp=float(lc))
+    try:
+        e = sum((math.log(K.predict(q, None, b, 0, cfg)[0]) - math.log(v)) ** 2
+                for b, v in curve.items())
+        for r in rows:
+            pa = q if r["a"] == name else prof[r["a"]]
+            pb = q if r["b"] == name else prof[r["b"]]
+            ra, rb = _rel_pred(pa, pb, r["b1"], r["b2"], cfg)
+            e += lam * (math.log(ra + rb) - math.log(r["speedup"])) ** 2
+    except (K.KerneletError, ValueError):
+        return float("inf")
+    return e
+
+
+def joint_refine(prof, curves, rows, cfgd, rounds=2, lam=1.0, pool=None):
+    """Coordinate descent of every kernel's (lat_mem, lat_comp) on the
+    joint objective; returns the refined table (copies)."""
+    import numpy as np
+    prof = {k: dict(v) for k, v in prof.items()}
+    lm_grid = np.logspace(0, 4.3, 14)
+    for _ in range(rounds):
+        for name in sorted(curves):
+            lc_grid = np.logspace(0, 3.3, 7) if prof[name]["r_comp"] > 0 else [1.0]
+            mine = [r for r in rows if name in (r["a"], r["b"])]
+            cand = [(name, lm, lc, prof, curves[name], mine, cfgd, lam)
+                    for lm in lm_grid for lc in lc_grid]
+            errs = (pool.map(_kernel_objective, cand) if pool else
+                    [_kernel_objective(c) for c in cand])
+            i = int(np.argmin(errs))
+            prof[name]["lat_mem"] = float(cand[i][1])
+            prof[name]["lat_comp"] = float(cand[i][2])
+    return prof
+
+
+def corun_errors(prof, rows, cfgd):
+    """Absolute relative error of the predicted speedup S = rel_a + rel_b
+    on each co-run row."""
+    import numpy as np
+    import paper_1303_5164_amd as K
+    cfg = K.default_config(**cfgd)
+    out = []
+    for r in rows:
+        ra, rb = _rel_pred(prof[r["a"]], prof[r["b"]], r["b1"], r["b2"], cfg)
+        out.append(abs(ra + rb - r["speedup"]) / r["speedup"])
+    return np.array(out)
+
+
+def fit_joint(table_path, occupancy_path, corun_path, out_path, folds=4, lam=1.0,
+              slopes=((2.0, 4.0), (4.0, 4.0), (4.0, 16.0), (8.0, 16.0), (2.0, 16.0))):
+    """Refit a profile table (from fit_pools) jointly on its solo occupancy
+    curves and a balanced co-run sweep; the contention slopes are chosen by
+    the cross-validated co-run error (pairs split into `folds` folds, each
+    fold predicted by the table fitted without it), and the table written
+    is refitted on every pair at the chosen slopes."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from paper_1303_5164_amd import profiles
+    t = json.load(open(table_path))
+    occ = json.load(open(occupancy_path)).get("solo_occupancy_ms", {})
+    rows = [r for r in json.load(open(corun_path))["rows"] if r.get("rel_a") and r.get("rel_b")]
+    prof = {k: dict(profiles._COMMON, **v) for k, v in t["profiles"].items()}
+    curves = {}
+    for name, p in prof.items():
+        o = {int(b): v for b, v in occ.get(name, {}).items()}
+        pur = min(p["pur"], 0.999)
+        if o:
+            if p["lds_bytes"] < 16384:
+                o.pop(1, None)
+            bm = max(o)
+            curves[name] = {b: pur * o[bm] / o[b] for b in o}
+        else:
+            curves[name] = {p["max_wg_per_cu"]: pur}
+    pairs = sorted({(r["a"], r["b"]) for r in rows})
+    fold_of = {pr: i % folds for i, pr in enumerate(pairs)}
+    res = []
+    with mp.Pool(min(8, os.cpu_count() or 1)) as pool:
+        for bh, bl in slopes:
+            cfgd = dict(beta=bh, beta_lds=bl)
+            held = np.zeros(len(rows))
+            for f in range(folds):
+                train = [r for r in rows if fold_of[(r["a"], r["b"])] != f]
+                test = [i for i, r in enumerate(rows) if fold_of[(r["a"], r["b"])] == f]
+                pf = joint_refine(prof, curves, train, cfgd, lam=lam, pool=pool)
+                held[test] = corun_errors(pf, [rows[i] for i in test], cfgd)
+            full = joint_refine(prof, curves, rows, cfgd, lam=lam, pool=pool)
+            fit_err = corun_errors(full, rows, cfgd)
+            res.append((float(held.mean()), bh, bl, full, float(fit_err.mean())))
+            print(f"# joint fit beta {bh} beta_lds {bl}: co-run MAPE {fit_err.mean():.3f} "
+                  f"fitted, {held.mean():.3f} on held-out pairs ({folds} folds)",
+                  file=sys.stderr, flush=True)
+    best = min(res, key=lambda x: x[0])
+    held, bh, bl, full, fit_mape = best
+    out_prof = {k: {kk: vv for kk, vv in v.items() if kk in t["profiles"][k] or
+                    kk in ("lat_mem", "lat_comp")} for k, v in full.items()}
+    import paper_1303_5164_amd as K
+    cfg = K.default_config(beta=bh, beta_lds=bl)
+    for k, v in out_prof.items():
+        v["model_solo_ipc"] = K.predict(full[k], None, full[k]["max_wg_per_cu"], 0, cfg)[0]
+    meta = dict(t["meta"])
+    meta["model"] = dict(meta.get("model", {}), beta=bh, beta_lds=bl,
+                         joint_fit={"corun": os.path.basename(corun_path),
+                                    "points": len(rows), "lambda": lam, "folds": folds,
+                                    "mape_fitted": fit_mape, "mape_held_out": held,
+                                    "slopes": [[r[1], r[2], r[0], r[4]] for r in res]})
+    meta["source"] = (meta.get("source", "") + "; base latencies refitted jointly on the "
+                      "co-run sweep (calibrate.py fit-joint)")
+    with open(out_path, "w") as f:
+        json.dump({"meta": meta, "profiles": out_prof}, f, indent=1, sort_keys=True)
+    return out_prof
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -687,7 +827,17 @@ def main():
     f.add_argument("--occupancy", default=None,
                    help="sweep JSON with solo_occupancy_ms: fit the model with contention "
                         "pools to every kernel's IPC-vs-occupancy curve")
+    j = sub.add_parser("fit-joint")
+    j.add_argument("--table", required=True, help="profile table written by fit")
+    j.add_argument("--occupancy", required=True)
+    j.add_argument("--corun", required=True)
+    j.add_argument("--out", default=os.path.join(HERE, "profiles_mi355x.json"))
+    j.add_argument("--folds", type=int, default=4)
+    j.add_argument("--lam", type=float, default=1.0)
     a = ap.parse_args()
+    if a.cmd == "fit-joint":
+        fit_joint(a.table, a.occupancy, a.corun, a.out, folds=a.folds, lam=a.lam)
+        return
     if a.cmd == "run":
         t0 = time.time()
         run(a.out, a.reps)

@@ -417,7 +417,11 @@ Triple best_triple(const kl_profile* const p[3], const double* solo, const kl_co
     return best;
 }
 
+// A pair is pruned when both its PUR and MUR differences are small; a
+// kernel whose MUR is unknown (negative: profiled without memory counters)
+// is never pruned.
 bool pair_pruned(const kl_profile& a, const kl_profile& b, double ap, double am) {
+    if (a.mur < 0 || b.mur < 0) return false;
     return std::fabs(a.pur - b.pur) < ap && std::fabs(a.mur - b.mur) < am;
 }
 

@@ -246,6 +246,7 @@ static kl_config defaults() {
     c.lanes = 2;
     c.inflight = 2;
     c.inflight_us = 50;
+    c.auto_profile = 1;
     c.lds_reserve = 2;
     c.max_slices = 0;
     c.hbm_budget = 0;
@@ -258,7 +259,8 @@ static kl_status check_cfg(const kl_config& c) {
         c.lanes > 4 || c.inflight < 1 || c.inflight > 64 || c.n_cu < 0 || c.mem_latency < 1 ||
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.inflight_us < 0 ||
-        c.inflight_us > 100000 || c.surrogate_topk < 0 || c.max_slices < 0 ||
+        c.inflight_us > 100000 || c.auto_profile < 0 || c.auto_profile > 1 ||
+ c.surrogate_topk < 0 || c.max_slices < 0 ||
         c.solo_overlap < 0 || c.solo_overlap > 1 || c.pair_same_type < 0 ||
         c.pair_same_type > 1 || c.group_max < 2 || c.group_max > 3 ||
         c.hbm_budget < 0) {
@@ -688,7 +690,159 @@ static uint64_t splitmix64(uint64_t seed, uint64_t i) {
     return z ^ (z >> 31);
 }
 
-static void decide(kl_runtime* rt, kl_policy policy) {
+// Code-object resources of kernel kt: resident workgroups per CU alone,
+// VGPRs per lane and static LDS bytes per workgroup.
+static kl_status kernel_resources(const KernelType& kt, int* nb, int* regs, int* lds) {
+    if (kt.mfn) {
+        KL_HIP(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(nb, kt.mfn, (int)kt.block, 0));
+        KL_HIP(hipFuncGetAttribute(regs, HIP_FUNC_ATTRIBUTE_NUM_REGS, kt.mfn));
+        KL_HIP(hipFuncGetAttribute(lds, HIP_FUNC_ATTRIBUTE_SHARED_SIZE_BYTES, kt.mfn));
+        return KL_OK;
+    }
+    hipFuncAttributes attr;
+    KL_HIP(hipFuncGetAttributes(&attr, kt.fn));
+    KL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, kt.fn, (int)kt.block, 0));
+    *regs = attr.numRegs;
+    *lds = (int)attr.sharedSizeBytes;
+    return KL_OK;
+}
+
+// The model's IPC of a kernel alone at w waves per SIMD.
+static double model_ipc(kl_runtime* rt, const kl_profile& p, int w) {
+    KernelModel km = kernel_model(p, rt->cfg);
+    double ipc = 0.0;
+    chain_ipc(&km, &w, 1, rt->cfg.beta, rt->cfg.beta_lds, &ipc);
+    return ipc;
+}
+
+// Launch `count` workgroups of job jid alone on lane 0 at dynamic LDS `dyn`
+// and wait for them; *ms receives their time from the events the dispatch
+// carries.
+static kl_status timed_solo_slice(kl_runtime* rt, kl_job jid, uint32_t count, uint32_t dyn,
+                                  double* ms) {
+    Job& j = rt->jobs.at(jid);
+    KernelType& kt = rt->kernels[j.type];
+    Lane& ln = rt->lanes[0];
+    const bool was_timed = kt.timed;
+    const double t0 = kt.time_ms;
+    const int64_t n0 = kt.time_launches, w0 = kt.time_wgs;
+    kt.timed = true;
+    ln.dyn_lds = dyn;
+    kl_status s = launch_slice(rt, 0, jid, count);
+    if (s == KL_OK && hipStreamSynchronize(ln.s) != hipSuccess) {
+        set_error("kernelet: a profiling slice failed on the device");
+        s = KL_EHIP;
+    }
+    poll_lanes(rt);
+    *ms = kt.time_ms - t0;
+    kt.timed = was_timed;
+    if (!was_timed) {
+        kt.time_ms = t0;
+        kt.time_launches = n0;
+        kt.time_wgs = w0;
+    }
+    return s;
+}
+
+// Profile a kernel type from its job jid (Section 4.4 takes the model's
+// inputs from profiling a few pre-executed thread blocks).  The job's first
+// workgroups run alone on lane 0, timed by the events their dispatch
+// carries: four rounds at the kernel's full occupancy, then, if it can be
+// held there by LDS reservation, four rounds at two workgroups per CU; they
+// are the job's own progress, so nothing runs twice.  Without hardware
+// counters the memory-instruction ratio is the one whose two-state chain
+// (memory latency cfg.mem_latency) reproduces the measured ratio of the
+// two rates, the instructions per wave those that give the measured rate at
+// full occupancy, PUR the model's solo IPC, and MUR unknown (-1: the pair
+// is never pruned).  Occupancy, VGPRs and static LDS come from the code
+// object.
+static kl_status profile_by_preexecution(kl_runtime* rt, kl_job jid) {
+    Job& j = rt->jobs.at(jid);
+    KernelType& kt = rt->kernels[j.type];
+    const int n_cu = rt->cfg.n_cu;
+    int nb = 0, regs = 0, lds = 0;
+    if (kl_status s = kernel_resources(kt, &nb, &regs, &lds)) return s;
+    const int wps = std::max(1, (int)kt.block / 256);  // waves per SIMD per workgroup
+    const int bmax = std::max(1, std::min(nb, rt->cfg.wmax / wps));
+    // alone: wait for every lane to drain first
+    for (auto& ln : rt->lanes) KL_HIP(hipStreamSynchronize(ln.s));
+    poll_lanes(rt);
+    const uint64_t rounds = 4;
+    uint32_t sa = (uint32_t)std::min<uint64_t>(j.total - j.next, rounds * n_cu * bmax);
+    double ta = 0.0;
+    if (kl_status s = timed_solo_slice(rt, jid, sa, 0, &ta)) return s;
+    kl_profile p{};
+    p.waves_per_simd = wps;
+    p.max_wg_per_cu = bmax;
+    p.vgpr = regs;
+    p.lds_bytes = lds;
+    p.lat_mem = 0.0;  // the configuration's memory latency
+    p.mem_req = 1.0;
+    p.r_comp = 0.0;
+    p.lat_comp = 1.0;
+    p.instr_per_wave = 1.0;
+    p.mur = -1.0;
+    p.access = 0;
+    p.comp_pool = 0;
+    p.min_slice_wgs = 0;
+    double rho = 0.0;  // rate at full occupancy over rate at two per CU
+    const uint32_t dyn2 = bmax > 2 ? dyn_lds_for(rt, kt, 2, 0, 0, true) : 0;
+    const uint64_t rem = j.total - j.next;
+    if (dyn2 > 0 && rem >= (uint64_t)2 * n_cu) {
+        const uint32_t sb = (uint32_t)std::min<uint64_t>(rem, rounds * n_cu * 2);
+        double tb = 0.0;
+        if (kl_status s = timed_solo_slice(rt, jid, sb, dyn2, &tb)) return s;
+        if (ta > 0 && tb > 0) rho = ((double)sa / ta) / ((double)sb / tb);
+    }
+    const int wf = bmax * wps, wl = 2 * wps;
+    p.r_mem = 0.01;  // no second point: a nominal ratio
+    if (rho > 0) {
+        const double hi_ratio = (double)wf / wl;
+        const double target = std::min(std::max(rho, 1.0), hi_ratio);
+        double lo = 1e-4, hi = 0.5;
+        for (int it = 0; it < 40; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            p.r_mem = mid;
+            const double ratio = model_ipc(rt, p, wf) / model_ipc(rt, p, wl);
+            if (ratio < target)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        p.r_mem = 0.5 * (lo + hi);
+    }
+    const double ipc = model_ipc(rt, p, wf);
+    // workgroups per issue slot measured at full occupancy (an issue slot is
+    // 4 cycles at 2.4 GHz, 600000 slots per millisecond)
+    const double rate = ta > 0 ? (double)sa / ta / 600000.0 : 0.0;
+    p.instr_per_wave = rate > 0 ? (double)n_cu * ipc / ((double)wps * rate) : 1.0;
+    p.pur = std::min(ipc, 1.0);
+    p.solo_ipc = ipc;
+    if (kl_status s = check_profile(p)) return s;
+    kt.prof = p;
+    kt.has_prof = true;
+    rt->planner->set_type(j.type, p);
+    rt->stats.kernels_profiled++;
+    return KL_OK;
+}
+
+static bool model_policy(kl_policy p) {
+    return p == KL_POLICY_MARKOV || p == KL_POLICY_SURROGATE || p == KL_POLICY_OPT ||
+           p == KL_POLICY_RANDOM;
+}
+
+static kl_status decide(kl_runtime* rt, kl_policy policy) {
+    // kernels without a profile are profiled from their earliest runnable job
+    if (model_policy(policy) && rt->cfg.auto_profile) {
+        for (int t = 0; t < (int)rt->unlaunched_by_type.size(); ++t) {
+            if (rt->kernels[t].has_prof) continue;
+            for (kl_job id : rt->unlaunched_by_type[t]) {
+                if (!runnable(rt->jobs.at(id))) continue;
+                if (kl_status s = profile_by_preexecution(rt, id)) return s;
+                break;
+            }
+        }
+    }
     // FindCoSchedule's candidates are the earliest runnable jobs of each
     // kernel type (two per type when two instances of a kernel may pair):
     // collect those, not every pending job
@@ -706,7 +860,7 @@ static void decide(kl_runtime* rt, kl_policy policy) {
     rt->cs_job[0] = rt->cs_job[1] = rt->cs_job[2] = KL_NO_JOB;
     if (pend.empty()) {
         for (auto& ln : rt->lanes) ln.job = KL_NO_JOB;
-        return;
+        return KL_OK;
     }
     auto t0 = std::chrono::steady_clock::now();
     Decision d;
@@ -819,6 +973,7 @@ static void decide(kl_runtime* rt, kl_policy policy) {
     }
     rt->cs_active = true;
     log_decision(rt, d, sl, us);
+    return KL_OK;
 }
 
 // Whether job j would finish alone within the pairing threshold (such a
@@ -843,7 +998,7 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
             ended = true;
     }
     if (ended) {
-        decide(rt, policy);
+        if (kl_status s = decide(rt, policy)) return s;
         if (!rt->cs_active) return KL_OK;
         *progressed = true;
     }
@@ -1404,7 +1559,7 @@ kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags) {
             return KL_ESTATE;
         }
         if (policy != KL_POLICY_FIFO && policy != KL_POLICY_FIXED &&
-            policy != KL_POLICY_CONCURRENT) {
+            policy != KL_POLICY_CONCURRENT && !rt->cfg.auto_profile) {
             for (kl_job id : rt->live) {
                 const Job& j = rt->jobs.at(id);
                 if ((j.st == J_PENDING || j.st == J_WAIT_DEP) && !rt->kernels[j.type].has_prof) {

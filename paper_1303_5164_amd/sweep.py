@@ -218,7 +218,10 @@ def main():
               "bs": dict(r=F["bs"]["r"], sigma=F["bs"]["sigma"])}
     prof = profiles.load()
     mcfg = profiles.model_config()
-    rt = K.Runtime(0, lds_reserve=a.lds_reserve, **mcfg)
+    # no pairing threshold: a job the table predicts to be short would run
+    # beside the next one (without holding the other lane), so a window of
+    # solo launches would overlap
+    rt = K.Runtime(0, lds_reserve=a.lds_reserve, **dict(mcfg, min_pair_slots=0.0))
     pcfg = K.default_config(**mcfg)
     n_cu = rt.cfg.n_cu
     kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}

@@ -2,6 +2,7 @@
 #include "hip/hip_runtime.h"
 #include "hip/hip_ext.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>

@@ -103,3 +103,4 @@ def test_groups_of_three_same_bits_as_fifo():
         if d["j3"] >= 0:
             assert len({d["j1"], d["j2"], d["j3"]}) == 3
             assert d["b1"] + d["b2"] + d["b3"] <= 8
+

@@ -551,11 +551,11 @@ def test_groups_of_three_run_side_by_side_on_three_lanes(L):
     h.close()
 
 
-def test_model_policies_refuse_a_kernel_without_profile(L):
-    """Profiles are measured offline: under a model policy a pending job of a
-    kernel registered without one is refused (KL_ESTATE) before anything is
+def test_model_policies_refuse_a_kernel_without_profile_when_not_profiling(L):
+    """With auto_profile off, a pending job of a kernel registered without a
+    profile is refused under a model policy (KL_ESTATE) before anything is
     launched, while FIFO runs it."""
-    h = Harness(L)
+    h = Harness(L, auto_profile=0)
     d = _lib.KernelDesc(b"noprof", C.addressof(L._keys[0]), 256, C.sizeof(VisitArgs), 0, None)
     h.kids.append(h.rt.register(d))
     j = h.job(16, 1, kind=2)
@@ -568,3 +568,29 @@ def test_model_policies_refuse_a_kernel_without_profile(L):
     h.rt.wait(j[0], 5_000_000_000)
     assert np.all(j[1] == 1)
     h.close()
+
+
+@pytest.mark.parametrize("pol", ["markov", "random"])
+def test_model_policies_profile_a_kernel_without_profile(L, pol):
+    """By default a model policy profiles a kernel registered without a
+    profile from its first job's own workgroups (four rounds at full
+    occupancy, four at two per CU), then schedules it: every workgroup runs
+    exactly once, the kernel has a valid profile afterwards, and a profiled
+    kernel's job beside it also completes."""
+    h = Harness(L)
+    d = _lib.KernelDesc(b"noprof", C.addressof(L._keys[0]), 256, C.sizeof(VisitArgs), 0, None)
+    h.kids.append(h.rt.register(d))
+    with pytest.raises(K.KerneletError):
+        h.rt.get_profile(h.kids[2])
+    jobs = [h.job(200, 1, kind=2, us=20), h.job(64, 2, kind=0, us=20),
+            h.job(100, 3, kind=2, us=20)]
+    _run_with_deadline(lambda: h.rt.schedule(pol, blocking=True, wait_done=True))
+    for j in jobs:
+        h.rt.wait(j[0], 5_000_000_000)
+        assert np.all(j[1] == 1)
+    p = h.rt.get_profile(h.kids[2])
+    assert p["instr_per_wave"] > 0 and 0 < p["r_mem"] <= 0.5 and p["mur"] < 0
+    assert p["max_wg_per_cu"] >= 1 and p["waves_per_simd"] == 1
+    assert h.rt.stats()["kernels_profiled"] == 1
+    h.close()
+

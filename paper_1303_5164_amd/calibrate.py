@@ -804,6 +804,62 @@ def fit_joint(table_path, occupancy_path, corun_path, out_path, folds=4, lam=1.0
     return out_prof
 
 
+def pruned_pair(pa, pb, alpha_p, alpha_m):
+    """Section 4.3's rule as this library applies it: a pair is pruned when
+    both its PUR and its MUR differ by less than the thresholds (strict)."""
+    return abs(pa[0] - pb[0]) < alpha_p and abs(pa[1] - pb[1]) < alpha_m
+
+
+def prune_table(prof: dict, corun_rows: list, alphas_p=None, alphas_m=None):
+    """The pruning table of the evaluation (tb:pruningTableC2050) on this
+    GPU's profiles, with the measured co-runs beside it.
+
+    prof: kernel -> profile with "pur" and "mur"; corun_rows: the balanced
+    sweep's rows (a, b, speedup).  For every (alpha_p, alpha_m) of the grid:
+    the pairs pruned, and how many of them gain when co-run (best measured
+    speedup over the ratios above 1).  The chosen thresholds prune the most
+    pairs that lose among the grid cells that prune no pair that gains
+    (ties: the smaller alpha_p, then the smaller alpha_m)."""
+    alphas_p = alphas_p or [round(0.1 * i, 2) for i in range(1, 11)]
+    alphas_m = alphas_m or [round(0.05 * i, 2) for i in range(1, 11)]
+    best = {}
+    for r in corun_rows:
+        key = tuple(sorted((r["a"], r["b"])))
+        best[key] = max(best.get(key, 0.0), float(r["speedup"]))
+    pairs = sorted(k for k in best if all(x in prof for x in k))
+    cells = []
+    for am in alphas_m:
+        for ap in alphas_p:
+            pr = [k for k in pairs
+                  if pruned_pair((prof[k[0]]["pur"], prof[k[0]]["mur"]),
+                                 (prof[k[1]]["pur"], prof[k[1]]["mur"]), ap, am)]
+            gain = [k for k in pr if best[k] > 1.0]
+            cells.append(dict(alpha_p=ap, alpha_m=am, pruned=len(pr), pruned_gaining=len(gain),
+                              pairs=[list(k) for k in pr]))
+    ok = [c for c in cells if c["pruned_gaining"] == 0]
+    choice = max(ok, key=lambda c: (c["pruned"], -c["alpha_p"], -c["alpha_m"]))
+    return dict(pairs=len(pairs), gaining=sum(best[k] > 1.0 for k in pairs),
+                best_speedup={f"{a}+{b}": best[(a, b)] for a, b in pairs},
+                alphas_p=alphas_p, alphas_m=alphas_m, cells=cells, choice=choice)
+
+
+def prune_report(res: dict) -> str:
+    ap_, am_ = res["alphas_p"], res["alphas_m"]
+    by = {(c["alpha_p"], c["alpha_m"]): c for c in res["cells"]}
+    lines = ["| alpha_m \\ alpha_p | " + " | ".join(f"{a:g}" for a in ap_) + " |",
+             "|---|" + "---:|" * len(ap_)]
+    for am in am_:
+        lines.append(f"| {am:g} | " + " | ".join(
+            f"{by[ap, am]['pruned']} ({by[ap, am]['pruned_gaining']})" for ap in ap_) + " |")
+    c = res["choice"]
+    lines.append("")
+    lines.append(f"{res['pairs']} pairs, {res['gaining']} of them gaining (best measured speedup "
+                 f"above 1).  Cells: pairs pruned (of which gaining).  Chosen: alpha_p "
+                 f"{c['alpha_p']:g}, alpha_m {c['alpha_m']:g}, pruning {c['pruned']}: "
+                 + ", ".join("+".join(p) for p in c["pairs"]) + ".")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -834,7 +890,33 @@ def main():
     j.add_argument("--out", default=os.path.join(HERE, "profiles_mi355x.json"))
     j.add_argument("--folds", type=int, default=4)
     j.add_argument("--lam", type=float, default=1.0)
+    pt = sub.add_parser("prune-table")
+    pt.add_argument("--table", default=os.path.join(HERE, "profiles_mi355x.json"))
+    pt.add_argument("--corun", default=os.path.join(HERE, "coruns_mi355x.json"))
+    pt.add_argument("--out", default=None, help="JSON of every cell")
+    pt.add_argument("--write", action="store_true",
+                    help="store the chosen thresholds in the table's model metadata")
     a = ap.parse_args()
+    if a.cmd == "prune-table":
+        with open(a.table) as f:
+            prof = json.load(f)["profiles"]
+        with open(a.corun) as f:
+            rows = json.load(f)["rows"]
+        res = prune_table(prof, rows)
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+        print(prune_report(res))
+        if a.write:
+            with open(a.table) as f:
+                tab = json.load(f)
+            m = tab.setdefault("meta", {}).setdefault("model", {})
+            m["alpha_p"] = res["choice"]["alpha_p"]
+            m["alpha_m"] = res["choice"]["alpha_m"]
+            m["prune_table"] = {k: res[k] for k in ("pairs", "gaining", "choice")}
+            with open(a.table, "w") as f:
+                json.dump(tab, f, indent=1, sort_keys=True)
+        return
     if a.cmd == "fit-joint":
         fit_joint(a.table, a.occupancy, a.corun, a.out, folds=a.folds, lam=a.lam)
         return

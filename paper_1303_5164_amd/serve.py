@@ -9,11 +9,14 @@ the inputs of the five size classes are built once and shared read-only).
 The factor scales the leading dimension: SGEMM rows, SpMV rows, stencil
 rows, and the element counts of the other kernels.
 
-Each client thread sleeps until its request's arrival time, allocates the
-instance's outputs and submits its launches to one runtime whose scheduler
-runs in the background (continuous batching: every arrival joins the
-pending set and is considered at the next decision).  Admission is bounded
-by the runtime's memory budget.  A reaper waits for each instance in
+Each client thread sleeps until its request's arrival time, waits until the
+memory budget has room for the instance's footprint (admission in arrival
+order), allocates the instance's outputs and submits its launches to one
+runtime whose scheduler runs in the background (continuous batching: every
+arrival joins the pending set and is considered at the next decision).  The
+budget is held from allocation until the reaper has the instance's result,
+so it bounds the device memory the requests allocate; the runtime checks
+the same budget again when it admits launches.  A reaper waits for each instance in
 arrival order, records its turnaround (completion - submission) and frees
 it; a sample of the instances is compared bit for bit with the output of
 the same instance run alone.
@@ -133,6 +136,44 @@ def params_of(kind):
     return {}
 
 
+class Budget:
+    """Bytes of device memory held by admitted requests.  `acquire` blocks
+    until every earlier ticket has been admitted and the budget has room,
+    so requests are admitted in arrival order and a request larger than the
+    whole budget is refused rather than waited for."""
+
+    def __init__(self, limit):
+        self.limit = int(limit)
+        self.held = 0
+        self.peak = 0
+        self.next_ticket = 0
+        self.aborted = False
+        self.cv = threading.Condition()
+
+    def acquire(self, ticket, nbytes):
+        if nbytes > self.limit:
+            raise ValueError(f"request of {nbytes} bytes exceeds the budget of {self.limit}")
+        with self.cv:
+            self.cv.wait_for(lambda: self.aborted or (ticket == self.next_ticket and
+                                                      self.held + nbytes <= self.limit))
+            if self.aborted:
+                raise RuntimeError("serving aborted")
+            self.held += nbytes
+            self.peak = max(self.peak, self.held)
+            self.next_ticket += 1
+            self.cv.notify_all()
+
+    def release(self, nbytes):
+        with self.cv:
+            self.held -= nbytes
+            self.cv.notify_all()
+
+    def abort(self):
+        with self.cv:
+            self.aborted = True
+            self.cv.notify_all()
+
+
 class Server:
     """The inputs of every (kind, size class), the solo reference output of
     each, and one runtime per serving run."""
@@ -147,7 +188,7 @@ class Server:
         self.kinds = kinds or W.TYPES
         self.base_scale = base_scale
         self.prof = profiles.load()
-        self.inputs, self.ref, self.solo_ms = {}, {}, {}
+        self.inputs, self.ref, self.solo_ms, self.footprint = {}, {}, {}, {}
         self.client_streams = []
         self.log = log or (lambda s: None)
         for kind in self.kinds:
@@ -201,6 +242,7 @@ class Server:
                     ts.append(time.perf_counter() - t0)
                     rt.reap()
                 self.ref[kind, c] = inst.tensors[inst.result].clone()
+                self.footprint[kind, c] = inst.footprint
                 self.solo_ms[kind, c] = 1e3 * statistics.median(ts[1:] if reps > 1 else ts)
         finally:
             rt.close()
@@ -215,7 +257,10 @@ class Server:
         """Serve the requests `reqs` (from `arrivals`) with one runtime under
         `policy`; returns the per-request records and a summary."""
         torch = self.torch
+        if not self.footprint:
+            raise RuntimeError("Server.references() must run before serve()")
         rt, kids = self.runtime(hbm_budget=int(budget), **cfg)
+        held = Budget(budget)
         n = len(reqs)
         by_client = {}
         for r in reqs:
@@ -234,6 +279,7 @@ class Server:
                     delay = t_base[0] + r["t"] - time.perf_counter()
                     if delay > 0:
                         time.sleep(delay)
+                    held.acquire(r["i"], self.footprint[r["kind"], r["size"]])
                     inst = self.new_instance(r["kind"], r["size"], s)
                     lag = time.perf_counter() - (t_base[0] + r["t"])
                     jobs = self.W.submit(rt, kids, inst, client=r["client"])
@@ -241,6 +287,7 @@ class Server:
                     ready[r["i"]].set()
             except BaseException as e:  # noqa: BLE001
                 errors.append(e)
+                held.abort()
                 for ev in ready:
                     ev.set()
 
@@ -286,10 +333,13 @@ class Server:
                         bad.append({"i": i, "kind": r["kind"], "size": r["size"]})
                 recs.append(rec)
                 slots[i] = None
+                del inst, jobs
+                held.release(self.footprint[r["kind"], r["size"]])
             for th in threads:
                 th.join()
             st = rt.stats()
         finally:
+            held.abort()
             gc.enable()
             rt.close()
         t0 = min(r["submit_ns"] for r in recs)
@@ -308,6 +358,7 @@ class Server:
                      kind=recs[i]["kind"], size=recs[i]["size"], client=recs[i]["client"])
                 for i in sorted(range(n), key=lambda i: -recs[i]["lag_ms"])[:8]],
             "resident_peak_bytes": st["resident_peak"],
+            "allocated_peak_bytes": held.peak,
             "decisions": st["decisions"], "slices": st["slices_launched"],
             "verified": n_verified, "mismatches": len(bad), "mismatched": bad[:20],
         }

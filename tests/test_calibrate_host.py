@@ -24,3 +24,39 @@ def test_min_slice_is_the_smallest_within_p():
     assert C.min_slice(1.0, [], 0.02) == 0
     # order of the rows does not matter
     assert C.min_slice(1.0, list(reversed(rows)), 0.02) == 768
+
+
+def test_prune_table_counts_match_the_oracle_and_choice_keeps_gaining_pairs():
+    """The recalibrated pruning table (the evaluation's tb:pruningTableC2050
+    method on this GPU's PUR/MUR): every cell's count equals the oracle's
+    AND-rule count over the same pairs, and the chosen thresholds prune no
+    pair whose best measured co-run gains."""
+    import json
+    import os
+
+    from oracle import prune as P
+    from paper_1303_5164_amd import calibrate as CAL
+    here = os.path.dirname(CAL.__file__)
+    with open(os.path.join(here, "profiles_mi355x.json")) as f:
+        prof = json.load(f)["profiles"]
+    with open(os.path.join(here, "coruns_mi355x.json")) as f:
+        rows = json.load(f)["rows"]
+    res = CAL.prune_table(prof, rows)
+    pairs = sorted({tuple(sorted((r["a"], r["b"]))) for r in rows})
+    assert res["pairs"] == len(pairs) >= 20
+    for c in res["cells"]:
+        want = sum(P.pruned((prof[a]["pur"], prof[a]["mur"]), (prof[b]["pur"], prof[b]["mur"]),
+                           c["alpha_p"], c["alpha_m"]) for a, b in pairs)
+        assert c["pruned"] == want, c
+    ch = res["choice"]
+    assert ch["pruned_gaining"] == 0 and ch["pruned"] >= 1
+    gains = res["best_speedup"]
+    assert all(gains["+".join(p)] <= 1.0 for p in ch["pairs"])
+    # a hand case: two kernels close in both ratios are pruned, a third far
+    # from both in PUR is kept with each
+    toy = {"x": {"pur": 0.5, "mur": 0.5}, "y": {"pur": 0.55, "mur": 0.52},
+           "z": {"pur": 0.95, "mur": 0.5}}
+    toy_rows = [dict(a="x", b="y", speedup=0.9), dict(a="x", b="z", speedup=1.2),
+                dict(a="y", b="z", speedup=1.1)]
+    t = CAL.prune_table(toy, toy_rows, alphas_p=[0.1], alphas_m=[0.05])
+    assert t["choice"]["pairs"] == [["x", "y"]]

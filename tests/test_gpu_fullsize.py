@@ -9,7 +9,7 @@ streams.  Outputs are checked
 against the oracle in full where that is cheap (polynomial, gather, SpMV,
 histogram) and on seeded samples the oracle computes point by point
 elsewhere (SGEMM entries, stencil points after 10 sweeps, Black-Scholes
-options, lookup queries)."""
+options, lookup queries), and once in full for those four after a Markov run."""
 import json
 
 import numpy as np
@@ -146,3 +146,41 @@ def test_full_mix_matches_oracle(mix, policy):
                 idx[:2] = [0, h["q"].size - 1]
                 ref = oracle.lower_bound(h["keys"], h["q"][idx])
                 assert np.array_equal(_out(inst)[idx], ref)
+
+
+def test_full_outputs_in_full(mix):
+    """Every output element of the four kernels checked on samples above
+    (SGEMM 4096^3, the stencil's 8192^2 grid after 10 sweeps, 2^25
+    Black-Scholes options, 2^26 lookups), compared in full with the oracle
+    after a Markov-policy run; the second instance of each must equal the
+    first bit for bit."""
+    hosts, insts = mix
+    _run(insts, "markov")
+    by = {}
+    for inst in insts:
+        by.setdefault(inst.kind, []).append(inst)
+    for kind in ("sgemm", "stencil", "bs", "lookup"):
+        h = hosts[kind]
+        first, second = by[kind]
+        print(f"full check {kind}", flush=True)
+        for name in ([first.result] if kind != "bs" else ["call", "put"]):
+            assert np.array_equal(_out(first, name), _out(second, name)), (kind, name)
+        if kind == "sgemm":
+            ref = oracle.sgemm(h["a"], h["b"])
+            got = _out(first).astype(np.float64)
+            assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
+            assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+        elif kind == "stencil":
+            ref = oracle.stencil(h["u"], F["stencil"]["iters"], F["stencil"]["c0"],
+                                 F["stencil"]["c1"])
+            assert np.abs(_out(first) - ref).max() <= 1e-5 * np.abs(h["u"]).max()
+        elif kind == "bs":
+            c_ref, p_ref = oracle.black_scholes(h["s"], h["k"], h["t"], F["bs"]["r"],
+                                                F["bs"]["sigma"])
+            s = h["s"].astype(np.float64)
+            assert_close_scaled(_out(first, "call"), c_ref, np.maximum(np.abs(c_ref), s), 1e-5,
+                                "call")
+            assert_close_scaled(_out(first, "put"), p_ref, np.maximum(np.abs(p_ref), s), 1e-5,
+                                "put")
+        else:
+            assert np.array_equal(_out(first), oracle.lower_bound(h["keys"], h["q"]))

@@ -62,3 +62,44 @@ def test_scaled_shapes_keep_kernel_multiples():
     assert S.scaled_shape("sgemm", -2)["m"] == 1024 and S.scaled_shape("sgemm", -2)["k"] == 4096
     assert S.scaled_shape("stencil", -1) == {"ny": 4096, "nx": 8192}
     assert S.scaled_shape("lookup", -4)["nkeys"] == 1 << 26
+
+
+def test_budget_admits_in_arrival_order_within_the_limit():
+    import threading
+    import time
+    b = S.Budget(100)
+    order = []
+
+    def take(ticket, nbytes):
+        b.acquire(ticket, nbytes)
+        order.append(ticket)
+
+    b.acquire(0, 60)
+    # ticket 2 fits now but must wait for ticket 1, which does not fit yet
+    t2 = threading.Thread(target=take, args=(2, 10))
+    t1 = threading.Thread(target=take, args=(1, 50))
+    t2.start()
+    t1.start()
+    time.sleep(0.2)
+    assert order == [] and b.held == 60
+    b.release(60)
+    t1.join(5)
+    t2.join(5)
+    assert order == [1, 2] and b.held == 60 and b.peak == 60
+    with pytest.raises(ValueError):
+        b.acquire(3, 101)
+    # an aborted budget wakes a waiting client with an error
+    errs = []
+
+    def blocked():
+        try:
+            b.acquire(3, 90)
+        except RuntimeError as e:
+            errs.append(e)
+
+    t3 = threading.Thread(target=blocked)
+    t3.start()
+    time.sleep(0.1)
+    b.abort()
+    t3.join(5)
+    assert len(errs) == 1

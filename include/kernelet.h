@@ -242,6 +242,8 @@ typedef struct {
     int64_t surrogate_pairs;    /* pairs ranked by the surrogate */
     int64_t kernels_profiled;   /* kernel types profiled by pre-execution
                                    (kl_config.auto_profile) */
+    int64_t model_solves;       /* pair (and triple) ratio searches solved by
+                                   the Markov model, cache misses only */
 } kl_stats;
 
 /* One measured co-run (KL_POLICY_OPT): kernel a at b1 workgroups per CU

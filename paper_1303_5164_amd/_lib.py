@@ -76,7 +76,7 @@ class Stats(C.Structure):
                 ("cache_hits", C.c_int64), ("resident_bytes", C.c_int64),
                 ("resident_peak", C.c_int64), ("surrogate_us_total", C.c_double),
                 ("surrogate_candidates", C.c_int64), ("surrogate_pairs", C.c_int64),
-                ("kernels_profiled", C.c_int64)]
+                ("kernels_profiled", C.c_int64), ("model_solves", C.c_int64)]
 
 
 class PairMeasure(C.Structure):

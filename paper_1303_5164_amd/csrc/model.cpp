@@ -472,6 +472,7 @@ Ratio Planner::pair(int t1, int t2) {
         return it->second;
     }
     double s1 = solo(t1), s2 = solo(t2);
+    ++model_solves;
     auto t0 = std::chrono::steady_clock::now();
     Ratio r = best_ratio_with(types_[t1], types_[t2], cfg_, s1, s2, t1 == t2);
     model_us += std::chrono::duration<double, std::micro>(
@@ -493,6 +494,7 @@ Triple Planner::triple(int t1, int t2, int t3) {
     } else {
         const kl_profile* p[3] = {&types_[key[0]], &types_[key[1]], &types_[key[2]]};
         double s[3] = {solo(key[0]), solo(key[1]), solo(key[2])};
+        ++model_solves;
         auto t0 = std::chrono::steady_clock::now();
         r = best_triple(p, s, cfg_);
         model_us += std::chrono::duration<double, std::micro>(

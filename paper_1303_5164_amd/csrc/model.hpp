@@ -169,6 +169,7 @@ class Planner {
     int ntypes() const { return (int)types_.size(); }
     double model_us = 0;
     int64_t cache_hits = 0;
+    int64_t model_solves = 0;   // pair and triple ratio searches run (cache misses)
 
   private:
     // The earliest pending job of each type (submission order) that is not

@@ -1803,6 +1803,7 @@ kl_status kernelet_stats(kl_runtime* rt, kl_stats* out) {
     std::lock_guard<std::mutex> g(rt->mu);
     *out = rt->stats;
     out->surrogate_pairs = rt->planner->scored_pairs;
+    out->model_solves = rt->planner->model_solves;
     out->resident_bytes = rt->resident;
     out->resident_peak = rt->resident_peak;
     return KL_OK;

@@ -67,12 +67,24 @@ def pair_features(pa: dict, pb: dict, b1: int, b2: int, cfg=None) -> np.ndarray:
 
 
 # ------------------------------------------------ synthetic kernel population
-# Each synthetic kernel is one instantiation of the template kernels
-# synthk_v<V>_l<L> with runtime parameters: ALU instructions per load
-# (log-uniform in [1, 64]), access pattern (coalesced, strided, random),
-# VGPR class and LDS class (uniform over four each).
+# Each synthetic kernel has a memory-instruction ratio r (uniform in
+# [0, 0.6]), an access pattern (coalesced, strided, random), a VGPR class
+# and an LDS class (uniform over four each).  Its model profile takes r
+# itself.  The template kernels synthk_v<V>_l<L> realise r with one load and
+# `alu` dependent FMAs per iteration plus LOOP_OVERHEAD loop instructions,
+# r = 1 / (alu + LOOP_OVERHEAD + 1), so `alu` = 1 / r - 6 clamped to
+# [1, 64]: ratios in [1/70, 1/7] run on the GPU as drawn, the rest run as
+# the nearest template and enter training through their profiles only.
 LOOP_OVERHEAD = 5      # address, loop counter, compare, branch, wait per iteration
 LINES_PER_LOAD = (4, 64, 64)   # 64-byte lines one wave's load touches
+R_MEM_MAX = 0.6
+
+
+def template_alu(r_mem: float) -> int:
+    """ALU instructions per load of the template closest to ratio r_mem."""
+    if r_mem <= 0:
+        return 64
+    return max(1, min(64, int(round(1.0 / r_mem)) - LOOP_OVERHEAD - 1))
 
 
 def sample_kernels(seed: int, n: int) -> list:
@@ -81,22 +93,27 @@ def sample_kernels(seed: int, n: int) -> list:
     u = (r >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     out = []
     for i in range(n):
-        alu = int(round(2.0 ** (6.0 * u[i, 0])))
-        out.append({"alu": max(1, min(64, alu)), "pattern": int(u[i, 1] * 3),
+        rm = R_MEM_MAX * float(u[i, 0])
+        out.append({"r_mem": rm, "alu": template_alu(rm), "pattern": int(u[i, 1] * 3),
                     "vgpr": _lib.SYNTHK_VGPR[int(u[i, 2] * 4)],
                     "lds_kb": _lib.SYNTHK_LDS_KB[int(u[i, 3] * 4)]})
     return out
 
 
-def analytic_profile(k: dict, iters: int = 64, cfg=None) -> dict:
-    """First-order model profile of a synthetic kernel from its parameters
-    (what counters would report for it): one memory instruction per
-    iteration of alu + LOOP_OVERHEAD + 1 instructions."""
+def analytic_profile(k: dict, iters: int = 64, cfg=None, realized: bool = False) -> dict:
+    """First-order model profile of a synthetic kernel (what counters would
+    report for it): memory-instruction ratio k["r_mem"] when given (the
+    population's draw), else, or with `realized`, the template's own
+    1 / (alu + LOOP_OVERHEAD + 1); `iters` memory instructions per wave."""
     from .runtime import default_config, predict
-    per_it = k["alu"] + LOOP_OVERHEAD + 1
+    if realized or "r_mem" not in k:
+        r_mem = 1.0 / (k["alu"] + LOOP_OVERHEAD + 1)
+    else:
+        r_mem = float(k["r_mem"])
+    per_it = 1.0 / max(r_mem, 1.0 / 1024)
     lds = k["lds_kb"] * 1024
     occ = min(8, 512 // k["vgpr"], (160 * 1024) // lds if lds else 8)
-    p = dict(r_mem=1.0 / per_it, mem_req=float(LINES_PER_LOAD[k["pattern"]]), lat_mem=0.0,
+    p = dict(r_mem=r_mem, mem_req=float(LINES_PER_LOAD[k["pattern"]]), lat_mem=0.0,
              r_comp=0.0, lat_comp=0.0, instr_per_wave=float(iters * per_it),
              max_wg_per_cu=occ, waves_per_simd=1, vgpr=k["vgpr"], lds_bytes=lds,
              access=k["pattern"])

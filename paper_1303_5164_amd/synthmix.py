@@ -54,7 +54,7 @@ def _setup(seed, n_types, lds_reserve=2, topk=4):
     for i, k in enumerate(pop):
         d = K.builtin_desc(f"synthk_v{k['vgpr']}_l{k['lds_kb']}")
         d.name = f"syn{i}".encode()
-        p = S.analytic_profile(k, iters=ITERS)
+        p = S.analytic_profile(k, iters=ITERS, realized=True)
         kids.append(rt.register(d, p))
         profs.append(p)
     return rt, kids, profs, pop, src, _lib, torch
@@ -93,7 +93,8 @@ def decide(args):
         results[pol] = outs
         nd = s1["decisions"] - s0["decisions"]
         run = {"policy": pol, "wall_ms": wall * 1e3, "kernels_per_s": args.jobs / wall,
-               "decisions": nd}
+               "decisions": nd, "model_solves": s1["model_solves"] - s0["model_solves"],
+               "decision_ms_total": (s1["decision_us_total"] - s0["decision_us_total"]) / 1e3}
         if nd:
             run.update(
                 us_per_decision=(s1["decision_us_total"] - s0["decision_us_total"]) / nd,

@@ -1,7 +1,8 @@
 """GPU tests of the surrogate path: the synthetic template kernels give the
 same bits sliced, co-run and alone; a network trained on the device reaches
 under 10% error on kernels it has not seen; the SURROGATE policy needs its
-weights and runs a mix to the same bits as FIFO."""
+weights and runs a mix to the same bits as FIFO; with 64 synthetic types it
+needs far fewer Markov solves than the Markov policy alone."""
 import numpy as np
 import pytest
 import torch
@@ -100,3 +101,25 @@ def test_surrogate_policy_same_bits_as_fifo():
            if not np.array_equal(a, b)]
     assert not bad, f"outputs differ from FIFO: {bad}"
     assert st["surrogate_pairs"] > 0 and st["surrogate_candidates"] > 0
+
+
+def test_surrogate_gain_over_markov_on_64_synthetic_types():
+    """What the trained network gains over the Markov model alone: the same
+    256 jobs of 64 synthetic kernel types scheduled under MARKOV and under
+    SURROGATE (network ranking every surviving pair, the Markov model
+    judging the top 4).  The surrogate run needs far fewer Markov ratio
+    searches, and every output equals FIFO's."""
+    import argparse
+
+    from paper_1303_5164_amd import synthmix
+    res = synthmix.decide(argparse.Namespace(seed=7, types=64, jobs=256, topk=4))
+    runs = {r["policy"]: r for r in res["runs"]}
+    for pol in ("markov", "surrogate"):
+        r = runs[pol]
+        print(f"{pol}: decisions {r['decisions']} model solves {r['model_solves']} "
+              f"decision ms {r['decision_ms_total']:.2f} wall ms {r['wall_ms']:.2f}", flush=True)
+    assert res["mismatches_vs_fifo"] == 0
+    m, s = runs["markov"], runs["surrogate"]
+    assert m["decisions"] > 0 and s["decisions"] > 0
+    assert s["pairs_scored"] > 0
+    assert s["model_solves"] * 2 < m["model_solves"], (s["model_solves"], m["model_solves"])

@@ -51,10 +51,22 @@ def test_population_is_seeded_and_spread():
         got = [k[key] for k in a]
         for v in vals:
             assert abs(got.count(v) / len(a) - 1 / len(vals)) < 0.05
+    # memory-instruction ratio uniform in [0, 0.6]
+    r = np.array([k["r_mem"] for k in a])
+    assert r.min() >= 0 and r.max() < 0.6
+    for q in (0.15, 0.3, 0.45):
+        assert abs(np.mean(r < q) - q / 0.6) < 0.05
+    # the template closest to each ratio: 1 / (alu + 6) within the clamp
     alu = np.array([k["alu"] for k in a])
     assert alu.min() == 1 and alu.max() == 64
-    # log-uniform: about half below 8
-    assert abs(np.mean(alu < 8) - 0.5) < 0.05
+    for k in a[:200]:
+        best = min(range(1, 65), key=lambda x: abs(1 / (x + 6) - k["r_mem"]) if k["r_mem"] > 0
+                   else -x)
+        assert abs(1 / (k["alu"] + 6) - k["r_mem"]) <= abs(1 / (best + 6) - k["r_mem"]) + 2e-3
+    # profiles take the drawn ratio; realized ones the template's
+    p = S.analytic_profile(a[0])
+    assert p["r_mem"] == a[0]["r_mem"]
+    assert S.analytic_profile(a[0], realized=True)["r_mem"] == 1 / (a[0]["alu"] + 6)
 
 
 def test_profile_occupancy_limits():

@@ -277,8 +277,11 @@ typedef struct {
 /* Fill *cfg with the defaults listed beside kl_config's fields. */
 kl_status kernelet_default_config(kl_config* cfg);
 
-/* Create a runtime on HIP device `hip_device`.  `cfg` (host, may be NULL for
- * defaults) is copied.  The runtime owns its streams, events and threads. */
+/* Create a runtime on HIP device `hip_device`: the paper's runtime system
+ * (Section 3.2: the queue of submitted kernels, the scheduler and the
+ * co-execution of slices on one GPU).  `cfg` (host, may be NULL for
+ * defaults) is copied.  The runtime owns its streams, events and threads.
+ * Errors: KL_EINVAL (a field of cfg out of range, no such device), KL_EHIP. */
 kl_status kernelet_init(kl_runtime** rt, int hip_device, const kl_config* cfg);
 
 /* Copy the runtime's effective configuration (with n_cu filled in from the
@@ -355,7 +358,10 @@ kl_status kernelet_get_profile(kl_runtime* rt, kl_kernel k, kl_profile* p);
 /* ------------------------------------------------------------------ jobs */
 
 /* Submit one launch of kernel `k` over the ORIGINAL grid `grid` with
- * argument block `args` (host, args_bytes bytes, copied before return).
+ * argument block `args` (host, args_bytes bytes, copied before return): a
+ * kernel of Section 2.2's problem definition (a grid of independent thread
+ * blocks), entering the pending set that Algorithm 1 re-optimises whenever
+ * kernels arrive (Section 3.2).
  * Device pointers inside `args` are borrowed: the caller keeps the memory
  * alive until kernelet_wait on this job returns KL_OK.  `after` (or
  * KL_NO_JOB) names a job that must finish before this one starts.
@@ -387,9 +393,12 @@ kl_status kernelet_submit_chain(kl_runtime* rt, uint32_t n, const kl_kernel* k,
                                 const uint32_t* args_bytes, kl_job after,
                                 uint32_t client, uint64_t footprint, kl_job* out);
 
-/* Fix the slicing plan of a job before it starts: slices of `wgs_per_slice`
- * workgroups (0: the calibrated minimum of its kernel, else its whole
- * grid); *n_slices receives the slice count.  Used by the FIXED policy and
+/* Fix the slicing plan of a job before it starts (Section 4.1: a slice is
+ * a run of consecutive workgroups launched as its own kernel, the offset
+ * added back to the block index on the device; Section 2.2: a slicing plan
+ * cuts a kernel into slices): slices of `wgs_per_slice` workgroups (0: the
+ * calibrated minimum of its kernel, else its whole grid); *n_slices
+ * receives the slice count.  Used by the FIXED policy and
  * by tests.  KL_ESTATE if the job has started. */
 kl_status kernelet_slice(kl_runtime* rt, kl_job j, uint32_t wgs_per_slice,
                          uint32_t* n_slices);
@@ -399,22 +408,30 @@ kl_status kernelet_slice(kl_runtime* rt, kl_job j, uint32_t wgs_per_slice,
  * enabled, is computed for it.  KL_ESTATE if the job has started. */
 kl_status kernelet_job_occupancy(kl_runtime* rt, kl_job j, int32_t wg_per_cu);
 
-/* Run the scheduler with `policy` over the pending jobs.  With KL_BLOCKING
+/* Run the scheduler with `policy` over the pending jobs (Algorithm 1:
+ * FindCoSchedule picks a pair of pending kernels and their slice ratio,
+ * their slices run side by side while both have workgroups left, then the
+ * next decision; Section 4.2).  With KL_BLOCKING
  * the call returns once every pending job (including dependants released
  * meanwhile) has been launched; otherwise a scheduler thread keeps serving
  * submissions until kernelet_shutdown.  Launches are asynchronous: use
  * kernelet_wait for completion.  The model's policies (MARKOV, SURROGATE,
- * OPT, RANDOM) need a profile for every pending job's kernel (profiles are
- * measured offline, Section 4.4, and given at registration or by
- * kernelet_set_profile; nothing is profiled on submission); FIFO, FIXED and
- * CONCURRENT need none.  KL_ESTATE: a pending kernel without a profile
- * under a model policy, SURROGATE without kernelet_set_surrogate, OPT
+ * OPT, RANDOM) need a profile for every pending job's kernel: given at
+ * registration or by kernelet_set_profile, or, with cfg.auto_profile, measured
+ * from the first job's own pre-executed workgroups before its kernel is
+ * first scheduled (Section 4.4, the model's inputs from a few pre-executed
+ * thread blocks); FIFO, FIXED and CONCURRENT need none.  KL_ESTATE: a pending
+ * kernel without a profile under a model policy when auto_profile is off,
+ * SURROGATE without kernelet_set_surrogate, OPT
  * without kernelet_set_pair_measures, or a scheduler already running;
  * KL_EINVAL: an unknown policy. */
 kl_status kernelet_schedule(kl_runtime* rt, kl_policy policy, uint32_t flags);
 
 /* Block until job j has finished on the GPU, or `timeout_ns` (< 0:
- * forever) elapses.  KL_OK, KL_ETIMEOUT, KL_EHIP (device error),
+ * forever) elapses (Section 2.2: kernels arrive in an order not known
+ * beforehand and are throughput oriented, so a caller learns of each one's
+ * completion separately).  After KL_OK the memory its argument block points
+ * to may be reused.  KL_OK, KL_ETIMEOUT, KL_EHIP (device error),
  * KL_ECANCELED, KL_ENOTFOUND. */
 kl_status kernelet_wait(kl_runtime* rt, kl_job j, int64_t timeout_ns);
 

@@ -34,6 +34,9 @@ def main():
     ap.add_argument("--instances", type=int, default=8, help="instances per kernel type")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mc-seed", type=int, default=1)
+    ap.add_argument("--shared-inputs", action="store_true",
+                    help="all instances of a kernel read one set of inputs (default: each "
+                         "instance its own seeded inputs, as in the bench)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
 
@@ -47,7 +50,7 @@ def main():
 
     dev = torch.device("cuda:0")
     hosts, params = W.full_hosts(a.seed)
-    insts = W.mix(hosts, params, a.instances, a.seed, dev)
+    insts = W.mix(hosts, params, a.instances, a.seed, dev, distinct=not a.shared_inputs)
     prof = profiles.load()
     with open(S.CORUNS) as f:
         table = json.load(f)
@@ -110,7 +113,8 @@ def main():
     mc = np.array(mc)
     kern, opt, fifo = (res[p]["kernels_per_s"] for p in ("markov", "opt", "fifo"))
     out = {
-        "workload": "eight-kernel mix, %d instances per type, seed %d" % (a.instances, a.seed),
+        "workload": "eight-kernel mix, %d instances per type, seed %d, %s inputs" % (
+            a.instances, a.seed, "shared" if a.shared_inputs else "per-instance"),
         "co_run_table": table["source"], "co_run_rows": len(table["rows"]),
         "fifo": res["fifo"], "kernelet": res["markov"], "opt": res["opt"],
         "gain_vs_fifo": {"kernelet": kern / fifo, "opt": opt / fifo,

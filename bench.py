@@ -84,6 +84,8 @@ def parse():
                     help="skip the blocked-order FIFO and main-policy runs")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inflight", type=int, default=None, help="slices queued per lane")
+    ap.add_argument("--lane-streams", type=int, default=None,
+                    help="HIP streams per lane (1 or 2: a job's slices alternate between two)")
     ap.add_argument("--lds-reserve", type=int, default=None)
     ap.add_argument("--cp-min", type=float, default=None)
     ap.add_argument("--ratio-mode", default=None, choices=["balanced", "cp", "literal"],
@@ -383,6 +385,8 @@ def main():
     over = {}
     if args.inflight is not None:
         over["inflight"] = args.inflight
+    if args.lane_streams is not None:
+        over["lane_streams"] = args.lane_streams
     if args.lds_reserve is not None:
         over["lds_reserve"] = args.lds_reserve
     if args.cp_min is not None:
@@ -529,7 +533,8 @@ def main():
            "parallelism": "single GPU, 2 co-execution lanes",
            "leg_order": "seeded permutation of the legs every step",
            "inflight": rt.cfg.inflight, "lds_reserve": rt.cfg.lds_reserve,
-           "cp_min": rt.cfg.cp_min, "solo_overlap": rt.cfg.solo_overlap,
+           "cp_min": round(rt.cfg.cp_min, 4), "solo_overlap": rt.cfg.solo_overlap,
+           "lane_streams": rt.cfg.lane_streams,
            "beta": rt.cfg.beta, "beta_lds": rt.cfg.beta_lds,
            "min_pair_slots": rt.cfg.min_pair_slots,
            "profiles": "estimates" if args.estimates else "measured"}

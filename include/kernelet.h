@@ -221,7 +221,18 @@ typedef struct {
                               deriving the model inputs from the timings
                               and the code object's resources; 0: such a
                               schedule call fails with KL_ESTATE (1)     */
-    int32_t reserved[1];
+    int32_t lane_streams;  /* HIP streams per lane, 1 or 2.  With 2, the
+                              model and FIXED policies alternate a job's
+                              consecutive slices between the lane's two
+                              streams, so that a slice's tail overlaps the
+                              next slice's head (slices of one job are
+                              independent, Section 2.2); LDS reservation
+                              still caps the kernel per CU, a job's
+                              completion is that of all its slices, and
+                              each stream keeps the lane's in-flight window.
+                              FIFO and CONCURRENT use one stream per lane.
+                              On the MI355X mixes measured, 2 lowered the
+                              gain over FIFO (1)                          */
     double beta_lds;       /* latency added per wave stalled on LDS, slots
                               (0: LDS stalls have fixed latencies)         */
     double min_pair_slots; /* a job predicted to finish alone within this

@@ -24,8 +24,12 @@ takes the pair of largest predicted profit whatever its sign (its candidate
 space holds pairs only); the earliest pending kernel runs alone at its own
 full occupancy (a co-schedule of one slice, which the problem definition
 allows) only with a single pending kernel type, when no pair fits on a CU,
-or when the best profit is not above `cp_min` (default -1: a pair predicted
-to halve the two kernels' throughput).
+or when no pair's profit is above `cp_min` (default -1: a pair predicted to
+halve the two kernels' throughput).  A pair of two instances of one kernel,
+whose profit the model puts at zero (identical kernels lump), is held only
+to min(cp_min, -1): a positive cp_min, which asks pairs of different kernels
+for a predicted profit beyond the model's error, leaves it the last resort
+that keeps both lanes busy.
 
 Co-schedules of three kernels (group_max 3) are an extension the paper
 leaves out (it schedules pairs, Section 4.2; its model covers more kernels,
@@ -186,9 +190,12 @@ def find_coschedule(pending, model: Model) -> Decision:
         b1, b2, val, c1, c2 = r
         if sw:
             b1, b2, c1, c2 = b2, b1, c2, c1
+        floor = cfg.cp_min if a.type != b.type else min(cfg.cp_min, -1.0)
+        if not val > floor:
+            continue
         if best is None or val > best.value:
             best = Decision(a.id, b.id, b1, b2, val, c1, c2)
-    if best is None or best.value <= cfg.cp_min:
+    if best is None:
         return solo
     return extend(best, order, model)
 

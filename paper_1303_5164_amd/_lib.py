@@ -64,7 +64,7 @@ class Config(C.Structure):
                 ("random_seed", C.c_uint32), ("solo_overlap", C.c_int32),
                 ("pair_same_type", C.c_int32), ("group_max", C.c_int32),
                 ("inflight_us", C.c_int32), ("auto_profile", C.c_int32),
-                ("reserved", C.c_int32 * 1),
+                ("lane_streams", C.c_int32),
                 ("beta_lds", C.c_double),
                 ("min_pair_slots", C.c_double)]
 

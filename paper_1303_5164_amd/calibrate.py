@@ -738,6 +738,14 @@ def corun_errors(prof, rows, cfgd):
     return np.array(out)
 
 
+def pairing_margin(mape_held_out: float) -> float:
+    """The CP a pair must be predicted to exceed before it is co-scheduled:
+    Eq. (1) at a weighted speedup of 1 + e, where e is the model's mean
+    relative error on co-runs it was not fitted to.  A pair predicted to
+    gain less than the model's own error is as likely to lose as to gain."""
+    return 1.0 - 1.0 / (1.0 + float(mape_held_out))
+
+
 def fit_joint(table_path, occupancy_path, corun_path, out_path, folds=4, lam=1.0,
               slopes=((2.0, 4.0), (4.0, 4.0), (4.0, 16.0), (8.0, 16.0), (2.0, 16.0))):
     """Refit a profile table (from fit_pools) jointly on its solo occupancy
@@ -793,6 +801,7 @@ def fit_joint(table_path, occupancy_path, corun_path, out_path, folds=4, lam=1.0
         v["model_solo_ipc"] = K.predict(full[k], None, full[k]["max_wg_per_cu"], 0, cfg)[0]
     meta = dict(t["meta"])
     meta["model"] = dict(meta.get("model", {}), beta=bh, beta_lds=bl,
+                         cp_min=pairing_margin(held),
                          joint_fit={"corun": os.path.basename(corun_path),
                                     "points": len(rows), "lambda": lam, "folds": folds,
                                     "mape_fitted": fit_mape, "mape_held_out": held,

@@ -732,7 +732,9 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
                 // the surrogate decides: its best pair at its best ratio
                 const int i = idx[0];
                 const double S = sc[i];
-                if (rat[i].first < 1 || !(S > 0) || 1.0 - 1.0 / S <= cfg_.cp_min) return solo_d;
+                const bool same = order[pairs[i].first].type == order[pairs[i].second].type;
+                const double floor = same ? std::min(cfg_.cp_min, -1.0) : cfg_.cp_min;
+                if (rat[i].first < 1 || !(S > 0) || 1.0 - 1.0 / S <= floor) return solo_d;
                 Decision d;
                 d.j1 = order[pairs[i].first].id;
                 d.j2 = order[pairs[i].second].id;
@@ -767,6 +769,11 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
             std::swap(r.b1, r.b2);
             std::swap(r.cipc1, r.cipc2);
         }
+        // a pair of two instances of one kernel (predicted profit zero:
+        // identical kernels lump) is held only to min(cp_min, -1), so that a
+        // positive cp_min leaves it the last resort
+        const double floor = a.type != b.type ? cfg_.cp_min : std::min(cfg_.cp_min, -1.0);
+        if (!(r.value > floor)) continue;
         if (!have || r.value > best.value) {
             have = true;
             best.j1 = a.id;
@@ -778,7 +785,7 @@ Decision Planner::search(const std::vector<PendingJob>& pending,
             best.cipc2 = r.cipc2;
         }
     }
-    if (!have || best.value <= cfg_.cp_min) return solo_d;
+    if (!have) return solo_d;
     // the surrogate's policy ranks pairs only
     return score ? best : extend(best, order);
 }

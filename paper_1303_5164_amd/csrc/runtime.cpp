@@ -141,7 +141,11 @@ struct Inflight {
     int type;
     uint32_t wgs;
     double pred_us;  // predicted duration (0: unknown)
+    int si;          // stream index: lane * 2 + the lane's stream
 };
+
+// Streams a job's slices may use: two per lane, at most four lanes.
+constexpr int kMaxStreams = 8;
 
 enum JobState { J_WAIT_DEP = 0, J_PENDING, J_LAUNCHED, J_DONE, J_CANCELED };
 
@@ -158,22 +162,30 @@ struct Job {
     int64_t carry = 0;  // footprint of finished predecessors released with this job
     JobState st = J_PENDING;
     bool admitted = false;
-    int last_lane = -1;
-    int last_ev = -1;  // event pool index (ref held)
+    // slices launched and not yet retired; per stream, the event of the
+    // job's latest slice on it (pool index, ref held): the slices on one
+    // stream finish in order, so these events finishing means all have
+    int outstanding = 0;
+    int tail[kMaxStreams] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    uint32_t waited = 0;  // streams already ordered after the predecessor's slices
     std::vector<kl_job> dependents;
     int64_t t_submit = 0, t_start = 0, t_done = 0;
     bool error = false;
 };
 
 struct Lane {
-    hipStream_t s = nullptr;
+    // one or two streams (cfg.lane_streams); a co-schedule alternates a
+    // job's slices between them
+    hipStream_t s[2] = {nullptr, nullptr};
+    int nsub = 1;
+    int next_sub = 0;
     std::deque<Inflight> inflight;
     double queued_us = 0;  // predicted work of the slices in flight
     int unpredicted = 0;   // slices in flight without a prediction
     kl_job job = KL_NO_JOB;
     uint32_t slice = 0;
     uint32_t dyn_lds = 0;
-    int barrier_ev = -1;  // wait on this before the next launch (solo runs)
+    std::vector<int> barrier;  // wait on these before the next launch (solo runs)
 };
 
 }  // namespace kl
@@ -247,6 +259,7 @@ static kl_config defaults() {
     c.inflight = 2;
     c.inflight_us = 50;
     c.auto_profile = 1;
+    c.lane_streams = 1;
     c.lds_reserve = 2;
     c.max_slices = 0;
     c.hbm_budget = 0;
@@ -260,6 +273,7 @@ static kl_status check_cfg(const kl_config& c) {
         c.beta < 0 || !(c.beta_lds >= 0) || !(c.min_pair_slots >= 0) || c.alpha_p < 0 || c.alpha_m < 0 || c.ratio_mode < 0 || c.ratio_mode > 2 ||
         c.lds_reserve < 0 || c.lds_reserve > 2 || c.inflight_us < 0 ||
         c.inflight_us > 100000 || c.auto_profile < 0 || c.auto_profile > 1 ||
+        c.lane_streams < 1 || c.lane_streams > 2 ||
  c.surrogate_topk < 0 || c.max_slices < 0 ||
         c.solo_overlap < 0 || c.solo_overlap > 1 || c.pair_same_type < 0 ||
         c.pair_same_type > 1 || c.group_max < 2 || c.group_max > 3 ||
@@ -341,18 +355,49 @@ static hipEvent_t timing_event(kl_runtime* rt) {
     return e;
 }
 
-// Retire finished slices on every lane and finished jobs; a timed slice
+// Drop the job's references to its latest slice events.
+static void release_tails(kl_runtime* rt, Job& j) {
+    for (int& e : j.tail) {
+        if (e >= 0) rt->pool.unref(e);
+        e = -1;
+    }
+}
+
+// Whether every slice of a fully launched job has finished (its latest
+// slice on each stream has); *failed: one of them failed.
+static bool tails_done(kl_runtime* rt, const Job& j, bool* failed) {
+    *failed = false;
+    for (int e : j.tail) {
+        if (e < 0) continue;
+        const hipError_t q = hipEventQuery(rt->pool.ev[e]);
+        if (q == hipErrorNotReady) return false;
+        if (q != hipSuccess) *failed = true;
+    }
+    return true;
+}
+
+// The job's events other lanes must wait on to start after all of it.
+static void tails_of(const Job& j, std::vector<int>* out) {
+    for (int e : j.tail)
+        if (e >= 0) out->push_back(e);
+}
+
+// Retire finished slices on every lane (in any order: a lane's two streams
+// run side by side) and the jobs whose last slice they were; a timed slice
 // adds its dispatch's duration (start event to completion event) to its
 // kernel's counters.
 static void poll_lanes(kl_runtime* rt) {
     for (auto& ln : rt->lanes) {
-        while (!ln.inflight.empty()) {
-            const Inflight f = ln.inflight.front();
+        for (size_t i = 0; i < ln.inflight.size();) {
+            const Inflight f = ln.inflight[i];
             const int e = f.ev;
             hipError_t q = hipEventQuery(rt->pool.ev[e]);
-            if (q == hipErrorNotReady) break;
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
             const kl_job jid = f.job;
-            ln.inflight.pop_front();
+            ln.inflight.erase(ln.inflight.begin() + (std::ptrdiff_t)i);
             ln.queued_us = ln.inflight.empty() ? 0.0 : std::max(0.0, ln.queued_us - f.pred_us);
             if (f.pred_us <= 0) --ln.unpredicted;
             if (f.start) {
@@ -370,17 +415,25 @@ static void poll_lanes(kl_runtime* rt) {
             if (it != rt->jobs.end()) {
                 Job& j = it->second;
                 if (q != hipSuccess) j.error = true;
-                if (j.st == J_LAUNCHED && j.last_ev == e) {
-                    mark_done(rt, j, q != hipSuccess);
-                    rt->pool.unref(j.last_ev);
-                    j.last_ev = -1;
+                if (j.outstanding > 0) --j.outstanding;
+                if (j.tail[f.si] == e) {
+                    rt->pool.unref(e);
+                    j.tail[f.si] = -1;
+                }
+                if (j.st == J_LAUNCHED && j.outstanding == 0) {
+                    mark_done(rt, j, j.error);
+                    release_tails(rt, j);
                 }
             }
             rt->pool.unref(e);
         }
-        if (ln.barrier_ev >= 0 && hipEventQuery(rt->pool.ev[ln.barrier_ev]) == hipSuccess) {
-            rt->pool.unref(ln.barrier_ev);
-            ln.barrier_ev = -1;
+        for (size_t i = 0; i < ln.barrier.size();) {
+            if (hipEventQuery(rt->pool.ev[ln.barrier[i]]) == hipSuccess) {
+                rt->pool.unref(ln.barrier[i]);
+                ln.barrier.erase(ln.barrier.begin() + (std::ptrdiff_t)i);
+            } else {
+                ++i;
+            }
         }
     }
 }
@@ -428,33 +481,47 @@ static double predict_us(kl_runtime* rt, const KernelType& kt, int type, uint32_
 // `inflight` slices, or less than `inflight_us` of predicted work when every
 // slice in flight has a prediction (at most 64 slices).
 static bool lane_has_room(kl_runtime* rt, const Lane& ln) {
+    // the window is per stream: a lane with two streams queues twice as much
     const size_t n = ln.inflight.size();
-    if ((int)n < rt->cfg.inflight) return true;
+    if ((int)n < rt->cfg.inflight * ln.nsub) return true;
     if (rt->cfg.inflight_us <= 0 || n >= 64 || ln.unpredicted > 0) return false;
-    return ln.queued_us < (double)rt->cfg.inflight_us;
+    return ln.queued_us < (double)rt->cfg.inflight_us * ln.nsub;
 }
 
-// Launch the next slice of job `jid` on lane `li`, `count` workgroups.
-static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count) {
+// Launch the next slice of job `jid` on lane `li`, `count` workgroups: on
+// the lane's first stream, or with `alternate` on its two streams in turn.
+// Slices of one job need no order among themselves (their workgroups are
+// independent); a job starts after its predecessor's every slice, and after
+// the lane's barrier.
+static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count,
+                              bool alternate) {
     Lane& ln = rt->lanes[li];
     Job& j = rt->jobs.at(jid);
     const KernelType& kt = rt->kernels[j.type];
     if (count > j.total - j.next) count = j.total - j.next;
     if (count == 0) return KL_OK;
-    // ordering against work on other lanes
-    if (ln.barrier_ev >= 0) {
-        KL_HIP(hipStreamWaitEvent(ln.s, rt->pool.ev[ln.barrier_ev], 0));
-        rt->pool.unref(ln.barrier_ev);
-        ln.barrier_ev = -1;
+    int sub = 0;
+    if (alternate && ln.nsub > 1) {
+        sub = ln.next_sub;
+        ln.next_sub = (ln.next_sub + 1) % ln.nsub;
     }
-    if (j.next == 0 && j.after != KL_NO_JOB) {
+    hipStream_t st = ln.s[sub];
+    const int si = li * 2 + sub;
+    // ordering against work on other lanes: every stream of the lane waits
+    if (!ln.barrier.empty()) {
+        for (int b = 0; b < ln.nsub; ++b)
+            for (int e : ln.barrier) KL_HIP(hipStreamWaitEvent(ln.s[b], rt->pool.ev[e], 0));
+        for (int e : ln.barrier) rt->pool.unref(e);
+        ln.barrier.clear();
+    }
+    if (j.after != KL_NO_JOB && !(j.waited & (1u << si))) {
         auto it = rt->jobs.find(j.after);
-        if (it != rt->jobs.end() && it->second.st != J_DONE && it->second.last_ev >= 0 &&
-            it->second.last_lane != li)
-            KL_HIP(hipStreamWaitEvent(ln.s, rt->pool.ev[it->second.last_ev], 0));
+        if (it != rt->jobs.end() && it->second.st != J_DONE)
+            for (int y = 0; y < kMaxStreams; ++y)
+                if (y != si && it->second.tail[y] >= 0)  // same stream: in order already
+                    KL_HIP(hipStreamWaitEvent(st, rt->pool.ev[it->second.tail[y]], 0));
+        j.waited |= 1u << si;
     }
-    if (j.last_ev >= 0 && j.last_lane != li)
-        KL_HIP(hipStreamWaitEvent(ln.s, rt->pool.ev[j.last_ev], 0));
     kl_slice s;
     s.offset = j.next;
     s.count = count;
@@ -485,10 +552,10 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
     // the completion event (and the start event of a timed kernel) travel
     // with the dispatch itself
     hipError_t e = kt.mfn ? hipExtModuleLaunchKernel(kt.mfn, count * kt.block, 1, 1, kt.block,
-                                                     1, 1, ln.dyn_lds, ln.s, params, nullptr,
+                                                     1, 1, ln.dyn_lds, st, params, nullptr,
                                                      ta, rt->pool.ev[ev], 0)
                           : hipExtLaunchKernel(kt.fn, dim3(count), dim3(kt.block), params,
-                                               ln.dyn_lds, ln.s, ta, rt->pool.ev[ev], 0);
+                                               ln.dyn_lds, st, ta, rt->pool.ev[ev], 0);
     if (e != hipSuccess) {
         rt->pool.unref(ev);
         if (ta) rt->tev_free.push_back(ta);
@@ -500,13 +567,13 @@ static kl_status launch_slice(kl_runtime* rt, int li, kl_job jid, uint32_t count
     j.next += count;
     rt->stats.slices_launched++;
     const double pred = predict_us(rt, kt, j.type, count);
-    ln.inflight.push_back(Inflight{ev, jid, ta, j.type, count, pred});
+    ln.inflight.push_back(Inflight{ev, jid, ta, j.type, count, pred, si});
     ln.queued_us += pred;
     if (pred <= 0) ++ln.unpredicted;
+    ++j.outstanding;
     rt->pool.ref(ev);  // the job's reference
-    rt->pool.unref(j.last_ev);
-    j.last_ev = ev;
-    j.last_lane = li;
+    if (j.tail[si] >= 0) rt->pool.unref(j.tail[si]);
+    j.tail[si] = ev;
     if (j.next >= j.total) {
         j.st = J_LAUNCHED;
         leave_unlaunched(rt, j);
@@ -578,7 +645,7 @@ static kl_status fifo_step(kl_runtime* rt, bool* progressed) {
         Job& j = rt->jobs.at(*it);
         ++it;  // launching the job takes it out of the set
         if (!runnable(j)) break;
-        kl_status s = launch_slice(rt, 0, j.id, j.total - j.next);
+        kl_status s = launch_slice(rt, 0, j.id, j.total - j.next, false);
         if (s) return s;
         *progressed = true;
     }
@@ -604,7 +671,7 @@ static kl_status concurrent_step(kl_runtime* rt, bool* progressed) {
                 }
             }
             if (!next) break;
-            kl_status s = launch_slice(rt, li, next->id, next->total);
+            kl_status s = launch_slice(rt, li, next->id, next->total, false);
             if (s) return s;
             *progressed = true;
         }
@@ -728,8 +795,8 @@ static kl_status timed_solo_slice(kl_runtime* rt, kl_job jid, uint32_t count, ui
     const int64_t n0 = kt.time_launches, w0 = kt.time_wgs;
     kt.timed = true;
     ln.dyn_lds = dyn;
-    kl_status s = launch_slice(rt, 0, jid, count);
-    if (s == KL_OK && hipStreamSynchronize(ln.s) != hipSuccess) {
+    kl_status s = launch_slice(rt, 0, jid, count, false);
+    if (s == KL_OK && hipStreamSynchronize(ln.s[0]) != hipSuccess) {
         set_error("kernelet: a profiling slice failed on the device");
         s = KL_EHIP;
     }
@@ -765,7 +832,8 @@ static kl_status profile_by_preexecution(kl_runtime* rt, kl_job jid) {
     const int wps = std::max(1, (int)kt.block / 256);  // waves per SIMD per workgroup
     const int bmax = std::max(1, std::min(nb, rt->cfg.wmax / wps));
     // alone: wait for every lane to drain first
-    for (auto& ln : rt->lanes) KL_HIP(hipStreamSynchronize(ln.s));
+    for (auto& ln : rt->lanes)
+        for (int b = 0; b < ln.nsub; ++b) KL_HIP(hipStreamSynchronize(ln.s[b]));
     poll_lanes(rt);
     const uint64_t rounds = 4;
     uint32_t sa = (uint32_t)std::min<uint64_t>(j.total - j.next, rounds * n_cu * bmax);
@@ -1010,16 +1078,19 @@ static kl_status markov_step(kl_runtime* rt, kl_policy policy, bool* progressed)
         const bool hold_others = solo && !rt->cfg.solo_overlap &&
                                  !(j.next == 0 && too_short_to_pair(rt, j));
         while (lane_has_room(rt, ln) && j.next < j.total) {
-            kl_status s = launch_slice(rt, li, j.id, ln.slice);
+            kl_status s = launch_slice(rt, li, j.id, ln.slice, true);
             if (s) return s;
             *progressed = true;
             if (hold_others && j.next >= j.total) {
                 // later launches on the other lanes start after this run
+                std::vector<int> tails;
+                tails_of(j, &tails);
                 for (int o = 0; o < (int)rt->lanes.size(); ++o) {
                     if (o == li) continue;
-                    rt->pool.unref(rt->lanes[o].barrier_ev);
-                    rt->lanes[o].barrier_ev = j.last_ev;
-                    rt->pool.ref(j.last_ev);
+                    for (int e : tails) {
+                        rt->lanes[o].barrier.push_back(e);
+                        rt->pool.ref(e);
+                    }
                 }
             }
         }
@@ -1223,7 +1294,11 @@ kl_status kernelet_init(kl_runtime** out, int hip_device, const kl_config* cfg) 
     rt->cfg = c;
     rt->planner = std::make_unique<Planner>(c);
     rt->lanes.resize(c.lanes);
-    for (auto& ln : rt->lanes) KL_HIP(hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking));
+    for (auto& ln : rt->lanes) {
+        ln.nsub = rt->cfg.lane_streams;
+        for (int b = 0; b < ln.nsub; ++b)
+            KL_HIP(hipStreamCreateWithFlags(&ln.s[b], hipStreamNonBlocking));
+    }
     *out = rt.release();
     return KL_OK;
 }
@@ -1248,10 +1323,12 @@ kl_status kernelet_shutdown(kl_runtime* rt) {
     if (rt->worker.joinable()) rt->worker.join();
     (void)hipSetDevice(rt->device);
     for (auto& ln : rt->lanes) {
-        if (ln.s) (void)hipStreamSynchronize(ln.s);
+        for (hipStream_t x : ln.s)
+            if (x) (void)hipStreamSynchronize(x);
     }
     for (auto& ln : rt->lanes)
-        if (ln.s) (void)hipStreamDestroy(ln.s);
+        for (hipStream_t x : ln.s)
+            if (x) (void)hipStreamDestroy(x);
     for (auto& ln : rt->lanes)
         for (auto& f : ln.inflight)
             if (f.start) (void)hipEventDestroy(f.start);
@@ -1616,14 +1693,11 @@ kl_status kernelet_wait(kl_runtime* rt, kl_job jid, int64_t timeout_ns) {
             }
             return KL_OK;
         }
-        if (j.st == J_LAUNCHED && j.last_ev >= 0) {
-            hipError_t q = hipEventQuery(rt->pool.ev[j.last_ev]);
-            if (q != hipErrorNotReady) {
-                mark_done(rt, j, q != hipSuccess);
-                rt->pool.unref(j.last_ev);
-                j.last_ev = -1;
-                continue;
-            }
+        bool failed = false;
+        if (j.st == J_LAUNCHED && tails_done(rt, j, &failed)) {
+            mark_done(rt, j, failed || j.error);
+            release_tails(rt, j);
+            continue;
         }
         if (now_ns() >= deadline) {
             set_error("kernelet_wait: timed out");
@@ -1639,16 +1713,16 @@ kl_status kernelet_synchronize(kl_runtime* rt) {
         return KL_EINVAL;
     }
     KL_HIP(hipSetDevice(rt->device));
-    for (auto& ln : rt->lanes) KL_HIP(hipStreamSynchronize(ln.s));
+    for (auto& ln : rt->lanes)
+        for (int b = 0; b < ln.nsub; ++b) KL_HIP(hipStreamSynchronize(ln.s[b]));
     std::lock_guard<std::mutex> g(rt->mu);
     poll_lanes(rt);
     const std::vector<kl_job> ids(rt->live.begin(), rt->live.end());
     for (kl_job id : ids) {
         Job& j = rt->jobs.at(id);
         if (j.st == J_LAUNCHED) {
-            mark_done(rt, j, false);
-            rt->pool.unref(j.last_ev);
-            j.last_ev = -1;
+            mark_done(rt, j, j.error);
+            release_tails(rt, j);
         }
     }
     return KL_OK;
@@ -1669,7 +1743,8 @@ kl_status kernelet_stream_barrier(kl_runtime* rt, void* stream) {
     // each wait takes the event as recorded now; the pool may reuse it later
     hipError_t r = hipEventRecord(rt->pool.ev[e], (hipStream_t)stream);
     for (size_t i = 0; r == hipSuccess && i < rt->lanes.size(); ++i)
-        r = hipStreamWaitEvent(rt->lanes[i].s, rt->pool.ev[e], 0);
+        for (int b = 0; r == hipSuccess && b < rt->lanes[i].nsub; ++b)
+            r = hipStreamWaitEvent(rt->lanes[i].s[b], rt->pool.ev[e], 0);
     rt->pool.unref(e);
     if (r != hipSuccess) {
         set_error(std::string("kernelet_stream_barrier: ") + hipGetErrorString(r));
@@ -1746,7 +1821,7 @@ kl_status kernelet_reap(kl_runtime* rt) {
     for (auto it = rt->jobs.begin(); it != rt->jobs.end();) {
         Job& j = it->second;
         if (j.st == J_DONE || j.st == J_CANCELED) {
-            rt->pool.unref(j.last_ev);
+            release_tails(rt, j);
             it = rt->jobs.erase(it);
         } else {
             ++it;

@@ -59,11 +59,12 @@ def load(prefer_measured: bool = True) -> dict:
 
 def model_config(prefer_measured: bool = True) -> dict:
     """Runtime configuration fields the measured table was fitted with
-    (contention slopes, pairing threshold, pruning thresholds); empty for
-    the estimates."""
+    (contention slopes, pairing threshold, pruning thresholds, the CP a pair
+    must be predicted to exceed); empty for the estimates."""
     if prefer_measured and os.path.exists(MEASURED):
         with open(MEASURED) as f:
             m = json.load(f).get("meta", {}).get("model", {})
-        return {k: float(m[k]) for k in ("beta", "beta_lds", "min_pair_slots", "alpha_p", "alpha_m")
+        return {k: float(m[k]) for k in ("beta", "beta_lds", "min_pair_slots", "alpha_p", "alpha_m",
+                                           "cp_min")
                 if k in m}
     return {}

@@ -134,21 +134,26 @@ def _types_and_jobs(seed, n_types=5, n_jobs=30, arrivals=True):
     return profs, jp, jw, ja
 
 
-@pytest.mark.parametrize("seed,prune,betas,short", [(1, True, (0.0, 0.0), 0.0),
-                                                    (2, False, (0.0, 0.0), 0.0),
-                                                    (3, True, (0.0, 0.0), 0.0),
-                                                    (4, True, (1.0, 8.0), 0.0),
-                                                    (5, False, (0.0, 0.0), 3000.0)])
-def test_simulate_matches_oracle(seed, prune, betas, short):
+@pytest.mark.parametrize("seed,prune,betas,short,cp_min", [(1, True, (0.0, 0.0), 0.0, -1.0),
+                                                           (2, False, (0.0, 0.0), 0.0, -1.0),
+                                                           (3, True, (0.0, 0.0), 0.0, -1.0),
+                                                           (4, True, (1.0, 8.0), 0.0, -1.0),
+                                                           (5, False, (0.0, 0.0), 3000.0, -1.0),
+                                                           (6, True, (2.0, 4.0), 0.0, 0.14),
+                                                           (7, False, (0.0, 0.0), 0.0, 0.3)])
+def test_simulate_matches_oracle(seed, prune, betas, short, cp_min):
     profs, jp, jw, ja = _types_and_jobs(seed)
     cfg = K.default_config(use_prune=int(prune), n_cu=256, beta=betas[0], beta_lds=betas[1],
-                           min_pair_slots=short)
+                           min_pair_slots=short, cp_min=cp_min)
     decs, span, done = K.simulate(profs, jp, jw, ja, "markov", cfg)
     types = {i: S.TypeInfo(oracle_kprof(p), p["pur"], p["mur"]) for i, p in enumerate(profs)}
     ocfg = S.Config(use_prune=prune, mode="cp", n_cu=256, beta=betas[0], beta_lds=betas[1],
-                    min_pair_slots=short)
+                    min_pair_slots=short, cp_min=cp_min)
     jobs = [S.Job(i, jp[i], jw[i], ja[i]) for i in range(len(jp))]
     log, ospan, odone = S.simulate_kernelet(jobs, types, ocfg)
+    if cp_min > 0:
+        # the margin refuses some pairs of different kernels
+        assert any(o.j2 < 0 for o in log)
     assert len(decs) == len(log)
     for d, o in zip(decs, log):
         assert (d["j1"], d["j2"], d["b1"], d["b2"]) == (o.j1, o.j2, o.b1, o.b2)

@@ -153,6 +153,28 @@ def test_two_instances_of_one_kernel_pair_at_a_balanced_split():
         assert 1.0 - s / c <= d.value + 1e-12
 
 
+def test_positive_cp_min_refuses_mixed_pairs_but_keeps_same_kernel_pairs():
+    """cp_min asks a pair of different kernels for a predicted profit above
+    it; a pair of two instances of one kernel is held only to
+    min(cp_min, -1), so it is taken when the mixed pairs are refused."""
+    types = _types()
+    pend = [sched.Job(0, 0, 10), sched.Job(1, 1, 10), sched.Job(2, 1, 10)]
+    loose = sched.find_coschedule(pend, sched.Model(types, sched.Config(use_prune=False)))
+    assert loose.j2 >= 0
+    strict = sched.find_coschedule(pend, sched.Model(types, sched.Config(use_prune=False,
+                                                                         cp_min=0.99)))
+    # every pair of different kernels is refused at 0.99; the two instances
+    # of kernel 1 remain
+    assert (strict.j1, strict.j2) == (1, 2)
+    # with pruning, the same-kernel pair (equal PUR and MUR) survives only
+    # when it is all that is left: then the margin does not refuse it
+    pruned = sched.find_coschedule(pend[1:], sched.Model(types, sched.Config(cp_min=0.99)))
+    assert (pruned.j1, pruned.j2) == (1, 2)
+    only_mixed = [sched.Job(0, 0, 10), sched.Job(1, 1, 10)]
+    d = sched.find_coschedule(only_mixed, sched.Model(types, sched.Config(cp_min=0.99)))
+    assert d.j2 == -1 and d.j1 == 0
+
+
 def test_simulation_executes_every_workgroup_once_and_beats_fifo():
     types = _types()
     cfg = sched.Config()

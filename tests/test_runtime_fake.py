@@ -119,9 +119,10 @@ def test_fifo_then_fixed_slices_with_wait_done(L):
     h.close()
 
 
+@pytest.mark.parametrize("streams", [1, 2])
 @pytest.mark.parametrize("policy", ["fifo", "fixed", "markov"])
-def test_every_workgroup_once_and_chains_in_order(L, policy):
-    h = Harness(L)
+def test_every_workgroup_once_and_chains_in_order(L, policy, streams):
+    h = Harness(L, lane_streams=streams)
     jobs = []
     for i in range(6):
         jobs.append(h.job(37 + 11 * i, 10 + i, kind=i % 2, us=20))
@@ -142,6 +143,31 @@ def test_every_workgroup_once_and_chains_in_order(L, policy):
     assert start(c2) >= end(c1) and start(c3) >= end(c2)
     if policy == "markov":
         assert any(d["j2"] >= 0 for d in h.rt.decisions())
+    h.close()
+
+
+@pytest.mark.parametrize("streams", [1, 2])
+def test_slices_of_one_job_overlap_only_on_two_streams(L, streams):
+    """With two streams per lane a job's consecutive slices alternate
+    between them and run side by side; with one they run one after the
+    other.  Either way every workgroup runs once and wait returns only
+    after the last slice has ended."""
+    h = Harness(L, lane_streams=streams)
+    j, visits, log, ln = h.job(64, 1, kind=0, us=300)
+    h.rt.slice(j, 8)
+    _run_with_deadline(lambda: h.rt.schedule("fixed", blocking=True))
+    h.rt.wait(j, 5_000_000_000)
+    assert np.all(visits == 1)
+    e = log[: ln[0]]
+    e = e[np.argsort(e[:, 1])]          # by slice offset
+    assert len(e) == 8
+    overlaps = sum(e[i + 1, 3] < e[i, 4] for i in range(len(e) - 1))
+    if streams == 1:
+        assert overlaps == 0
+    else:
+        assert overlaps >= 3
+    st = h.rt.stats()
+    assert st["jobs_done"] >= 1 and st["slices_launched"] == 8
     h.close()
 
 

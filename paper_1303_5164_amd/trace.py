@@ -5,7 +5,11 @@ csv` writes and prints a markdown table of calls, average / min / max and
 total duration per kernel, and for one kernel the same broken down by grid
 size (sliced launches have smaller grids than whole ones).
 
-Usage: python -m paper_1303_5164_amd.trace TRACE.csv [--kernel kl_lookup]
+With --last N, also the average duration and grid of the kernel's last N
+dispatches (the bench's profiling steps come last, so this is the figure
+its roofline object times with events).
+
+Usage: python -m paper_1303_5164_amd.trace TRACE.csv [--kernel kl_lookup] [--last 20]
 """
 from __future__ import annotations
 
@@ -27,13 +31,25 @@ def _grid(row):
 
 
 def load(path):
-    """[(kernel, grid threads, duration ms)] of every dispatch."""
+    """[(kernel, grid threads, duration ms)] of every dispatch, in order of
+    start time."""
     out = []
     with open(path) as f:
         for row in csv.DictReader(f):
-            t = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e6
-            out.append((_name(row), _grid(row), t))
-    return out
+            t0 = int(row["Start_Timestamp"])
+            t = (int(row["End_Timestamp"]) - t0) / 1e6
+            out.append((t0, _name(row), _grid(row), t))
+    out.sort(key=lambda r: r[0])
+    return [r[1:] for r in out]
+
+
+def last(rows, kernel, n):
+    """Average duration (ms) and workgroups of the kernel's last n dispatches."""
+    sel = [(g, t) for k, g, t in rows if k == kernel][-n:]
+    if not sel:
+        return None
+    return (sum(t for _, t in sel) / len(sel), sum(g for g, _ in sel) / len(sel) / 256,
+            len(sel))
 
 
 def table(rows):
@@ -67,12 +83,19 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("trace")
     ap.add_argument("--kernel", default=None)
+    ap.add_argument("--last", type=int, default=0)
     a = ap.parse_args()
     rows = load(a.trace)
     print(table(rows))
     if a.kernel:
         print()
         print(by_grid(rows, a.kernel))
+        if a.last:
+            r = last(rows, a.kernel, a.last)
+            if r:
+                print()
+                print(f"Last {r[2]} dispatches of {a.kernel}: average {r[0]:.4f} ms, "
+                      f"{r[1]:.0f} workgroups on average")
 
 
 if __name__ == "__main__":

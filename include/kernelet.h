@@ -63,7 +63,7 @@ typedef struct {
 } kl_slice;
 
 /* Per-kernel inputs of the performance model and of pruning (Section 4.4,
- * "getting the input for the model"; PUR and MUR of Section 4.3).  The
+ * its paragraph on obtaining the model's inputs; PUR and MUR of Section 4.3).  The
  * Markov model runs on a virtual SIMD (the paper's virtual single-scheduler
  * SM, one of the 4 SIMDs of a CU); its time unit is one issue slot. */
 typedef struct {

@@ -9,7 +9,7 @@ alone, in the order the paper obtains them:
   reads plus writes over what the memory could have served in that time);
   pur() and mur() of prune.py state both.
 
-  Section 4.4 ("getting the input for the model") profiles the kernel for
+  Section 4.4 (its paragraph on the model's inputs) profiles the kernel for
   the probability that an issued instruction is a memory instruction (R_m,
   the ratio of memory instructions to all instructions) and for the
   instructions each warp executes (I_K).

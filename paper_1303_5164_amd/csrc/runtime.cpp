@@ -812,7 +812,7 @@ static kl_status timed_solo_slice(kl_runtime* rt, kl_job jid, uint32_t count, ui
 }
 
 // Profile a kernel type from its job jid (Section 4.4 takes the model's
-// inputs from profiling a few pre-executed thread blocks).  The job's first
+// inputs from a few thread blocks run ahead of the rest).  The job's first
 // workgroups run alone on lane 0, timed by the events their dispatch
 // carries: four rounds at the kernel's full occupancy, then, if it can be
 // held there by LDS reservation, four rounds at two workgroups per CU; they

@@ -290,7 +290,7 @@ def main():
     ap.add_argument("--measured", default=None,
                     help="balanced co-run sweep JSON of the built-in kernels: its measured "
                          "speedups join the training set")
-    ap.add_argument("--measured-weight", type=int, default=40,
+    ap.add_argument("--measured-weight", type=int, default=100,
                     help="times each measured sample is repeated in the training set")
     a = ap.parse_args()
 

@@ -232,14 +232,16 @@ def _traffic(kernel):
 
 def _ceiling(bound):
     """The chip's measured ceiling for a roofline bound, in the roofline's
-    unit (a 1 GiB device copy in GB/s; the FP32 FMA or matrix loop in
-    TFLOP/s; mean of the runs under profiles/), or None."""
+    unit (a 1 GiB device copy in GB/s, or its read stream for "hbm_read";
+    the FP32 FMA or matrix loop in TFLOP/s; mean of the runs under
+    profiles/), or None."""
     path = os.path.join(ROOT, "profiles", "ceilings_mi355x.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         runs = json.load(f).get("runs", [])
-    key = {"hbm": "copy_gbps", "mfma": "mfma_tflops", "alu": "fma_tflops"}[bound]
+    key = {"hbm": "copy_gbps", "hbm_read": "read_gbps", "mfma": "mfma_tflops",
+           "alu": "fma_tflops"}[bound]
     vals = [r[key] for r in runs if key in r]
     return sum(vals) / len(vals) if vals else None
 
@@ -619,6 +621,9 @@ def main():
     if ceil:
         roof["measured_ceiling"] = round(ceil, 2)
         roof["frac_of_measured_ceiling"] = round(roof["achieved"] / ceil, 4)
+    rceil = _ceiling("hbm_read") if roof["bound"] == "hbm" else None
+    if rceil:
+        roof["measured_read_ceiling"] = round(rceil, 2)
     roof["achieved"] = round(roof["achieved"], 3)
     roof["frac"] = round(roof["frac"], 4)
     roof["traffic"] = None

@@ -156,6 +156,20 @@ typedef struct {
     uint32_t iters;
 } kl_ceiling_args;
 
+/* ceil_read (a probe of the chip's HBM read bandwidth, not a workload):
+ * workgroup w reads the 256 * per_thread float4 at src + 4 * (w * 256 *
+ * per_thread), thread t the ones at t, t + 256, t + 512, ... (coalesced
+ * 16-byte loads), and writes the sum of its 4 * per_thread floats to
+ * out[w * 256 + t].  src holds n_wg * 256 * per_thread float4 (16-byte
+ * aligned); out n_wg * 256 floats.  grid = n_wg; per_thread a positive
+ * multiple of 8, at most 2^16. */
+typedef struct {
+    const float* src;
+    float* out;
+    uint32_t n_wg;
+    uint32_t per_thread;
+} kl_read_args;
+
 /* synthk_v<V>_l<L> (synthetic kernels of known character, the training
  * population of the surrogate model): thread t (t < n_threads) runs `iters`
  * iterations of one load of src[addr] followed by a chain of `alu`

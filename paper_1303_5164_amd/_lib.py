@@ -155,7 +155,12 @@ class CeilingArgs(C.Structure):
                 ("iters", C.c_uint32)]
 
 
-ARGS = {"probe": ProbeArgs, "ceil_fma": CeilingArgs, "ceil_mfma": CeilingArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
+class ReadArgs(C.Structure):
+    _fields_ = [("src", P), ("out", P), ("n_wg", C.c_uint32), ("per_thread", C.c_uint32)]
+
+
+ARGS = {"probe": ProbeArgs, "ceil_fma": CeilingArgs, "ceil_mfma": CeilingArgs,
+        "ceil_read": ReadArgs, "poly": PolyArgs, "gather": GatherArgs, "sgemm": SgemmArgs, "spmv": SpmvArgs,
         "stencil": StencilArgs, "bs": BsArgs, "hist": HistArgs, "lookup": LookupArgs,
         "lookup_index": LookupArgs, **{k: SynthkArgs for k in SYNTHK}}
 

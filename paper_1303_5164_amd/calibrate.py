@@ -166,7 +166,8 @@ def ceiling_flops(kind: str, n_wg: int, iters: int) -> float:
 def ceilings(out_path: str, reps: int = 5) -> dict:
     """The chip's measured ceilings beside its published peaks: a 1 GiB
     device copy (read + write bandwidth; far larger than the 256 MB MALL, so
-    every repetition streams from HBM), a loop of unpacked FP32 FMAs and a
+    every repetition streams from HBM), a read stream of the same 1 GiB
+    (ceil_read: read bandwidth), a loop of unpacked FP32 FMAs and a
     loop of FP32 matrix instructions (v_mfma_f32_32x32x2f32), each launched
     whole through the runtime and timed by HIP events on its lane; the GPU
     clocks as reported by amd-smi (or rocm-smi) idle, while the matrix loop
@@ -207,10 +208,36 @@ def ceilings(out_path: str, reps: int = 5) -> dict:
     out["copy"] = {"bytes": copy_bytes, "ms": copy_ms, "gbps": 2 * copy_bytes / copy_ms / 1e6,
                    "frac_of_8TBs": 2 * copy_bytes / copy_ms / 1e9 / 8.0}
     print(f"# copy {out['copy']['gbps']:.0f} GB/s", file=sys.stderr, flush=True)
-    del src, dst
+    del dst
     torch.cuda.empty_cache()
     rt = K.Runtime(0)
     n_cu = rt.cfg.n_cu
+    # the read stream (ceil_read) over the same 1 GiB of ones
+    per = 64
+    n_wg = copy_bytes // (256 * per * 16)
+    k = rt.register_builtin("ceil_read")
+    rbuf = torch.empty(n_wg * 256, dtype=torch.float32, device=dev)
+    rargs = _lib.ReadArgs(src.data_ptr(), rbuf.data_ptr(), n_wg, per)
+    for rep in range(reps + 1):
+        rbuf.fill_(-1.0)
+        torch.cuda.synchronize()
+        if rep == 1:
+            rt.time_kernel(k, True)
+        j = rt.submit(k, (n_wg, 1, 1), rargs)
+        rt.schedule("fifo", blocking=True, wait_done=True)
+        rt.wait(j, 60_000_000_000)
+        rt.synchronize()
+        rt.reap()
+    ms, n, _ = rt.kernel_time(k)
+    ms /= max(n, 1)
+    ok = bool(torch.all(rbuf == 4.0 * per).item())
+    out["read"] = {"bytes": copy_bytes, "n_wg": n_wg, "per_thread": per, "ms": ms,
+                   "gbps": copy_bytes / ms / 1e6, "frac_of_8TBs": copy_bytes / ms / 1e9 / 8.0,
+                   "outputs_exact": ok}
+    print(f"# read {out['read']['gbps']:.0f} GB/s, outputs exact: {ok}", file=sys.stderr,
+          flush=True)
+    del src, rbuf
+    torch.cuda.empty_cache()
     plan = {"ceil_fma": (n_cu * 32, 16384, 78.6e12), "ceil_mfma": (n_cu * 12, 8192, 157.3e12)}
     for kind, (n_wg, iters, peak) in plan.items():
         k = rt.register_builtin(kind)

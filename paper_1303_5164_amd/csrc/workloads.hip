@@ -683,6 +683,28 @@ __global__ __launch_bounds__(KL_WG) void kl_ceil_mfma(kl_ceiling_args a, kl_slic
     a.out[(uint64_t)lin * KL_WG + threadIdx.x] = sum;
 }
 
+// HBM read ceiling: every thread streams per_thread float4, eight loads in
+// flight, into four independent sums.
+__global__ __launch_bounds__(KL_WG) void kl_ceil_read(kl_read_args a, kl_slice s) {
+    const uint32_t lin = kl_wg_linear(s);
+    if (lin >= a.n_wg) return;
+    const float4* p = (const float4*)a.src + (uint64_t)lin * KL_WG * a.per_thread + threadIdx.x;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (uint32_t i = 0; i < a.per_thread; i += 8) {
+        float4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(uint64_t)(i + u) * KL_WG];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+            acc.z += v[u].z;
+            acc.w += v[u].w;
+        }
+    }
+    a.out[(uint64_t)lin * KL_WG + threadIdx.x] = (acc.x + acc.y) + (acc.z + acc.w);
+}
+
 // ===================================================== host-side registry
 namespace {
 
@@ -762,6 +784,13 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         if (!a.out || a.n_wg == 0) return "null out or n_wg == 0";
         if (a.iters > (1u << 20)) return "iters above 2^20";
         g->x = a.n_wg;
+    } else if (n == "ceil_read") {
+        KL_ARGS(kl_read_args);
+        if (!a.src || !a.out || a.n_wg == 0) return "null src or out, or n_wg == 0";
+        if (!aligned16(a.src)) return "src must be 16-byte aligned";
+        if (a.per_thread == 0 || a.per_thread % 8 || a.per_thread > (1u << 16))
+            return "per_thread not a positive multiple of 8 up to 2^16";
+        g->x = a.n_wg;
     } else if (n == "lookup" || n == "lookup_index") {
         KL_ARGS(kl_lookup_args);
         if (!a.keys || !a.index || a.nkeys == 0 || a.nkeys > 0x7fffffffu)
@@ -804,6 +833,7 @@ const BuiltinEntry kBuiltins[] = {
     {"probe", (const void*)kl_probe, sizeof(kl_probe_args), 0u},
     {"ceil_fma", (const void*)kl_ceil_fma, sizeof(kl_ceiling_args), KL_KF_IDEMPOTENT},
     {"ceil_mfma", (const void*)kl_ceil_mfma, sizeof(kl_ceiling_args), KL_KF_IDEMPOTENT},
+    {"ceil_read", (const void*)kl_ceil_read, sizeof(kl_read_args), KL_KF_IDEMPOTENT},
 #define KL_SYNTHK_ENTRY(V, L)                                                 \
     {"synthk_v" #V "_l" #L, (const void*)kl_synthk_v##V##_l##L, sizeof(kl_synthk_args), \
      KL_KF_IDEMPOTENT},

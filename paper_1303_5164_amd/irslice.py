@@ -316,24 +316,28 @@ def bench(n: int = 8192, reps: int = 5, inflight: int = 2) -> dict:
         k = rt.register_image("plain_matadd", image, "kl_plain_matadd", C.sizeof(Args))
         n_cu = rt.cfg.n_cu
 
-        def run(slice_wgs):
-            ts = []
-            rt.time_kernel(k, True)
-            for r in range(reps + 1):
-                c.zero_()
-                torch.cuda.synchronize()
-                j = rt.submit(k, (nb, nb, 1), args)
-                if slice_wgs:
-                    rt.slice(j, slice_wgs)
-                t0 = time.perf_counter()
-                rt.schedule("fixed" if slice_wgs else "fifo", blocking=True, wait_done=True)
-                ts.append(time.perf_counter() - t0)
-                rt.reap()
+        def once(slice_wgs):
+            c.zero_()
+            torch.cuda.synchronize()
+            j = rt.submit(k, (nb, nb, 1), args)
+            if slice_wgs:
+                rt.slice(j, slice_wgs)
+            t0 = time.perf_counter()
+            rt.schedule("fixed" if slice_wgs else "fifo", blocking=True, wait_done=True)
+            t = time.perf_counter() - t0
+            rt.reap()
             assert torch.equal(c, ref)
+            return t
+
+        def run(slice_wgs):
+            # wall time of a schedule call with no timing events, then one
+            # more run whose launches carry events: the GPU time of its slices
+            ts = [once(slice_wgs) for _ in range(reps + 1)]
+            rt.time_kernel(k, True)
+            once(slice_wgs)
             ms, nl, _ = rt.kernel_time(k)
             rt.time_kernel(k, False)
-            # wall time of a schedule call, and the GPU time of its launches
-            return statistics.median(ts[1:]), ms / (reps + 1), nl // (reps + 1)
+            return statistics.median(ts[1:]), ms, nl
 
         t_whole, g_whole, _ = run(0)
         out["runs"].append({"slice_wgs": 0, "ms": t_whole * 1e3, "gpu_ms": g_whole})

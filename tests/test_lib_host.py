@@ -307,3 +307,15 @@ def test_ceiling_probe_grids_and_refusals():
                     _lib.CeilingArgs(0, 1.0, 1.0, 37, 10), _lib.CeilingArgs(out, 1.0, 1.0, 0, 10)):
             with pytest.raises(K.KerneletError):
                 K.builtin_grid(name, bad)
+
+
+def test_read_probe_grid_and_refusals():
+    p = 256
+    d = K.builtin_desc("ceil_read")
+    assert d.args_bytes == ctypes.sizeof(_lib.ReadArgs) == 24
+    assert K.builtin_grid("ceil_read", _lib.ReadArgs(p, p, 4096, 64)) == (4096, 1, 1)
+    for bad in (_lib.ReadArgs(p, p, 4096, 12), _lib.ReadArgs(p, p, 4096, 0),
+                _lib.ReadArgs(p, p, 4096, (1 << 16) + 8), _lib.ReadArgs(p + 4, p, 1, 8),
+                _lib.ReadArgs(0, p, 1, 8), _lib.ReadArgs(p, 0, 1, 8), _lib.ReadArgs(p, p, 0, 8)):
+        with pytest.raises(K.KerneletError):
+            K.builtin_grid("ceil_read", bad)

@@ -4,8 +4,9 @@ together and co-scheduled by the Markov policy with the measured profiles
 (contention slopes, pairing threshold, LDS-capped slices), then by the
 surrogate policy, OPT on the measured co-run table, a Monte Carlo sample,
 the Markov policy with co-schedules of up to three kernels on three streams,
-and plain concurrent execution of whole launches over two and three
-streams.  Outputs are checked
+the Markov policy with two streams per lane (a job's slices alternating
+between them), and plain concurrent execution of whole launches over two
+and three streams.  Outputs are checked
 against the oracle in full where that is cheap (polynomial, gather, SpMV,
 histogram) and on seeded samples the oracle computes point by point
 elsewhere (SGEMM entries, stencil points after 10 sweeps, Black-Scholes
@@ -59,9 +60,11 @@ def _run(insts, policy):
     prof = profiles.load()
     lanes = 3 if policy in ("concurrent3", "markov3") else 2
     group_max = 3 if policy == "markov3" else 2
-    policy = {"concurrent3": "concurrent", "markov3": "markov"}.get(policy, policy)
+    lane_streams = 2 if policy == "markov_2streams" else 1
+    policy = {"concurrent3": "concurrent", "markov3": "markov",
+              "markov_2streams": "markov"}.get(policy, policy)
     with K.Runtime(0, surrogate_topk=0, random_seed=11, lanes=lanes, group_max=group_max,
-                   **profiles.model_config()) as rt:
+                   lane_streams=lane_streams, **profiles.model_config()) as rt:
         kids = {k: rt.register_builtin(k, prof[k]) for k in W.KERNELS}
         if policy == "surrogate":
             rt.set_surrogate(np.load(S.WEIGHTS_MEASURED))
@@ -85,7 +88,7 @@ def _out(inst, name=None):
 
 
 @pytest.mark.parametrize("policy", ["markov", "surrogate", "opt", "random", "fixed",
-                                    "markov3", "concurrent", "concurrent3"])
+                                    "markov3", "concurrent", "concurrent3", "markov_2streams"])
 def test_full_mix_matches_oracle(mix, policy):
     hosts, insts = mix
     dec = _run(insts, policy)

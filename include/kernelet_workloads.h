@@ -104,7 +104,8 @@ typedef struct {
  * keys 64 j .. 64 j + 63 as 16-bit distances below its largest key
  * keys[min(64 j + 63, n - 1)], two per uint32 word (slot 2w in the low
  * half), 32 words per leaf, slots past the last key 0; a leaf whose keys
- * span more than 65534 has 0xffff in slot 0 and is searched in `keys`.
+ * span more than 65534 has 0xffff in the first slot of each of its eight
+ * 16-byte pieces (slots 0, 8, ..., 56) and is searched in `keys`.
  * Level 1 entry j is leaf j's largest key, level k + 1 entry i is level k
  * entry min(32 i + 31, m_k - 1); sizes m_1 = ceil(n / 64), m_{k+1} =
  * ceil(m_k / 32), stopping at the first level with at most 1024 entries
@@ -114,7 +115,7 @@ typedef struct {
  * "lookup_index" kernel writes it (one thread per four words, grid =
  * ceil(words / 1024)) and the "lookup" kernel reads it (four queries per
  * thread, eight threads searching each query together, grid =
- * ceil(nq / 1024)).  nq a multiple of 4, nkeys >= 1; keys, q, out, index
+ * ceil(nq / 1024)).  nq a multiple of 4, 1 <= nkeys <= 2^31 - 64; keys, q, out, index
  * 16-byte aligned. */
 typedef struct {
     const uint32_t* keys;

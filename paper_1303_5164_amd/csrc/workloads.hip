@@ -276,7 +276,8 @@ __global__ __launch_bounds__(KL_WG) void kl_hist(kl_hist_args a, kl_slice s) {
 // per leaf, so the searched structure takes 2 bytes per key: for 2^26 keys
 // 128 MiB of leaves and a 4 MiB level 1, which the 256 MiB last-level cache
 // can hold while the 256 MiB key array is not read.  A leaf whose keys span
-// more than 65534 is flagged (its first distance is 0xffff) and searched in
+// more than 65534 is flagged (the first distance of each 16-byte piece is
+// 0xffff, so every lane reading a piece sees the flag) and searched in
 // the key array instead.  Level 1 holds the largest key of every leaf, level
 // k + 1 the largest entry of every 32-entry node of level k, up to a top
 // level of at most 1024 entries that each workgroup keeps in LDS.  Levels
@@ -346,8 +347,9 @@ __global__ __launch_bounds__(KL_WG) void kl_lookup_index(kl_lookup_args a, kl_sl
         const uint64_t last = j * kLkLeaf + kLkLeaf - 1 < n ? j * kLkLeaf + kLkLeaf - 1 : n - 1;
         const uint32_t mx = a.keys[last];
         if (mx - a.keys[j * kLkLeaf] > kLkEscape - 1) {
-            // searched in the keys: the flag in slot 0, nothing else
-            v = make_uint4(w % kLkLeafWords == 0 ? kLkEscape : 0u, 0u, 0u, 0u);
+            // searched in the keys: the flag in the first slot of every
+            // 16-byte piece, so each lane of a group sees it in its own piece
+            v = make_uint4(kLkEscape, 0u, 0u, 0u);
         } else {
             uint32_t d[8];
             if (k0 + 8 <= n) {
@@ -439,6 +441,34 @@ __device__ __forceinline__ uint32_t lk_above2(uint32_t w, kl_u16x2 tc) {
     return (uint32_t)(gt.x & 1) + (uint32_t)(gt.y & 1);
 }
 
+// Reads of the index by raw buffer loads with 32-bit byte offsets (fewer
+// address instructions than 64-bit flat addresses): one buffer resource for
+// the levels and one for the leaves, each under 4 GiB (nkeys <= 2^31 - 64:
+// fewer than 2^25 leaves of 128 bytes).
+struct LkIndex {
+    __amdgpu_buffer_rsrc_t lv, lf;
+    __device__ LkIndex(const uint32_t* idx, const LkLevels& L) {
+        // word 3 of a raw buffer resource on gfx9 (32-bit data format)
+        lv = __builtin_amdgcn_make_buffer_rsrc((void*)idx, 0, (int)(L.leaf_off * 4), 0x00020000);
+        const uint64_t lb = L.nleaf * kLkLeafWords * 4;
+        lf = __builtin_amdgcn_make_buffer_rsrc((void*)(idx + L.leaf_off), 0,
+                                               (int)(uint32_t)(lb < 0xffffffffull ? lb : 0xffffffffull),
+                                               0x00020000);
+    }
+    // 16 bytes at word w of the levels, or of the leaves
+    __device__ __forceinline__ uint4 level4(uint32_t w) const {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(lv, (int)(4u * w), 0, 0);
+        return make_uint4(t[0], t[1], t[2], t[3]);
+    }
+    __device__ __forceinline__ uint32_t level1(uint32_t w) const {
+        return __builtin_amdgcn_raw_buffer_load_b32(lv, (int)(4u * w), 0, 0);
+    }
+    __device__ __forceinline__ uint4 leaf4(uint32_t w) const {
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(lf, (int)(4u * w), 0, 0);
+        return make_uint4(t[0], t[1], t[2], t[3]);
+    }
+};
+
 template <int G>
 __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_slice& s) {
     constexpr int W4 = 8 / G;  // 16-byte pieces of a 128-byte line per lane
@@ -466,7 +496,7 @@ __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_sl
     const uint32_t g0 = lane & ~(uint32_t)(G - 1);  // first lane of this lane's group
     const uint32_t r = lane & (uint32_t)(G - 1);    // this lane's part of a line
     const uint32_t n = a.nkeys;
-    const uint32_t* __restrict__ idx = a.index;
+    const LkIndex idx(a.index, L);
     kl_u32x4 o = {n, n, n, n};
     // the group searches the four queries of each of its lanes in turn
     for (uint32_t b = 0; b < (uint32_t)G; ++b) {
@@ -492,8 +522,7 @@ __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_sl
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int v = 0; v < W4; ++v)
-                    x[i][v] = *(const uint4*)(idx + L.off[k] + kLkFan * (uint64_t)c[i] +
-                                              4 * (W4 * r + v));
+                    x[i][v] = idx.level4((uint32_t)L.off[k] + kLkFan * c[i] + 4 * (W4 * r + v));
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 uint32_t cnt = 0;
@@ -512,14 +541,13 @@ __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_sl
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int v = 0; v < W4; ++v)
-                w[i][v] = *(const uint4*)(idx + L.leaf_off + kLkLeafWords * (uint64_t)c[i] +
-                                          4 * (W4 * r + v));
-            mx[i] = idx[L.off[0] + c[i]];
+                w[i][v] = idx.leaf4(kLkLeafWords * c[i] + 4 * (W4 * r + v));
+            mx[i] = idx.level1((uint32_t)L.off[0] + c[i]);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            // slot 0 (the group's first lane) flags a leaf searched in the keys
-            const bool esc = lk_sum<G>(r == 0 && (w[i][0].x & 0xffffu) == kLkEscape) != 0;
+            // a leaf searched in the keys is flagged in every lane's piece
+            const bool esc = (w[i][0].x & 0xffffu) == kLkEscape;
             uint32_t cnt = 0;
             if (!esc) {
                 // key < q exactly when its distance below the leaf's largest
@@ -793,8 +821,8 @@ std::string grid_of(const char* name, const void* args, uint32_t bytes, kl_dim3*
         g->x = a.n_wg;
     } else if (n == "lookup" || n == "lookup_index") {
         KL_ARGS(kl_lookup_args);
-        if (!a.keys || !a.index || a.nkeys == 0 || a.nkeys > 0x7fffffffu)
-            return "null keys or index, or nkeys outside [1, 2^31 - 1]";
+        if (!a.keys || !a.index || a.nkeys == 0 || a.nkeys > 0x7fffffc0u)
+            return "null keys or index, or nkeys outside [1, 2^31 - 64]";
         if (!aligned16(a.keys) || !aligned16(a.index)) return "keys, index must be 16-byte aligned";
         if (n == "lookup_index") {
             LkLevels L;

@@ -319,3 +319,12 @@ def test_read_probe_grid_and_refusals():
                 _lib.ReadArgs(0, p, 1, 8), _lib.ReadArgs(p, 0, 1, 8), _lib.ReadArgs(p, p, 0, 8)):
         with pytest.raises(K.KerneletError):
             K.builtin_grid("ceil_read", bad)
+
+
+def test_lookup_key_count_bound():
+    """The index's leaves are read through one buffer resource below 4 GiB:
+    at most 2^31 - 64 keys."""
+    p = 256
+    assert K.builtin_grid("lookup", _lib.LookupArgs(p, p, p, p, 0x7fffffc0, 4)) == (1, 1, 1)
+    with pytest.raises(K.KerneletError):
+        K.builtin_grid("lookup", _lib.LookupArgs(p, p, p, p, 0x7fffffc1, 4))

@@ -140,7 +140,9 @@ class Budget:
     """Bytes of device memory held by admitted requests.  `acquire` blocks
     until every earlier ticket has been admitted and the budget has room,
     so requests are admitted in arrival order and a request larger than the
-    whole budget is refused rather than waited for."""
+    whole budget is refused rather than waited for.  Each waiting client has
+    an event of its own, set when its ticket is admitted, so an admission or
+    a release wakes only the client it lets in."""
 
     def __init__(self, limit):
         self.limit = int(limit)
@@ -148,30 +150,43 @@ class Budget:
         self.peak = 0
         self.next_ticket = 0
         self.aborted = False
-        self.cv = threading.Condition()
+        self.waiting = {}  # ticket -> (bytes, event)
+        self.lock = threading.Lock()
+
+    def _admit(self):
+        while self.next_ticket in self.waiting:
+            nbytes, ev = self.waiting[self.next_ticket]
+            if self.held + nbytes > self.limit:
+                return
+            del self.waiting[self.next_ticket]
+            self.held += nbytes
+            self.peak = max(self.peak, self.held)
+            self.next_ticket += 1
+            ev.set()
 
     def acquire(self, ticket, nbytes):
         if nbytes > self.limit:
             raise ValueError(f"request of {nbytes} bytes exceeds the budget of {self.limit}")
-        with self.cv:
-            self.cv.wait_for(lambda: self.aborted or (ticket == self.next_ticket and
-                                                      self.held + nbytes <= self.limit))
+        ev = threading.Event()
+        with self.lock:
             if self.aborted:
                 raise RuntimeError("serving aborted")
-            self.held += nbytes
-            self.peak = max(self.peak, self.held)
-            self.next_ticket += 1
-            self.cv.notify_all()
+            self.waiting[ticket] = (nbytes, ev)
+            self._admit()
+        ev.wait()
+        if self.aborted and ticket in self.waiting:
+            raise RuntimeError("serving aborted")
 
     def release(self, nbytes):
-        with self.cv:
+        with self.lock:
             self.held -= nbytes
-            self.cv.notify_all()
+            self._admit()
 
     def abort(self):
-        with self.cv:
+        with self.lock:
             self.aborted = True
-            self.cv.notify_all()
+            for _, ev in self.waiting.values():
+                ev.set()
 
 
 class Server:

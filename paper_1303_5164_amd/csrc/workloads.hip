@@ -408,26 +408,27 @@ __device__ __forceinline__ uint32_t lk_sum(uint32_t v) {
     return (uint32_t)x;
 }
 
-// Entries of the LDS top level (mt <= 1024 of them, sorted) that are < q,
-// found by the G lanes of a group together: while the range left is longer
-// than 16 entries it is cut into G blocks and lane r tests the last entry
-// of block r; then each lane tests 16 / G entries of the last 16.
+// The LDS copy of the top level: its entries (at most 1024, sorted), then
+// all-ones up to kLkTopPad, which no query is above.  A search that finds
+// all 1024 entries below q goes on reading past them, at most 16 entries.
+constexpr uint32_t kLkTopPad = 1024 + 16;
+
+// Entries of the LDS top level that are < q, found by the G lanes of a
+// group together: while the range left is longer than 16 entries it is cut
+// into G blocks and lane r tests the last entry of block r; then each lane
+// tests 16 / G entries of the last 16.  The padding makes every read valid,
+// so the rounds need no bounds tests (and no branches).
 template <int G>
-__device__ __forceinline__ uint32_t lk_top_count(const uint32_t* top, uint32_t mt, uint32_t q,
-                                                 uint32_t r) {
+__device__ __forceinline__ uint32_t lk_top_count(const uint32_t* top, uint32_t q, uint32_t r) {
     uint32_t base = 0;
 #pragma unroll
     for (uint32_t R = 1024; R > 16; R /= G) {
         const uint32_t B = R / G;
-        const uint32_t p = base + B * r + B - 1;
-        base += B * lk_sum<G>(p < mt && top[p] < q);
+        base += B * lk_sum<G>(top[base + B * r + B - 1] < q);
     }
     uint32_t c = 0;
 #pragma unroll
-    for (uint32_t u = 0; u < 16 / G; ++u) {
-        const uint32_t p = base + (16 / G) * r + u;
-        c += p < mt && top[p] < q;
-    }
+    for (uint32_t u = 0; u < 16 / G; ++u) c += top[base + (16 / G) * r + u] < q;
     return base + lk_sum<G>(c);
 }
 
@@ -460,9 +461,6 @@ struct LkIndex {
         const auto t = __builtin_amdgcn_raw_buffer_load_b128(lv, (int)(4u * w), 0, 0);
         return make_uint4(t[0], t[1], t[2], t[3]);
     }
-    __device__ __forceinline__ uint32_t level1(uint32_t w) const {
-        return __builtin_amdgcn_raw_buffer_load_b32(lv, (int)(4u * w), 0, 0);
-    }
     __device__ __forceinline__ uint4 leaf4(uint32_t w) const {
         const auto t = __builtin_amdgcn_raw_buffer_load_b128(lf, (int)(4u * w), 0, 0);
         return make_uint4(t[0], t[1], t[2], t[3]);
@@ -472,7 +470,7 @@ struct LkIndex {
 template <int G>
 __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_slice& s) {
     constexpr int W4 = 8 / G;  // 16-byte pieces of a 128-byte line per lane
-    __shared__ uint32_t top[1024];
+    __shared__ uint32_t top[kLkTopPad];
     LkLevels L;
     lk_levels(a.nkeys, &L);
     const uint32_t T = L.nlev - 1;
@@ -484,7 +482,8 @@ __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_sl
             mt = (uint32_t)L.m[j];
             top_off = L.off[j];
         }
-    for (uint32_t i = threadIdx.x; i < mt; i += KL_WG) top[i] = a.index[top_off + i];
+    for (uint32_t i = threadIdx.x; i < kLkTopPad; i += KL_WG)
+        top[i] = i < mt ? a.index[top_off + i] : 0xffffffffu;
     __syncthreads();
     // every lane loads its own four queries; lanes past the end search dummy
     // queries (the lanes of a group work together) and store nothing
@@ -503,12 +502,13 @@ __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_sl
         const int src = (int)(g0 + b);
         uint32_t q[4], c[4];
         bool past[4];
+        uint32_t mx[4];  // the largest key of each query's leaf
         q[0] = (uint32_t)__shfl((int)qv.x, src);
         q[1] = (uint32_t)__shfl((int)qv.y, src);
         q[2] = (uint32_t)__shfl((int)qv.z, src);
         q[3] = (uint32_t)__shfl((int)qv.w, src);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) c[i] = lk_top_count<G>(top, mt, q[i], r);
+        for (int i = 0; i < 4; ++i) c[i] = lk_top_count<G>(top, q[i], r);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             past[i] = c[i] >= mt;  // above every key
@@ -530,19 +530,34 @@ __device__ __forceinline__ void lookup_body(const kl_lookup_args& a, const kl_sl
                 for (int v = 0; v < W4; ++v)
                     cnt += (x[i][v].x < q[i]) + (x[i][v].y < q[i]) + (x[i][v].z < q[i]) +
                            (x[i][v].w < q[i]);
-                c[i] = kLkFan * c[i] + lk_sum<G>(cnt);
+                const uint32_t e = lk_sum<G>(cnt);
+                c[i] = kLkFan * c[i] + e;
+                if (k == 0) {
+                    // level 1: entry e of the node just read is the leaf's
+                    // largest key (e < 32 unless past[i]), held in piece
+                    // e / 4 of the line: lane e / (4 W4) of the group
+                    const uint32_t j = e & (4 * W4 - 1);
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int u = 0; u < W4; ++u) {
+                        v = j == 4u * u ? x[i][u].x : v;
+                        v = j == 4u * u + 1 ? x[i][u].y : v;
+                        v = j == 4u * u + 2 ? x[i][u].z : v;
+                        v = j == 4u * u + 3 ? x[i][u].w : v;
+                    }
+                    mx[i] = (uint32_t)__shfl((int)v, (int)(g0 + e / (4 * W4)));
+                }
             }
         }
         // c[i]: the leaf holding the answer, the first whose largest key
         // is >= q[i]
         uint4 w[4][W4];
-        uint32_t mx[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int v = 0; v < W4; ++v)
                 w[i][v] = idx.leaf4(kLkLeafWords * c[i] + 4 * (W4 * r + v));
-            mx[i] = idx.level1((uint32_t)L.off[0] + c[i]);
+            if (T == 0) mx[i] = top[c[i]];  // level 1 is the top (c[i] < mt)
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {

@@ -1717,11 +1717,14 @@ kl_status kernelet_synchronize(kl_runtime* rt) {
         for (int b = 0; b < ln.nsub; ++b) KL_HIP(hipStreamSynchronize(ln.s[b]));
     std::lock_guard<std::mutex> g(rt->mu);
     poll_lanes(rt);
+    // a scheduler thread may have launched more slices since the streams
+    // drained: a job is done only when its own latest slices are
     const std::vector<kl_job> ids(rt->live.begin(), rt->live.end());
     for (kl_job id : ids) {
         Job& j = rt->jobs.at(id);
-        if (j.st == J_LAUNCHED) {
-            mark_done(rt, j, j.error);
+        bool failed = false;
+        if (j.st == J_LAUNCHED && tails_done(rt, j, &failed)) {
+            mark_done(rt, j, failed || j.error);
             release_tails(rt, j);
         }
     }

@@ -620,3 +620,24 @@ def test_model_policies_profile_a_kernel_without_profile(L, pol):
     assert h.rt.stats()["kernels_profiled"] == 1
     h.close()
 
+
+
+def test_synchronize_beside_a_running_scheduler_finishes_only_finished_jobs(L):
+    """kernelet_synchronize drains the lanes while the background scheduler
+    keeps launching slices: a job it leaves done has run every workgroup,
+    and the jobs launched meanwhile still finish later."""
+    h = Harness(L)
+    h.rt.schedule("markov", blocking=False)
+    got = [h.job(24, i, kind=i % 2, us=100) for i in range(60)]
+    fn = h.lib.kernelet_wait
+    for _ in range(300):
+        h.rt.synchronize()
+        for j, visits, _, _ in got:
+            if fn(h.rt.h, j, 0) == 0:  # done, by synchronize or by its slices
+                assert np.all(visits == 1)
+        if all(fn(h.rt.h, j, 0) == 0 for j, _, _, _ in got):
+            break
+    for j, visits, _, _ in got:
+        h.rt.wait(j, 20_000_000_000)
+        assert np.all(visits == 1)
+    h.close()

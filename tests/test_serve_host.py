@@ -85,7 +85,8 @@ def test_budget_admits_in_arrival_order_within_the_limit():
     b.release(60)
     t1.join(5)
     t2.join(5)
-    assert order == [1, 2] and b.held == 60 and b.peak == 60
+    # both admitted by the one release (the threads may report in either order)
+    assert sorted(order) == [1, 2] and b.held == 60 and b.peak == 60 and b.next_ticket == 3
     with pytest.raises(ValueError):
         b.acquire(3, 101)
     # an aborted budget wakes a waiting client with an error

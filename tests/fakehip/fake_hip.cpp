@@ -3,6 +3,7 @@
 #include "hip/hip_ext.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdlib>
@@ -137,10 +138,21 @@ hipError_t hipStreamDestroy(hipStream_t s) {
     delete s;
     return hipSuccess;
 }
+// Test knob: microseconds a stream synchronisation lingers after the stream
+// drained, widening the window in which another host thread launches more.
+static std::atomic<int> g_sync_linger_us{0};
+extern "C" void fake_set_sync_linger_us(int us) { g_sync_linger_us = us; }
+
 hipError_t hipStreamSynchronize(hipStream_t s) {
-    std::unique_lock<std::mutex> lk(g_mu);
-    g_cv.wait(lk, [&] { return s->q.empty() && !s->busy; });
-    return s->failed ? hipErrorLaunchFailure : hipSuccess;
+    bool failed;
+    {
+        std::unique_lock<std::mutex> lk(g_mu);
+        g_cv.wait(lk, [&] { return s->q.empty() && !s->busy; });
+        failed = s->failed;
+    }
+    if (const int us = g_sync_linger_us.load())
+        std::this_thread::sleep_for(std::chrono::microseconds(us));
+    return failed ? hipErrorLaunchFailure : hipSuccess;
 }
 hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned) {
     std::lock_guard<std::mutex> g(g_mu);
@@ -356,9 +368,11 @@ extern "C" int fake_visit(const void* a_, const kl_slice* s) {
     FakeVisitArgs a;
     std::memcpy(&a, a_, sizeof(a));
     double t0 = now_ms();
-    for (uint32_t b = 0; b < s->count; ++b) a.visits[s->offset + b]++;
+    // the slice's work takes its time first and its writes land at its end,
+    // as a kernel's results are complete only when it finishes
     if (a.us_per_wg)
         std::this_thread::sleep_for(std::chrono::microseconds((uint64_t)a.us_per_wg * s->count));
+    for (uint32_t b = 0; b < s->count; ++b) a.visits[s->offset + b]++;
     double t1 = now_ms();
     std::lock_guard<std::mutex> g(g_mu);
     if (a.log && *a.log_len < a.log_cap) {

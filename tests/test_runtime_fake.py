@@ -623,21 +623,31 @@ def test_model_policies_profile_a_kernel_without_profile(L, pol):
 
 
 def test_synchronize_beside_a_running_scheduler_finishes_only_finished_jobs(L):
-    """kernelet_synchronize drains the lanes while the background scheduler
-    keeps launching slices: a job it leaves done has run every workgroup,
-    and the jobs launched meanwhile still finish later."""
+    """kernelet_synchronize while the background scheduler launches: jobs
+    submitted after the lanes drained (here while the synchronisation
+    lingers) are launched before synchronize takes the runtime's lock; it
+    must not report them done while their slices still run."""
     h = Harness(L)
-    h.rt.schedule("markov", blocking=False)
-    got = [h.job(24, i, kind=i % 2, us=100) for i in range(60)]
+    L.fake_set_sync_linger_us.argtypes = [C.c_int]
+    L.fake_set_sync_linger_us(5000)
     fn = h.lib.kernelet_wait
-    for _ in range(300):
-        h.rt.synchronize()
-        for j, visits, _, _ in got:
-            if fn(h.rt.h, j, 0) == 0:  # done, by synchronize or by its slices
+    try:
+        h.rt.schedule("markov", blocking=False)
+        for rnd in range(6):
+            t = threading.Thread(target=h.rt.synchronize)
+            t.start()
+            # the lanes are empty; synchronize lingers 5 ms after each of
+            # the two lanes' streams: submit during the second
+            time.sleep(0.0065)
+            batch = [h.job(24, 100 * rnd + i, kind=i % 2, us=400) for i in range(4)]
+            t.join(20)
+            assert not t.is_alive()
+            for j, visits, _, _ in batch:
+                if fn(h.rt.h, j, 0) == 0:
+                    assert np.all(visits == 1), "reported done before its slices ran"
+            for j, visits, _, _ in batch:
+                h.rt.wait(j, 20_000_000_000)
                 assert np.all(visits == 1)
-        if all(fn(h.rt.h, j, 0) == 0 for j, _, _, _ in got):
-            break
-    for j, visits, _, _ in got:
-        h.rt.wait(j, 20_000_000_000)
-        assert np.all(visits == 1)
+    finally:
+        L.fake_set_sync_linger_us(0)
     h.close()

@@ -702,6 +702,19 @@ def fit_pools(times_path: str, counter_paths, occupancy_path: str, out_path: str
 #   + lam * sum over its co-runs of (log S_model - log S)^2 ,
 # its partners' latencies held; a few rounds of this over all kernels.
 # Held-out pairs (folds) are left out of the fit.
+#
+# S is Eq. (1)'s sum of the two kernels' co-run rates over their solo rates,
+# measured per kernel (its solo time for its work over its busy time in the
+# co-run): the quantity the chain predicts.  The sweep's job speedup (both
+# kernels' solo times over the co-run's wall time) also carries the
+# imbalance of fixed amounts held at one ratio after the first kernel ran
+# out, which Algorithm 1 does not do (it decides again); it serves the
+# pruning table, which asks whether co-running the pair's jobs pays.
+
+
+def corun_measure(r) -> float:
+    """Measured weighted speedup of a co-run row: rel_a + rel_b."""
+    return float(r["rel_a"]) + float(r["rel_b"])
 
 def _rel_pred(pa, pb, b1, b2, cfg):
     """Predicted slowdowns (cIPC / solo IPC) of the two kernels of a co-run."""
@@ -726,7 +739,7 @@ def _kernel_objective(args):
             pa = q if r["a"] == name else prof[r["a"]]
             pb = q if r["b"] == name else prof[r["b"]]
             ra, rb = _rel_pred(pa, pb, r["b1"], r["b2"], cfg)
-            e += lam * (math.log(ra + rb) - math.log(r["speedup"])) ** 2
+            e += lam * (math.log(ra + rb) - math.log(corun_measure(r))) ** 2
     except (K.KerneletError, ValueError):
         return float("inf")
     return e
@@ -753,15 +766,16 @@ def joint_refine(prof, curves, rows, cfgd, rounds=2, lam=1.0, pool=None):
 
 
 def corun_errors(prof, rows, cfgd):
-    """Absolute relative error of the predicted speedup S = rel_a + rel_b
-    on each co-run row."""
+    """Absolute relative error of the predicted weighted speedup
+    S = rel_a + rel_b on each co-run row, against the measured one."""
     import numpy as np
     import paper_1303_5164_amd as K
     cfg = K.default_config(**cfgd)
     out = []
     for r in rows:
         ra, rb = _rel_pred(prof[r["a"]], prof[r["b"]], r["b1"], r["b2"], cfg)
-        out.append(abs(ra + rb - r["speedup"]) / r["speedup"])
+        m = corun_measure(r)
+        out.append(abs(ra + rb - m) / m)
     return np.array(out)
 
 

@@ -180,8 +180,10 @@ def dataset(seed: int, n_kernels: int, n_samples: int, lo: int, hi: int, cfg=Non
 def measured_samples(sweep_path: str, prof=None, kinds=None):
     """Samples from a balanced co-run sweep of the built-in kernels: for
     each measured (a at b1, b at b2) the features of both orders, labelled
-    with the measured weighted speedup S; returns X, T and each sample's
-    unordered pair name."""
+    with the measured weighted speedup S = cIPC_a / IPC_a + cIPC_b / IPC_b
+    (each kernel's solo time for its work over its busy time in the co-run;
+    the job speedup where a row has no per-kernel rates); returns X, T and
+    each sample's unordered pair name."""
     from . import profiles
     prof = prof or profiles.load()
     rows = json.load(open(sweep_path))["rows"]
@@ -192,7 +194,8 @@ def measured_samples(sweep_path: str, prof=None, kinds=None):
         pa, pb = prof[r["a"]], prof[r["b"]]
         for (p1, p2, c1, c2) in ((pa, pb, r["b1"], r["b2"]), (pb, pa, r["b2"], r["b1"])):
             X.append(pair_features(p1, p2, c1, c2))
-            T.append(r["speedup"])
+            T.append(r["rel_a"] + r["rel_b"] if r.get("rel_a") and r.get("rel_b")
+                     else r["speedup"])
             G.append("+".join(sorted((r["a"], r["b"]))))
     return np.array(X, np.float32), np.array(T, np.float32), G
 

@@ -129,18 +129,21 @@ def report(sweep_path: str, occupancy_path: str | None = None) -> str:
 
     fr = sorted({r.get("frac") or 0 for r in rows})
     if len(fr) > 1 or fr != [0]:
-        out += ["", "By slice size (fraction of each kernel's grid; all ratios): mean measured "
-                "S, model MAPE, mean co-run IPC of the two kernels (wave-instructions per "
+        out += ["", "By slice size (fraction of each kernel's grid; all ratios): mean job "
+                "speedup (dispatch gaps and tails included), mean measured weighted speedup "
+                "(the kernels' rates while their slices run), the model's MAPE against the "
+                "job speedup, mean co-run IPC of the two kernels (wave-instructions per "
                 "issue slot per SIMD) and mean HBM GB/s (solo counter bytes per launch over "
                 "the co-run time):", "",
-                "| slice | points | mean S | MAPE | IPC a + b | HBM GB/s |",
-                "|---|---:|---:|---:|---:|---:|"]
+                "| slice | points | mean job S | mean weighted S | MAPE (job S) | IPC a + b | "
+                "HBM GB/s |",
+                "|---|---:|---:|---:|---:|---:|---:|"]
         for f in fr:
             sel = [i for i, r in enumerate(rows) if (r.get("frac") or 0) == f]
-            m, p_ = meas[sel], pred[sel]
+            m, w, p_ = job[sel], meas[sel], pred[sel]
             ig = [ipc_gbps(rows[i]) for i in sel]
             out.append(f"| {'1/' + str(f) if f else 'min'} | {len(sel)} | {m.mean():.3f} | "
-                       f"{np.mean(np.abs(p_ - m) / m):.3f} | "
+                       f"{w.mean():.3f} | {np.mean(np.abs(p_ - m) / m):.3f} | "
                        f"{np.mean([x[0][0] + x[0][1] for x in ig]):.3f} | "
                        f"{np.mean([x[1] for x in ig]):.0f} |")
     out += ["", "Per co-run (pair at its measured best ratio and slice): IPC of each kernel "
